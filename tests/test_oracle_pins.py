@@ -1,0 +1,309 @@
+"""Pins the oracle to facts that do not come from the oracle itself: values
+derived by hand, closed forms, exact arithmetic, invariants and library
+routines. CPU only."""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+X0, Y0, D = -2.0, -1.5, 3.0 / 1024.0
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- escape-time
+def test_escape_hand_derived_points():
+    g = _gold("escape_points.json")
+    gr = g["grid"]
+    for mi in (16, 256, 1000):
+        for p in g["points"]:
+            want = mi if p["count"] == "max_iter" else p["count"]
+            got = O.escape_pixel(p["r"], p["c"], gr["x0"], gr["y0"], gr["dx"], gr["dy"], mi)
+            assert got == want, (p, mi)
+
+
+def _exact_count(cr: Fraction, ci: Fraction, max_iter: int):
+    """Escape count in exact rational arithmetic; also the smallest distance
+    of |z_n|^2 to 4 seen, so near-ties can be skipped."""
+    zr = zi = Fraction(0)
+    closest = None
+    n = 0
+    while n < max_iter:
+        m = zr * zr + zi * zi
+        dist = abs(m - 4)
+        closest = dist if closest is None else min(closest, dist)
+        if m > 4:
+            break
+        zr, zi = zr * zr - zi * zi + cr, 2 * zr * zi + ci
+        n += 1
+    return n, closest
+
+
+def test_escape_matches_exact_rational_arithmetic():
+    rng = np.random.default_rng(7)
+    mi = 9
+    checked = 0
+    for _ in range(400):
+        r, c = int(rng.integers(0, 1024)), int(rng.integers(0, 1024))
+        cr = Fraction(-2) + Fraction(c * 3, 1024)
+        ci = Fraction(-3, 2) + Fraction(r * 3, 1024)
+        want, closest = _exact_count(cr, ci, mi)
+        if closest is not None and closest < Fraction(1, 10**3):
+            continue
+        assert O.escape_pixel(r, c, X0, Y0, D, D, mi) == want, (r, c)
+        checked += 1
+    assert checked > 300
+
+
+def test_escape_conjugate_symmetry_bitwise():
+    img = O.escape(1024, 1024, X0, Y0, D, D, 256)
+    # row r has ci = -1.5 + r*3/1024, row 1024 - r has -ci exactly
+    assert np.array_equal(img[1:], img[1:][::-1])
+
+
+def test_escape_max_iter_monotone():
+    a = O.escape(256, 256, X0, Y0, 4 * D, 4 * D, 40)
+    b = O.escape(256, 256, X0, Y0, 4 * D, 4 * D, 300)
+    assert np.array_equal(a, np.minimum(b, 40))
+    assert a.min() >= 1
+
+
+def test_escape_area_estimate():
+    # The Mandelbrot set has area about 1.5066; pixels still bounded after
+    # 256 steps over-cover it slightly.
+    img = O.escape(1024, 1024, X0, Y0, D, D, 256)
+    area = float((img == 256).mean()) * 9.0
+    assert 1.50 < area < 1.58
+
+
+# ------------------------------------------------------------------- blur
+def test_gauss_weights_closed_form():
+    w = O.gauss5_weights(1.0).reshape(5, 5).astype(np.float64)
+    s1 = 1 + 2 * math.exp(-0.5) + 2 * math.exp(-2.0)
+    assert abs(w[2, 2] - 1.0 / (s1 * s1)) <= 2 ** -24 * w[2, 2]
+    assert np.array_equal(w, w.T) and np.array_equal(w, w[::-1]) and np.array_equal(w, w[:, ::-1])
+    assert abs(w[2, 3] / w[2, 2] - math.exp(-0.5)) < 1e-6
+    assert abs(w[0, 0] / w[2, 2] - math.exp(-4.0)) < 1e-6
+    assert abs(w.sum() - 1.0) < 1e-6
+
+
+def test_blur_impulse_gives_mirrored_weights():
+    rng = np.random.default_rng(3)
+    wt = rng.random(25).astype(np.float32)  # asymmetric on purpose
+    img = np.zeros((11, 13), np.float32)
+    img[5, 6] = 1.0
+    out = O.blur5(img, wt)
+    W = wt.reshape(5, 5)
+    for a in range(-2, 3):
+        for b in range(-2, 3):
+            assert out[5 + a, 6 + b] == W[2 - a, 2 - b]
+    mask = np.ones_like(out, bool)
+    mask[3:8, 4:9] = False
+    assert np.all(out[mask] == 0)
+
+
+def test_blur_clamp_corner():
+    wt = O.gauss5_weights(1.0)
+    W = wt.reshape(5, 5)
+    img = np.zeros((7, 9), np.float32)
+    img[0, 0] = 1.0
+    out = O.blur5(img, wt)
+    # fma(w, 1, acc) is a plain FP32 addition; taps with dy, dx in {-2,-1,0}
+    # all clamp onto (0, 0); the others add exact zeros.
+    acc = np.float32(0)
+    for dy in (-2, -1, 0):
+        for dx in (-2, -1, 0):
+            acc = np.float32(acc + W[dy + 2, dx + 2])
+    assert out[0, 0] == acc
+
+
+def test_blur_constant_image():
+    wt = O.gauss5_weights(1.0)
+    img = np.full((9, 10), 0.37, np.float32)
+    out = O.blur5(img, wt)
+    assert np.all(out == out[4, 4])
+    assert abs(float(out[0, 0]) - 0.37) < 1e-6
+
+
+def test_blur_matches_library_correlation():
+    from scipy import ndimage
+    rng = np.random.default_rng(11)
+    img = rng.random((37, 53)).astype(np.float32)
+    wt = O.gauss5_weights(1.0)
+    out = O.blur5(img, wt).astype(np.float64)
+    ref = ndimage.correlate(img.astype(np.float64), wt.reshape(5, 5).astype(np.float64), mode="nearest")
+    bound = 25 * 2 ** -24 * ndimage.correlate(np.abs(img).astype(np.float64),
+                                                np.abs(wt.reshape(5, 5)).astype(np.float64), mode="nearest")
+    assert np.all(np.abs(out - ref) <= bound)
+
+
+def test_blur_power_of_two_scaling_bitwise():
+    rng = np.random.default_rng(5)
+    img = rng.random((20, 21)).astype(np.float32)
+    wt = O.gauss5_weights(1.0)
+    assert np.array_equal(O.blur5(img * np.float32(4), wt), O.blur5(img, wt) * np.float32(4))
+
+
+# ----------------------------------------------------------------- n-body
+def test_rsqrt_lomont_accuracy():
+    xs = np.logspace(-7, 4, 4001)
+    worst = max(abs(float(O.rsqrt_lomont(float(np.float32(x)))) * math.sqrt(float(np.float32(x))) - 1.0)
+                for x in xs)
+    # three Newton steps from Lomont's estimate leave only FP32 rounding
+    assert worst < 4 * 2 ** -24
+
+
+def test_rsqrt_lomont_first_estimate_and_scaling():
+    # 1/sqrt(4x) is exactly half of 1/sqrt(x) through the bit estimate and Newton steps
+    for x in (0.3, 1.7, 123.0, 1e-5):
+        assert O.rsqrt_lomont(4 * x) == np.float32(O.rsqrt_lomont(x) / 2)
+    assert abs(float(O.rsqrt_lomont(1.0)) - 1.0) < 2 ** -23
+
+
+def test_nbody_two_body_closed_form():
+    pos = np.array([[0.1, 0.2, 0.3, 1.25], [0.7, -0.1, 0.5, 0.75]], np.float32)
+    eps2 = 1e-6
+    for strict in (True, False):
+        a = O.nbody_acc(pos, eps2, strict)
+        for i, j in ((0, 1), (1, 0)):
+            d = pos[j, :3].astype(np.float64) - pos[i, :3].astype(np.float64)
+            want = float(pos[j, 3]) * d / (d @ d + eps2) ** 1.5
+            assert np.allclose(a[i, :3], want, rtol=2e-6, atol=0)
+            assert a[i, 3] == 0
+
+
+def test_nbody_scaling_bitwise():
+    from paper_1805_02755_amd.synth import nbody_bodies
+    pos = nbody_bodies(96, seed=9)
+    eps2 = np.float32(1e-6)
+    for strict in (True, False):
+        base = O.nbody_acc(pos, float(eps2), strict)
+        p2 = pos.copy()
+        p2[:, 3] *= 2
+        assert np.array_equal(O.nbody_acc(p2, float(eps2), strict), base * 2)
+        p3 = pos.copy()
+        p3[:, :3] *= 2
+        assert np.array_equal(O.nbody_acc(p3, float(eps2 * 4), strict), base / 4)
+
+
+def test_nbody_tiny_vs_fp64_brute_force():
+    from paper_1805_02755_amd.synth import nbody_bodies
+    pos = nbody_bodies(64, seed=21)
+    eps2 = 1e-3
+    ref = O.nbody_acc_f64(pos, eps2)
+    # independent brute force in the test, FP64
+    p = pos.astype(np.float64)
+    d = p[None, :, :3] - p[:, None, :3]
+    r2 = (d ** 2).sum(-1) + eps2
+    terms = p[None, :, 3, None] * d / r2[..., None] ** 1.5
+    bf = terms.sum(1)
+    assert np.allclose(ref, bf, rtol=1e-12, atol=1e-12)
+    scale = np.linalg.norm(terms, axis=-1).sum(1)
+    for strict in (True, False):
+        a = O.nbody_acc(pos, eps2, strict)[:, :3].astype(np.float64)
+        err = np.linalg.norm(a - bf, axis=-1)
+        assert np.all(err <= 1e-5 * scale)
+
+
+def test_nbody_momentum_conservation():
+    from paper_1805_02755_amd.synth import nbody_bodies
+    pos = nbody_bodies(256, seed=4)
+    a = O.nbody_acc(pos, 1e-6, True)[:, :3].astype(np.float64)
+    m = pos[:, 3].astype(np.float64)
+    tot = (m[:, None] * a).sum(0)
+    mag = (m[:, None] * np.abs(a)).sum(0)
+    assert np.all(np.abs(tot) <= 1e-5 * mag)
+
+
+def test_nbody_self_term_is_zero():
+    pos = np.array([[0.5, 0.5, 0.5, 1.0]], np.float32)
+    assert np.array_equal(O.nbody_acc(pos, 1e-6, True), np.zeros((1, 4), np.float32))
+
+
+# -------------------------------------------------------------- schedulers
+def test_static_listing_example():
+    g = _gold("static_listing_example.json")
+    for key in ("static", "static_rev"):
+        got = O.static_plan(g["G"], g["props"], g[key]["order"])
+        assert got == [tuple(r) for r in g[key]["ranges"]]
+
+
+def test_static_bands_equal_split():
+    # 1024 rows, 8 bands of 128; device 0 takes 7/8, device 1 placed first
+    got = O.static_plan(1024, [0.875], [1, 0], n_bands=8)
+    assert got == [(128, 1024), (0, 128)]
+    # every device gets at least one band
+    got = O.static_plan(1024, [0.999], [0, 1], n_bands=8)
+    assert got == [(0, 896), (896, 1024)]
+    assert O.static_plan(1024, [0.5], [0, 1], n_bands=1) is None
+
+
+def test_static_plan_partitions():
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        n = int(rng.integers(1, 5))
+        G = int(rng.integers(n, 5000))
+        props = list(rng.dirichlet(np.ones(n))[: n - 1])
+        order = list(rng.permutation(n))
+        plan = O.static_plan(G, props, order)
+        cov = O.coverage(G, [(b, e - b) for b, e in plan])
+        assert cov.ok
+        # spatial order follows the delivery order
+        starts = [plan[d][0] for d in order]
+        assert starts == sorted(starts)
+
+
+def test_hguided_golden_vector():
+    g = _gold("hguided_vector.json")
+    seq = O.hguided_sequence(g["G"], g["P"], g["k"], g["min"], [i % 2 for i in range(1000)])
+    assert [[d, s] for d, _, s in seq] == g["packages"]
+    assert O.coverage(g["G"], [(b, s) for _, b, s in seq]).ok
+
+
+def test_hguided_sizes_shrink_and_respect_minimum():
+    rng = np.random.default_rng(2)
+    for _ in range(100):
+        n = int(rng.integers(1, 4))
+        P = [int(x) for x in rng.integers(1, 1000, n)]
+        mins = [int(x) for x in rng.integers(1, 20, n)]
+        G = int(rng.integers(1, 100000))
+        req = [int(x) for x in rng.integers(0, n, 100000)]
+        seq = O.hguided_sequence(G, P, int(rng.integers(1, 5)), mins, req)
+        assert O.coverage(G, [(b, s) for _, b, s in seq]).ok
+        last = {}
+        for idx, (d, _, s) in enumerate(seq):
+            if idx + 1 < len(seq):
+                assert s >= mins[d]
+            if d in last:
+                assert s <= last[d]
+            last[d] = s
+
+
+def test_dynamic_equal_packages_with_short_tail():
+    seq = O.dynamic_sequence(1000, 64, [0, 1] * 100)
+    sizes = [s for _, _, s in seq]
+    assert sizes[:-1] == [64] * 15 and sizes[-1] == 1000 - 15 * 64
+    assert O.dynamic_package_for_count(1000, 50) == 20
+    assert O.dynamic_package_for_count(1001, 50) == 21
+
+
+# ------------------------------------------------------------------ metrics
+def test_metrics_closed_forms():
+    assert O.overhead_pct(1.028, 1.0) == pytest.approx(2.8)
+    assert O.balance([2.0, 2.0, 2.0]) == 1.0
+    assert O.balance([1.0, 4.0]) == 0.25
+    # two devices: both readings of the S_max formula give 1 + T_fast / T_slow
+    t1, t2 = 0.5, 3.0
+    assert O.s_max([t1, t2]) == pytest.approx(1 + t1 / t2)
+    assert O.s_max([t1, t2]) == pytest.approx((t1 + t2) / max(t1, t2))
+    assert O.efficiency(1.1, O.s_max([t1, t2])) == pytest.approx(1.1 / (1 + t1 / t2))
