@@ -1,0 +1,326 @@
+#!/usr/bin/env python3
+"""Co-execution bench on one MI355X plus the host CPU cores.
+
+Default workload: 5x5 Gaussian blur of an 8192 x 8192 FP32 image (pixels
+uniform in [0, 1), seed 0xB1), HGuided scheduler, GPU + every host core. A
+step is one ce_engine_run over the whole image. Inputs are resident before
+the timed region: in HBM for the GPU and mirrored in host memory for the host
+workers; the output is gathered into HBM.
+
+The JSON line reports work-items/s of the co-executed run (value), the plain
+single-GPU launch of the same kernel, the engine's overhead over it, the
+balance and efficiency of section 7.3, the roofline of the persistent GPU
+kernel (timed with HIP events on its stream) and the oracle timed on the host.
+
+Other workloads: --workload escape (1024^2, max_iter 256, Static with 8
+packages, GPU + 1 host thread) and --workload nbody (65,536 bodies, Dynamic
+256-body packages, GPU + every host core).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "work-items/s co-executed (GPU+host) vs plain 1-GPU launch; balance efficiency"
+HBM_PEAK_GBS = 8000.0
+# Non-packed FP32 VALU issue rate: 256 CUs x 64 lanes per clock x 2.4 GHz.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["blur", "escape", "nbody"], default="blur")
+    ap.add_argument("--mode", choices=["device", "host"], default="device",
+                    help="device: inputs and output resident in HBM; host: host buffers, PCIe inside the step")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--host-threads", type=int, default=0)
+    return ap.parse_args()
+
+
+def timed_runs(fn, warmup, steps, sync):
+    for _ in range(warmup):
+        fn()
+    sync()
+    ts = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return ts
+
+
+def med(v):
+    return statistics.median(v) if v else float("nan")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1805_02755_amd as ce
+    from paper_1805_02755_amd import synth
+
+    ce.lib()  # fail loudly if the HIP library is missing
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    sync = torch.cuda.synchronize
+    host_cores = os.cpu_count() or 1
+
+    eng = ce.Engine()
+    eng.stream(stream.cuda_stream)
+
+    # ---------------------------------------------------------------- payload
+    wl = args.workload
+    if wl == "blur":
+        w = h = 8192
+        log("generating 8192x8192 image")
+        img = synth.blur_image(w, h)
+        wt = ce.ce_gauss5_weights(1.0)
+        img_d = torch.from_numpy(img).to(dev)
+        wt_d = torch.from_numpy(wt).to(dev)
+        out_d = torch.empty_like(img_d)
+        out_h = np.empty_like(img) if args.mode == "host" else None
+        params = ce.ce_blur5_params(w, h)
+        kid = ce.CE_KERNEL_BLUR5
+        gws, lws = [w, h], None
+        ins_host, ins_dev = [img, wt], [img_d, wt_d]
+        n_items = w * h
+        G = h
+        bytes_per_item = 8.0  # 4 B read + 4 B written; halo re-reads are not algorithmic
+        host_threads = args.host_threads
+        coexec = dict(kind=ce.CE_SCHED_HGUIDED, k=2)
+        config = {"workload": "blur5x5 8192x8192 fp32, sigma 1, clamp-to-edge", "scheduler": "hguided",
+                  "devices": "gpu+host", "residency": args.mode}
+        bound = "hbm"
+    elif wl == "escape":
+        p = synth.escape_small()
+        params = ce.ce_escape_params(p.w, p.h, *p.as_f32(), p.max_iter)
+        kid = ce.CE_KERNEL_ESCAPE
+        gws, lws = [p.w, p.h], None
+        out_d = torch.empty((p.h, p.w), dtype=torch.int32, device=dev)
+        out_h = np.empty((p.h, p.w), np.uint32) if args.mode == "host" else None
+        ins_host, ins_dev = [], []
+        n_items = p.w * p.h
+        G = p.h
+        host_threads = 1
+        coexec = dict(kind=ce.CE_SCHED_STATIC, n_packages=8, order=ce.CE_ORDER_HOST_FIRST)
+        config = {"workload": "escape-time 1024x1024 over [-2,1]x[-1.5,1.5], max_iter 256", "scheduler": "static x8",
+                  "devices": "gpu+1 host thread", "residency": args.mode}
+        bound = "alu"
+    else:
+        n = 65536
+        bodies = synth.nbody_bodies(n)
+        b_d = torch.from_numpy(bodies).to(dev)
+        out_d = torch.empty_like(b_d)
+        out_h = np.empty_like(bodies) if args.mode == "host" else None
+        params = ce.ce_nbody_params(n, 1e-6, 1)
+        kid = ce.CE_KERNEL_NBODY_ACC
+        gws, lws = [n], [256]
+        ins_host, ins_dev = [bodies], [b_d]
+        n_items = n
+        G = n // 256
+        host_threads = args.host_threads
+        coexec = dict(kind=ce.CE_SCHED_DYNAMIC, package_granules=1)
+        config = {"workload": "nbody acceleration 65536 bodies fp32, eps2 1e-6, strict rsqrt",
+                  "scheduler": "dynamic 256-body packages", "devices": "gpu+host", "residency": args.mode}
+        bound = "alu"
+    sync()
+
+    eng.work_items(gws, lws)
+    eng.program_kernel(kid, params)
+    for slot in range(len(ins_host)):
+        if args.mode == "host":
+            eng.program_in(slot, host=ins_host[slot])
+        else:
+            eng.program_in(slot, host=ins_host[slot], dev=ins_dev[slot], nbytes=ins_host[slot].nbytes)
+    if args.mode == "host":
+        eng.program_out(0, host=out_h)
+    else:
+        eng.program_out(0, dev=out_d, nbytes=out_d.numel() * out_d.element_size())
+
+    K, W = args.steps, args.warmup
+
+    # ---------------------------------------------- plain single-GPU launch
+    log("bare launch")
+    def bare():
+        if args.mode == "host":
+            for i, a in enumerate(ins_host):
+                ins_dev_b[i].copy_(torch.from_numpy(a), non_blocking=False)
+            ce.ce_bare_run(kid, params, ins_dev_b, out_d, stream=stream.cuda_stream, sync=True)
+            out_h_b[...] = out_d.cpu().numpy().view(out_h_b.dtype).reshape(out_h_b.shape)
+        else:
+            ce.ce_bare_run(kid, params, ins_dev, out_d, stream=stream.cuda_stream, sync=True)
+    if args.mode == "host":
+        ins_dev_b = [torch.empty(a.shape, dtype=torch.from_numpy(a).dtype, device=dev) for a in ins_host]
+        out_h_b = np.empty_like(out_h)
+    t_bare = timed_runs(bare, W, K, sync)
+
+    # ------------------------------------------------- engine, GPU alone
+    log("engine GPU only")
+    eng.use(ce.CE_DEV_GPU, 0, 0)
+    eng.scheduler(ce.CE_SCHED_STATIC)
+    t_gpu = timed_runs(eng.run, W, K, sync)
+
+    # ------------------------------------------------- engine, host alone
+    log("engine host only")
+    eng.use(ce.CE_DEV_HOST, 0, host_threads)
+    eng.scheduler(ce.CE_SCHED_STATIC)
+    t_host = timed_runs(eng.run, 1, min(K, 5), sync)
+    host_threads_used = eng.stats().host_threads
+
+    # ------------------------------------------------- co-execution
+    T_bare, T_gpu, T_host = med(t_bare), med(t_gpu), med(t_host)
+    if coexec["kind"] == ce.CE_SCHED_HGUIDED:
+        ratio = T_host / T_gpu  # computing powers from the standalone throughputs
+        coexec["power"] = [max(1, min(1 << 20, int(round(ratio)))), 1]
+    elif coexec["kind"] == ce.CE_SCHED_STATIC:
+        coexec["props"] = [max(0.0, 1.0 - T_gpu / (T_gpu + T_host))]
+    eng.use(ce.CE_DEV_GPU | ce.CE_DEV_HOST, 0, host_threads)
+    eng.scheduler(**coexec)
+    log(f"co-execution {coexec}")
+    for _ in range(W):
+        eng.run()
+    ev_s = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ev_e = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    per_run, stats = [], []
+    sync()
+    t0 = time.perf_counter()
+    for i in range(K):
+        eng.kernel_events(ev_s[i], ev_e[i])
+        a = time.perf_counter()
+        eng.run()
+        per_run.append(time.perf_counter() - a)
+        stats.append(eng.stats())
+    sync()
+    T_total = time.perf_counter() - t0
+    eng.kernel_events(None, None)
+    trace = eng.trace()
+
+    kern_ms = [ev_s[i].elapsed_time(ev_e[i]) for i in range(K)]
+    gpu_items = [s.items[0] for s in stats]
+    host_items = [s.items[1] for s in stats]
+    T_co = T_total / K
+    value = n_items * K / T_total
+    s_real = T_bare / T_co
+    s_max = min(T_bare, T_host) * (1.0 / T_bare + 1.0 / T_host)
+    balance = med([s.balance for s in stats])
+
+    # --------------------------------------------------------- roofline
+    if wl == "blur":
+        achieved = sum(bytes_per_item * g for g in gpu_items) / (sum(kern_ms) * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_persistent<Blur5Tile>", "kernel_ms": med(kern_ms),
+                "algorithmic_bytes_per_item": bytes_per_item}
+    elif wl == "escape":
+        cnt = out_d.cpu().numpy().view(np.uint32).astype(np.int64)
+        iters = int(cnt.sum())
+        ops = 8.0 * iters * (sum(gpu_items) / (K * n_items))
+        achieved = ops / (med(kern_ms) * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (FP32 VALU lane-ops)",
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "k_persistent<EscapeTile>",
+                "kernel_ms": med(kern_ms), "iterations": iters}
+    else:
+        n = n_items
+        ops = 24.0 * n * n * (sum(gpu_items) / (K * n_items))
+        achieved = ops / (med(kern_ms) * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (FP32 VALU lane-ops)",
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "k_persistent<NbodyTile<true>>",
+                "kernel_ms": med(kern_ms), "ops_per_interaction": 24}
+
+    # ------------------------------------------------------ CPU baseline
+    cpu_base = None
+    if not args.no_cpu_baseline:
+        log("oracle CPU baseline")
+        from oracle import oracle as O
+        t0 = time.perf_counter()
+        done_items = 0
+        if wl == "blur":
+            wt_o = O.gauss5_weights(1.0)
+            passes = 0
+            while passes < 4 and (time.perf_counter() - t0 < 10.0):
+                O.blur5(img, wt_o)
+                passes += 1
+                done_items += n_items
+            sample = f"{passes} full passes over the 8192x8192 image"
+        elif wl == "escape":
+            passes = 0
+            while passes < 40 and (time.perf_counter() - t0 < 10.0):
+                O.escape(p.w, p.h, *[float(v) for v in p.as_f32()], p.max_iter)
+                passes += 1
+                done_items += n_items
+            sample = f"{passes} full passes over the 1024x1024 grid"
+        else:
+            i = 0
+            while time.perf_counter() - t0 < 10.0:
+                O.nbody_acc_body(bodies, 1e-6, i, True)
+                i += 1
+            done_items = i
+            sample = f"{i} bodies (each against all 65536)"
+        dt = time.perf_counter() - t0
+        cpu_base = {"value": done_items / dt, "unit": "work-items/s", "cores": 1, "kind": "oracle",
+                    "sample": sample, "seconds": dt}
+
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "work-items/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": T_co * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32" if wl == "escape" else "f32",
+        "data": "synthetic (seeded SplitMix64 inputs; see DESIGN.md)",
+        "config": config,
+        "roofline": roof,
+        "cpu_baseline": cpu_base,
+        "coexec": {
+            "plain_gpu_items_per_s": n_items / T_bare,
+            "vs_plain_gpu": s_real,
+            "balance": balance,
+            "s_real": s_real,
+            "s_max": s_max,
+            "efficiency": s_real / s_max,
+            "overhead_pct_gpu_only": (T_gpu - T_bare) / T_bare * 100.0,
+            "t_bare_ms": T_bare * 1e3,
+            "t_engine_gpu_ms": T_gpu * 1e3,
+            "t_engine_host_ms": T_host * 1e3,
+            "t_coexec_ms_median": med(per_run) * 1e3,
+            "host_threads": host_threads_used,
+            "host_cores": host_cores,
+            "gpu_share": sum(gpu_items) / (K * n_items),
+            "packages_gpu": med([s.packages[0] for s in stats]),
+            "packages_host": med([s.packages[1] for s in stats]),
+            "scheduler": {k: (list(v) if isinstance(v, (list, tuple)) else v) for k, v in coexec.items()},
+            "t_device_ms": [med([s.t_device[0] for s in stats]) * 1e3, med([s.t_device[1] for s in stats]) * 1e3],
+            "trace_packages": len(trace),
+        },
+    }
+    print(json.dumps(res), flush=True)
+    eng.close()
+
+
+if __name__ == "__main__":
+    main()

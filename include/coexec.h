@@ -1,0 +1,235 @@
+/*
+ * coexec.h -- C ABI of the MI355X co-execution engine.
+ *
+ * One massive data-parallel kernel is co-executed over an N-dimensional index
+ * space by one MI355X (a persistent HIP kernel pulling packages from a
+ * dispenser) and the host CPU cores (a worker pool pulling from the same
+ * dispenser). The calls follow the programming model of the paper (sections
+ * 4.2 and 6): pick the devices, set the index space, pick a scheduler, bind a
+ * program (kernel, inputs, outputs, output pattern), run synchronously, then
+ * read statistics, the package trace and the error list.
+ *
+ * Conventions shared by every call:
+ *  - Every function returning ce_status returns CE_OK (0) or a negative code;
+ *    a failure is also appended to the engine's error list (section 6.1:
+ *    errors are collected, not thrown). No C++ exception crosses the ABI and
+ *    no call aborts the process.
+ *  - Pointers passed in are borrowed: the caller owns host and device memory,
+ *    which must stay valid and unmodified until ce_engine_run returns.
+ *    "Device pointer" means HIP device memory of the engine's GPU (e.g. a
+ *    PyTorch tensor's data_ptr); "host pointer" means ordinary or pinned host
+ *    memory.
+ *  - An engine is not thread-safe: calls on one engine must not overlap.
+ *    Different engines may be used from different threads.
+ */
+#ifndef COEXEC_H
+#define COEXEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ce_status;
+#define CE_OK 0
+#define CE_E_INVALID (-1)     /* bad argument, size mismatch, unbound slot      */
+#define CE_E_STATE (-2)       /* call not allowed in the engine's current state */
+#define CE_E_NOMEM (-3)       /* host or device allocation failed               */
+#define CE_E_DEVICE (-4)      /* HIP error, or no usable GPU                    */
+#define CE_E_UNSUPPORTED (-5) /* valid request the engine does not implement    */
+#define CE_E_BUDGET (-6)      /* server: job larger than the HBM budget         */
+#define CE_E_TIMEOUT (-7)     /* a device did not finish within the deadline    */
+
+/* Devices (section 6: device masks). Device index order inside the engine is
+ * fixed: the GPU (if used) is device 0, the host worker pool the next one. */
+#define CE_DEV_GPU 1u
+#define CE_DEV_HOST 2u
+#define CE_MAX_DEVICES 2
+
+/* Payload kernels: the paper's benchmark programs used on the hot path
+ * (section 7.2, Table 2). */
+#define CE_KERNEL_ESCAPE 1    /* escape-time fractal (Mandelbrot), 2-D, 0 in : 1 out  */
+#define CE_KERNEL_BLUR5 2     /* 5x5 Gaussian blur, 2-D, 2 in (image, weights) : 1 out */
+#define CE_KERNEL_NBODY_ACC 3 /* all-pairs N-body acceleration, 1-D, 1 in : 1 out      */
+
+/* Schedulers (section 5.3). */
+#define CE_SCHED_STATIC 0
+#define CE_SCHED_DYNAMIC 1
+#define CE_SCHED_HGUIDED 2
+/* Static delivery order (section 7.3: "Static" puts the host's part first
+ * along the index space, "Static rev" the GPU's). */
+#define CE_ORDER_HOST_FIRST 0
+#define CE_ORDER_GPU_FIRST 1
+
+/* Escape-time parameters. Pixel (r, c), 0 <= r < h, 0 <= c < w, has
+ * c = (x0 + c*dx) + i (y0 + r*dy); output uint32 count in [1, max_iter]. */
+typedef struct {
+  uint32_t w, h;
+  float x0, y0, dx, dy;
+  uint32_t max_iter;
+} ce_escape_params;
+
+/* Blur parameters: image w x h FP32 row-major in slot 0, 25 FP32 weights in
+ * slot 1 (row-major over dy = -2..2, dx = -2..2); output w x h FP32. */
+typedef struct {
+  uint32_t w, h;
+} ce_blur5_params;
+
+/* N-body parameters: n bodies as float4 (x, y, z, m) in slot 0; output n
+ * float4 (ax, ay, az, 0). eps2 > 0 is the squared softening. strict != 0
+ * evaluates 1/sqrt by Lomont's method so that GPU and host results are
+ * bitwise identical; strict == 0 uses the GPU's hardware reciprocal square
+ * root and the host's correctly rounded 1/sqrtf (results then agree within a
+ * tolerance, not bitwise). */
+typedef struct {
+  uint32_t n;
+  float eps2;
+  uint32_t strict;
+} ce_nbody_params;
+
+/* Scheduler description (section 5.3). Arrays are indexed by engine device
+ * index (GPU = 0 when used, then host).
+ *  STATIC : props[0..n-2] = fraction of each device but the last, which gets
+ *           the remainder (section 6.2 listing); order = CE_ORDER_*;
+ *           n_packages > 0 cuts the space into that many equal bands first
+ *           and hands each device whole bands (every device gets >= 1 band).
+ *  DYNAMIC: equal packages of package_granules granules, or, when that is 0,
+ *           ceil(G / n_packages) granules; handed in index order to whichever
+ *           device asks; the last package may be short.
+ *  HGUIDED: package for device i = max(min_granules[i],
+ *           floor(G_r * power[i] / (k * n * sum_j power[j]))), cut to the
+ *           pending granules G_r. power[i] in [1, 2^20]; k >= 1;
+ *           min_granules[i] == 0 selects the default (GPU: one tile per
+ *           resident workgroup; host: 1 granule). */
+typedef struct {
+  int32_t kind;
+  int32_t order;
+  uint32_t n_packages;
+  uint32_t k;
+  uint64_t package_granules;
+  double props[CE_MAX_DEVICES];
+  uint64_t power[CE_MAX_DEVICES];
+  uint64_t min_granules[CE_MAX_DEVICES];
+} ce_sched_desc;
+
+/* Statistics of the last run. Times are seconds on the host's steady clock,
+ * measured from the start of ce_engine_run. t_device[d] is the end of device
+ * d's last package (0 if it got none). */
+typedef struct {
+  double t_run;                       /* whole ce_engine_run call            */
+  double t_device[CE_MAX_DEVICES];    /* finish time of each device           */
+  double t_gpu_kernel;                /* GPU persistent kernel, first to last package end */
+  uint64_t granules[CE_MAX_DEVICES];  /* granules computed by each device     */
+  uint64_t items[CE_MAX_DEVICES];     /* work-items computed by each device   */
+  uint64_t packages[CE_MAX_DEVICES];  /* packages taken by each device        */
+  uint32_t n_devices;
+  uint32_t device_kind[CE_MAX_DEVICES]; /* CE_DEV_GPU or CE_DEV_HOST          */
+  double balance;                     /* min_d t_device / max_d t_device (section 7.3) */
+  uint64_t total_granules;
+  uint64_t total_items;
+  uint32_t gpu_workgroups;            /* persistent grid size of the last run */
+  uint32_t host_threads;              /* host worker threads of the last run  */
+} ce_run_stats;
+
+/* One package of the last run (section 5 "Introspector"): device, granule
+ * range and times (seconds from run start; GPU times mapped onto the host
+ * clock by a calibration done at engine creation). */
+typedef struct {
+  uint32_t device;
+  uint32_t pad;
+  uint64_t begin, end; /* granules [begin, end) */
+  double t_claim, t_end;
+} ce_package_rec;
+
+typedef struct ce_engine ce_engine;
+
+/* Creates an engine: initialises HIP on the GPU (ordinal 0 by default), the
+ * host-coherent dispenser memory, the clock calibration and the host pool.
+ * Fails with CE_E_DEVICE if no gfx950 GPU is present. *out is NULL on error. */
+ce_status ce_engine_create(ce_engine** out);
+/* Releases every resource of the engine; NULL-safe. */
+void ce_engine_destroy(ce_engine* e);
+
+/* Device set (section 6: engine.use). dev_mask = CE_DEV_GPU | CE_DEV_HOST;
+ * gpu_ordinal selects the HIP device (must match the engine's GPU, i.e. the
+ * one current at creation); host_threads <= 0 uses every host core. */
+ce_status ce_engine_use(ce_engine* e, uint32_t dev_mask, int gpu_ordinal, int host_threads);
+/* Index space (section 6: work_items). ndim 1 or 2; gws[0] is the fastest
+ * dimension. The granule -- the smallest package -- is one row (gws[0]
+ * items) for 2-D spaces and lws[0] items for 1-D spaces. lws may be NULL
+ * (1-D default 256). The space must match the bound kernel's parameters. */
+ce_status ce_engine_work_items(ce_engine* e, uint32_t ndim, const uint64_t* gws, const uint32_t* lws);
+/* Scheduler (section 6.2: engine.scheduler). The descriptor is copied. */
+ce_status ce_engine_scheduler(ce_engine* e, const ce_sched_desc* s);
+/* HIP stream (hipStream_t) the GPU work is ordered on; NULL = the engine's
+ * own stream. The stream is borrowed. */
+ce_status ce_engine_stream(ce_engine* e, void* hip_stream);
+
+/* Program (section 6: Program::kernel / in / out / out_pattern). params is
+ * copied; params_size must equal the size of the kernel's parameter struct. */
+ce_status ce_program_kernel(ce_engine* e, int kernel_id, const void* params, size_t params_size);
+/* Binds input slot `slot`. At least one of host_ptr / dev_ptr must be given.
+ * The GPU reads dev_ptr (or a device copy the engine makes of host_ptr); the
+ * host workers read host_ptr (or a host copy the engine makes of dev_ptr).
+ * bytes must equal the slot's size for the bound kernel. */
+ce_status ce_program_in(ce_engine* e, uint32_t slot, const void* host_ptr, const void* dev_ptr, size_t bytes);
+/* Binds output slot `slot`. After a successful run the whole output is in
+ * every pointer given (host_ptr and/or dev_ptr). */
+ce_status ce_program_out(ce_engine* e, uint32_t slot, void* host_ptr, void* dev_ptr, size_t bytes);
+/* Output pattern outs:items (section 4.2): each package of `items` work-items
+ * writes `outs` output elements. The payloads here write one element per
+ * work-item, so only 1:1 is accepted (others: CE_E_UNSUPPORTED). */
+ce_status ce_program_out_pattern(ce_engine* e, uint32_t outs, uint32_t items);
+
+/* Records the caller's HIP events (hipEvent_t handles) on the engine's
+ * stream immediately before and after the GPU kernel of each following run,
+ * so the caller can time the kernel with hipEventElapsedTime. NULL, NULL
+ * stops recording. The events are borrowed. */
+ce_status ce_engine_kernel_events(ce_engine* e, void* start_event, void* stop_event);
+
+/* Runs the bound program synchronously (section 6: engine.run): on return
+ * every output pointer holds the full result, or the call failed and outputs
+ * are unspecified. */
+ce_status ce_engine_run(ce_engine* e);
+
+/* Statistics of the last successful run. */
+ce_status ce_engine_stats(const ce_engine* e, ce_run_stats* out);
+/* Copies up to cap package records of the last run into buf (may be NULL
+ * with cap 0) and returns the total number of packages. */
+size_t ce_engine_trace(const ce_engine* e, ce_package_rec* buf, size_t cap);
+
+/* Error list (section 6.1: has_errors / get_errors). The string is owned by
+ * the engine and valid until the next call that changes the list. */
+int ce_engine_has_errors(const ce_engine* e);
+int ce_engine_error_count(const ce_engine* e);
+const char* ce_engine_error(const ce_engine* e, int i);
+void ce_engine_clear_errors(ce_engine* e);
+
+/* ---- plain single-GPU launch (the "native" side of the overhead metric,
+ * section 7.3): one grid launch of the same payload over the whole index
+ * space with no dispenser, on `hip_stream` (NULL = default stream). Device
+ * pointers only; ins[] follows the kernel's input slots. sync != 0 waits for
+ * completion. Returns CE_E_DEVICE without a GPU. */
+ce_status ce_bare_run(int kernel_id, const void* params, size_t params_size, const void* const* ins,
+                      void* out, void* hip_stream, int sync);
+
+/* ---- scheduler plan helpers (pure host logic, no GPU needed) */
+/* Static plan: begin/end granule of each of n devices (section 5.3). */
+ce_status ce_sched_static_plan(uint64_t G, uint32_t n, const double* props, const uint32_t* order,
+                               uint32_t n_bands, uint64_t* begin, uint64_t* end);
+/* HGuided package size for device i given G_r pending granules. */
+uint64_t ce_sched_hguided_size(uint64_t G_r, const uint64_t* power, uint32_t n, uint32_t k, uint32_t i,
+                               uint64_t min_i);
+
+/* 5x5 Gaussian weights for sigma (normalised in double, rounded to FP32). */
+ce_status ce_gauss5_weights(double sigma, float* w25);
+
+/* Library version string. */
+const char* ce_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COEXEC_H */

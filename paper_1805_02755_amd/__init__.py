@@ -1,0 +1,320 @@
+"""Python binding of the MI355X co-execution engine (libcoexec.so).
+
+Argument marshalling only: every step of a run executes inside the native
+library (HIP kernels on the GPU, C++ workers on the host cores). The names
+follow the C ABI declared in include/coexec.h. There is no fallback: if the
+library is not built, loading it raises.
+
+The library is loaded lazily, so ``import paper_1805_02755_amd.synth`` does
+not touch it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcoexec.so")
+
+# status codes
+CE_OK = 0
+CE_E_INVALID = -1
+CE_E_STATE = -2
+CE_E_NOMEM = -3
+CE_E_DEVICE = -4
+CE_E_UNSUPPORTED = -5
+CE_E_BUDGET = -6
+CE_E_TIMEOUT = -7
+STATUS_NAMES = {0: "CE_OK", -1: "CE_E_INVALID", -2: "CE_E_STATE", -3: "CE_E_NOMEM", -4: "CE_E_DEVICE",
+                -5: "CE_E_UNSUPPORTED", -6: "CE_E_BUDGET", -7: "CE_E_TIMEOUT"}
+
+CE_DEV_GPU = 1
+CE_DEV_HOST = 2
+CE_MAX_DEVICES = 2
+
+CE_KERNEL_ESCAPE = 1
+CE_KERNEL_BLUR5 = 2
+CE_KERNEL_NBODY_ACC = 3
+
+CE_SCHED_STATIC = 0
+CE_SCHED_DYNAMIC = 1
+CE_SCHED_HGUIDED = 2
+CE_ORDER_HOST_FIRST = 0
+CE_ORDER_GPU_FIRST = 1
+
+EXPORTED_SYMBOLS = (
+    "ce_engine_create", "ce_engine_destroy", "ce_engine_use", "ce_engine_work_items", "ce_engine_scheduler",
+    "ce_engine_stream", "ce_engine_kernel_events", "ce_program_kernel", "ce_program_in", "ce_program_out", "ce_program_out_pattern",
+    "ce_engine_run", "ce_engine_stats", "ce_engine_trace", "ce_engine_has_errors", "ce_engine_error_count",
+    "ce_engine_error", "ce_engine_clear_errors", "ce_bare_run", "ce_sched_static_plan", "ce_sched_hguided_size",
+    "ce_gauss5_weights", "ce_version",
+)
+
+
+class ce_escape_params(C.Structure):
+    _fields_ = [("w", C.c_uint32), ("h", C.c_uint32), ("x0", C.c_float), ("y0", C.c_float), ("dx", C.c_float),
+                ("dy", C.c_float), ("max_iter", C.c_uint32)]
+
+
+class ce_blur5_params(C.Structure):
+    _fields_ = [("w", C.c_uint32), ("h", C.c_uint32)]
+
+
+class ce_nbody_params(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("eps2", C.c_float), ("strict", C.c_uint32)]
+
+
+class ce_sched_desc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("order", C.c_int32), ("n_packages", C.c_uint32), ("k", C.c_uint32),
+                ("package_granules", C.c_uint64), ("props", C.c_double * CE_MAX_DEVICES),
+                ("power", C.c_uint64 * CE_MAX_DEVICES), ("min_granules", C.c_uint64 * CE_MAX_DEVICES)]
+
+
+class ce_run_stats(C.Structure):
+    _fields_ = [("t_run", C.c_double), ("t_device", C.c_double * CE_MAX_DEVICES), ("t_gpu_kernel", C.c_double),
+                ("granules", C.c_uint64 * CE_MAX_DEVICES), ("items", C.c_uint64 * CE_MAX_DEVICES),
+                ("packages", C.c_uint64 * CE_MAX_DEVICES), ("n_devices", C.c_uint32),
+                ("device_kind", C.c_uint32 * CE_MAX_DEVICES), ("balance", C.c_double),
+                ("total_granules", C.c_uint64), ("total_items", C.c_uint64), ("gpu_workgroups", C.c_uint32),
+                ("host_threads", C.c_uint32)]
+
+
+class ce_package_rec(C.Structure):
+    _fields_ = [("device", C.c_uint32), ("pad", C.c_uint32), ("begin", C.c_uint64), ("end", C.c_uint64),
+                ("t_claim", C.c_double), ("t_end", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libcoexec.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                          "python -m paper_1805_02755_amd._build")
+    L = C.CDLL(LIB_PATH)
+    vp, sz, u32, u64, i32 = C.c_void_p, C.c_size_t, C.c_uint32, C.c_uint64, C.c_int32
+    sigs = {
+        "ce_engine_create": (i32, [C.POINTER(vp)]),
+        "ce_engine_destroy": (None, [vp]),
+        "ce_engine_use": (i32, [vp, u32, C.c_int, C.c_int]),
+        "ce_engine_work_items": (i32, [vp, u32, C.POINTER(u64), C.POINTER(u32)]),
+        "ce_engine_scheduler": (i32, [vp, C.POINTER(ce_sched_desc)]),
+        "ce_engine_stream": (i32, [vp, vp]),
+        "ce_engine_kernel_events": (i32, [vp, vp, vp]),
+        "ce_program_kernel": (i32, [vp, C.c_int, vp, sz]),
+        "ce_program_in": (i32, [vp, u32, vp, vp, sz]),
+        "ce_program_out": (i32, [vp, u32, vp, vp, sz]),
+        "ce_program_out_pattern": (i32, [vp, u32, u32]),
+        "ce_engine_run": (i32, [vp]),
+        "ce_engine_stats": (i32, [vp, C.POINTER(ce_run_stats)]),
+        "ce_engine_trace": (sz, [vp, C.POINTER(ce_package_rec), sz]),
+        "ce_engine_has_errors": (C.c_int, [vp]),
+        "ce_engine_error_count": (C.c_int, [vp]),
+        "ce_engine_error": (C.c_char_p, [vp, C.c_int]),
+        "ce_engine_clear_errors": (None, [vp]),
+        "ce_bare_run": (i32, [C.c_int, vp, sz, C.POINTER(vp), vp, vp, C.c_int]),
+        "ce_sched_static_plan": (i32, [u64, u32, C.POINTER(C.c_double), C.POINTER(u32), u32, C.POINTER(u64),
+                                       C.POINTER(u64)]),
+        "ce_sched_hguided_size": (u64, [u64, C.POINTER(u64), u32, u32, u32, u64]),
+        "ce_gauss5_weights": (i32, [C.c_double, C.POINTER(C.c_float)]),
+        "ce_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+class CoexecError(RuntimeError):
+    def __init__(self, status: int, where: str, messages=()):
+        self.status = status
+        self.messages = list(messages)
+        msg = f"{where}: {STATUS_NAMES.get(status, status)}"
+        if self.messages:
+            msg += " -- " + " | ".join(self.messages)
+        super().__init__(msg)
+
+
+def _ptr(x) -> Optional[int]:
+    """Address of a torch tensor, numpy array, int or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if hasattr(x, "ctypes"):
+        return x.ctypes.data
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def _nbytes(x) -> int:
+    if hasattr(x, "nbytes"):
+        return int(x.nbytes)
+    if hasattr(x, "element_size"):
+        return int(x.numel() * x.element_size())
+    raise TypeError(f"cannot size {type(x)}")
+
+
+# ---------------------------------------------------------------- free functions
+def ce_version() -> str:
+    return lib().ce_version().decode()
+
+
+def ce_gauss5_weights(sigma: float = 1.0):
+    import numpy as np
+    w = np.empty(25, dtype=np.float32)
+    st = lib().ce_gauss5_weights(sigma, w.ctypes.data_as(C.POINTER(C.c_float)))
+    if st != CE_OK:
+        raise CoexecError(st, "ce_gauss5_weights")
+    return w
+
+
+def ce_sched_static_plan(G: int, props, order, n_bands: int = 0):
+    n = len(order)
+    p = (C.c_double * max(1, n - 1))(*(list(props)[: n - 1] or [0.0]))
+    o = (C.c_uint32 * n)(*order)
+    b = (C.c_uint64 * n)()
+    e = (C.c_uint64 * n)()
+    st = lib().ce_sched_static_plan(G, n, p, o, n_bands, b, e)
+    if st != CE_OK:
+        return None
+    return [(int(b[d]), int(e[d])) for d in range(n)]
+
+
+def ce_sched_hguided_size(G_r: int, power, k: int, i: int, min_i: int) -> int:
+    P = (C.c_uint64 * len(power))(*power)
+    return int(lib().ce_sched_hguided_size(G_r, P, len(power), k, i, min_i))
+
+
+def _params(kernel_id: int, params):
+    return params, C.sizeof(params)
+
+
+def ce_bare_run(kernel_id: int, params, ins, out, stream=None, sync: bool = True) -> None:
+    """One plain grid launch of the payload over the whole space (device pointers)."""
+    arr = (C.c_void_p * max(1, len(ins)))(*[_ptr(x) for x in ins]) if ins else None
+    st = lib().ce_bare_run(kernel_id, C.byref(params), C.sizeof(params), arr, _ptr(out),
+                           _ptr(stream) if stream is not None else None, int(sync))
+    if st != CE_OK:
+        raise CoexecError(st, "ce_bare_run")
+
+
+def stream_handle(stream) -> Optional[int]:
+    """hipStream_t of a torch.cuda.Stream (or None)."""
+    if stream is None:
+        return None
+    return int(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------- engine
+class Engine:
+    """Owns one ce_engine; methods mirror the C calls one to one."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        st = lib().ce_engine_create(C.byref(h))
+        if st != CE_OK:
+            raise CoexecError(st, "ce_engine_create")
+        self._h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ce_engine_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def errors(self):
+        L = lib()
+        return [L.ce_engine_error(self._h, i).decode() for i in range(L.ce_engine_error_count(self._h))]
+
+    def clear_errors(self):
+        lib().ce_engine_clear_errors(self._h)
+
+    def _check(self, st, where):
+        if st != CE_OK:
+            raise CoexecError(st, where, self.errors()[-3:])
+        return st
+
+    def use(self, dev_mask: int, gpu_ordinal: int = 0, host_threads: int = 0):
+        return self._check(lib().ce_engine_use(self._h, dev_mask, gpu_ordinal, host_threads), "ce_engine_use")
+
+    def work_items(self, gws, lws=None):
+        g = (C.c_uint64 * len(gws))(*gws)
+        l = (C.c_uint32 * len(lws))(*lws) if lws else None
+        return self._check(lib().ce_engine_work_items(self._h, len(gws), g, l), "ce_engine_work_items")
+
+    def scheduler(self, kind: int, order: int = CE_ORDER_HOST_FIRST, n_packages: int = 0, k: int = 2,
+                  package_granules: int = 0, props=(), power=(), min_granules=()):
+        d = ce_sched_desc()
+        d.kind, d.order, d.n_packages, d.k, d.package_granules = kind, order, n_packages, k, package_granules
+        for i, v in enumerate(props):
+            d.props[i] = v
+        for i, v in enumerate(power):
+            d.power[i] = v
+        for i, v in enumerate(min_granules):
+            d.min_granules[i] = v
+        return self._check(lib().ce_engine_scheduler(self._h, C.byref(d)), "ce_engine_scheduler")
+
+    def stream(self, hip_stream):
+        return self._check(lib().ce_engine_stream(self._h, hip_stream), "ce_engine_stream")
+
+    def kernel_events(self, start=None, stop=None):
+        """Records torch.cuda.Event objects (or raw hipEvent_t) around the GPU kernel."""
+        a = None if start is None else int(getattr(start, "cuda_event", start))
+        b = None if stop is None else int(getattr(stop, "cuda_event", stop))
+        return self._check(lib().ce_engine_kernel_events(self._h, a, b), "ce_engine_kernel_events")
+
+    def program_kernel(self, kernel_id: int, params):
+        self._params = params
+        return self._check(lib().ce_program_kernel(self._h, kernel_id, C.byref(params), C.sizeof(params)),
+                           "ce_program_kernel")
+
+    def program_in(self, slot: int, host=None, dev=None, nbytes: Optional[int] = None):
+        nb = nbytes if nbytes is not None else _nbytes(host if host is not None else dev)
+        self._keep += [host, dev]
+        return self._check(lib().ce_program_in(self._h, slot, _ptr(host), _ptr(dev), nb), "ce_program_in")
+
+    def program_out(self, slot: int, host=None, dev=None, nbytes: Optional[int] = None):
+        nb = nbytes if nbytes is not None else _nbytes(host if host is not None else dev)
+        self._keep += [host, dev]
+        return self._check(lib().ce_program_out(self._h, slot, _ptr(host), _ptr(dev), nb), "ce_program_out")
+
+    def program_out_pattern(self, outs: int, items: int):
+        return self._check(lib().ce_program_out_pattern(self._h, outs, items), "ce_program_out_pattern")
+
+    def run(self):
+        return self._check(lib().ce_engine_run(self._h), "ce_engine_run")
+
+    def run_status(self) -> int:
+        return int(lib().ce_engine_run(self._h))
+
+    def stats(self) -> ce_run_stats:
+        s = ce_run_stats()
+        self._check(lib().ce_engine_stats(self._h, C.byref(s)), "ce_engine_stats")
+        return s
+
+    def trace(self):
+        n = lib().ce_engine_trace(self._h, None, 0)
+        buf = (ce_package_rec * max(1, n))()
+        n = lib().ce_engine_trace(self._h, buf, n)
+        return [(r.device, r.begin, r.end, r.t_claim, r.t_end) for r in buf[:n]]

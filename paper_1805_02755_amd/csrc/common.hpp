@@ -1,0 +1,110 @@
+// Layouts and integer helpers shared by the host engine (g++) and the GPU
+// kernels (hipcc). Nothing here does payload arithmetic.
+#pragma once
+
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define CE_HD __host__ __device__ inline
+#else
+#define CE_HD inline
+#endif
+
+namespace ce {
+
+enum SchedKind : uint32_t { kStatic = 0, kDynamic = 1, kHGuided = 2 };
+
+// Tiles: how a package of granules is cut for the GPU's workgroups.
+// 2-D payloads: a tile is kTileRows rows by one column block.
+constexpr uint32_t kEscapeTileRows = 16;
+constexpr uint32_t kEscapeTileCols = 64;
+constexpr uint32_t kBlurTileRows = 16;
+constexpr uint32_t kBlurTileCols = 1024;  // 256 threads x 4 columns
+constexpr uint32_t kNbodyGranule = 256;   // bodies per granule (1-D lws)
+constexpr uint32_t kBlockThreads = 256;
+
+// Dispenser state shared by the GPU and the host, in host-coherent pinned
+// memory. The GPU uses system-scope atomics on it.
+struct alignas(64) L1State {
+  uint64_t next;        // next granule not yet handed to any device
+  uint64_t pad0[7];
+  // written by the last GPU workgroup of a run (system-scope stores)
+  uint64_t gpu_run_id;  // run id of the finished GPU part
+  uint64_t gpu_t_first; // s_memrealtime of the first package claim
+  uint64_t gpu_t_last;  // s_memrealtime of the last package end
+  uint64_t gpu_granules;
+  uint64_t gpu_packages;
+  uint64_t gpu_flags;   // bit 0: a wait on the dispenser timed out
+  uint64_t pad1[2];
+  // clock calibration mailbox
+  uint64_t ping;
+  uint64_t pong;
+  uint64_t tick;
+  uint64_t pad2[5];
+};
+
+// Per-run GPU queue state in HBM (device-scope atomics only). The last
+// workgroup to leave a run resets it to zero for the next run.
+struct alignas(64) L2State {
+  uint64_t ticket;      // next tile ticket
+  uint64_t total;       // tiles of all published packages
+  uint32_t n_pkgs;      // packages published
+  uint32_t done;        // no more packages for this device
+  uint32_t exit_count;  // workgroups that left
+  uint32_t st_next;     // static: next band of this device
+  uint64_t granules;    // granules published
+  uint64_t t_first;     // first claim tick
+  uint64_t t_last;      // latest package end tick
+  uint64_t pad[2];
+};
+
+// One GPU package as published to the workgroups; also its trace record.
+struct alignas(64) PkgSlot {
+  uint64_t g0, g1;      // granules [g0, g1)
+  uint64_t base;        // first tile ticket of the package
+  uint32_t ntiles;
+  uint32_t tiles_done;
+  uint64_t t_claim;     // s_memrealtime at claim
+  uint64_t t_end;       // s_memrealtime when its last tile finished
+  uint64_t pad[2];
+};
+
+// Scheduler arguments of one device for one run (kernel argument by value).
+struct SchedArgs {
+  uint32_t kind;
+  uint32_t n_dev;       // devices in the set (HGuided n)
+  uint32_t k;           // HGuided k
+  uint32_t direct;      // Dynamic with one tile per package: claim per workgroup
+  uint64_t G;           // granules in the index space
+  uint64_t pkg;         // Dynamic package size (granules)
+  uint64_t P_self;      // HGuided power of this device
+  uint64_t sumP;        // HGuided sum of powers
+  uint64_t min_self;    // HGuided minimum package of this device
+  uint64_t st_begin, st_end;  // Static: this device's granule range
+  uint64_t st_nbands;   // Static: band grid (0 = one package)
+  uint64_t run_id;
+  uint64_t spin_limit;  // bound on any wait inside the kernel (iterations)
+  L1State* l1;          // device address of the host-coherent dispenser
+  L2State* l2;          // HBM
+  PkgSlot* pkgs;
+  uint32_t max_pkgs;
+  uint32_t pad;
+};
+
+// HGuided package size (section 5.3 equation), integer only. Callers keep
+// G_r < 2^40 and P <= 2^20 so the products fit in 64 bits.
+CE_HD uint64_t hguided_size(uint64_t G_r, uint64_t P_i, uint64_t sumP, uint32_t n, uint32_t k,
+                            uint64_t min_i) {
+  const uint64_t den = (uint64_t)k * (uint64_t)n * sumP;
+  uint64_t s = den ? (G_r * P_i) / den : G_r;
+  if (s < min_i) s = min_i;
+  if (s > G_r) s = G_r;
+  return s;
+}
+
+// Static: the b-th band of a grid of nb bands over G granules.
+CE_HD uint64_t band_edge(uint64_t b, uint64_t G, uint64_t nb) { return nb ? (b * G) / nb : 0; }
+
+CE_HD uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+}  // namespace ce

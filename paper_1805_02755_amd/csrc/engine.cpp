@@ -1,0 +1,1192 @@
+// Host engine of the co-execution library and the C ABI (include/coexec.h).
+//
+// Architecture (section 4.2, section 5): the engine owns a device set (the
+// GPU and a host worker pool), an index space cut into granules, a scheduler
+// (section 5.3) and a program (kernel, buffers, output pattern). A run arms
+// the shared level-1 dispenser in host-coherent memory, launches the GPU's
+// persistent kernel and wakes the host pool; both sides claim packages from
+// the same dispenser until the space is exhausted. Outputs are then merged so
+// that every bound output pointer holds the full result.
+#include <hip/hip_runtime_api.h>
+#include <immintrin.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <exception>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/coexec.h"
+#include "common.hpp"
+#include "host_payloads.hpp"
+#include "kernels.hpp"
+
+namespace ce {
+namespace {
+
+inline int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+inline void cpu_relax() { _mm_pause(); }
+
+constexpr uint32_t kHostNbodyTile = 16;  // bodies per host tile
+constexpr int kMaxSlots = 2;
+
+struct Binding {
+  const void* host = nullptr;  // input: read by host workers
+  const void* dev = nullptr;   // input: read by the GPU
+  void* host_out = nullptr;
+  void* dev_out = nullptr;
+  size_t bytes = 0;
+  bool bound = false;
+};
+
+// Engine-owned scratch memory that grows on demand.
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  bool ensure(size_t bytes) {
+    if (bytes <= n) return true;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+    if (hipMalloc(&p, bytes) != hipSuccess) return false;
+    n = bytes;
+    return true;
+  }
+};
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  bool ensure(size_t bytes) {
+    if (bytes <= n) return true;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return false;
+    n = bytes;
+    return true;
+  }
+};
+
+struct HostPkg {
+  uint64_t g0 = 0, g1 = 0, base = 0;
+  uint32_t ntiles = 0;
+  std::atomic<uint32_t> tiles_done{0};
+  int64_t t_claim = 0;
+  std::atomic<int64_t> t_end{0};
+};
+
+// The host worker pool's own level-2 chain (same protocol as the GPU's).
+struct HostQueue {
+  alignas(64) std::atomic<uint64_t> ticket{0};
+  alignas(64) std::atomic<uint64_t> total{0};
+  alignas(64) std::atomic<uint32_t> done{0};
+  uint32_t n_pkgs = 0;     // written by the claimer only
+  uint64_t st_next = 0;    // static band cursor (claimer only)
+  uint64_t granules = 0;   // claimer only
+  std::unique_ptr<HostPkg[]> pkgs;
+  size_t cap = 0;
+  bool ensure(size_t n) {
+    if (n <= cap) return true;
+    pkgs.reset(new (std::nothrow) HostPkg[n]);
+    cap = pkgs ? n : 0;
+    return pkgs != nullptr;
+  }
+  void reset() {
+    ticket.store(0, std::memory_order_relaxed);
+    total.store(0, std::memory_order_relaxed);
+    done.store(0, std::memory_order_relaxed);
+    n_pkgs = 0;
+    st_next = 0;
+    granules = 0;
+  }
+};
+
+}  // namespace
+}  // namespace ce
+
+using namespace ce;
+
+struct ce_engine {
+  // ---- device and HIP state
+  int gpu = -1;
+  int n_cu = 0;
+  uint32_t wallclock_hz = 100000000;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // caller's, optional
+  L1State* l1 = nullptr;       // host view
+  L1State* l1_dev = nullptr;   // device view
+  L2State* l2 = nullptr;
+  DevBuf pkgs_dev;
+  uint32_t pkgs_dev_cap = 0;
+  double clock_offset_ns = 0.0;  // host_ns = tick * period + offset
+  bool clock_ok = false;
+  const HostPayloadFns* hp = nullptr;
+
+  // ---- configuration
+  uint32_t dev_mask = CE_DEV_GPU;
+  int host_threads = 0;  // resolved count
+  uint32_t ndim = 0;
+  uint64_t gws[2] = {0, 0};
+  uint32_t lws0 = 256;
+  ce_sched_desc sched{};
+  bool sched_set = false;
+  int kernel_id = 0;
+  ce_escape_params esc{};
+  ce_blur5_params blur{};
+  ce_nbody_params nb{};
+  Binding in[kMaxSlots];
+  Binding out[1];
+  uint32_t pat_outs = 1, pat_items = 1;
+
+  // ---- scratch
+  DevBuf in_dev[kMaxSlots];
+  PinnedBuf in_host[kMaxSlots];
+  DevBuf out_dev_scratch;
+  PinnedBuf out_host_scratch;
+
+  // ---- host pool
+  std::vector<std::thread> pool;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::atomic<uint64_t> epoch{0};
+  std::atomic<uint32_t> pool_done{0};
+  std::atomic<bool> quit{false};
+  std::atomic<int> sleeping{0};
+
+  // ---- per-run state
+  HostQueue hq;
+  SchedArgs host_args{};
+  KernelArgs kargs{};
+  uint64_t run_id = 0;
+  int64_t t0_ns = 0;
+  const void* host_in0 = nullptr;
+  const void* host_in1 = nullptr;
+  void* host_out = nullptr;
+  std::atomic<int> host_error{0};
+
+  // ---- results
+  ce_run_stats stats{};
+  bool stats_valid = false;
+  std::vector<ce_package_rec> trace;
+  uint64_t gpu_pkgs_last = 0;
+  uint32_t gpu_grid_last = 0;
+
+  std::vector<std::string> errors;
+
+  ce_status fail(ce_status code, const char* fmt, ...) __attribute__((format(printf, 3, 4))) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    errors.emplace_back(buf);
+    return code;
+  }
+  ce_status hip_fail(hipError_t e, const char* what) {
+    return fail(CE_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  }
+
+  bool use_gpu() const { return dev_mask & CE_DEV_GPU; }
+  bool use_host() const { return dev_mask & CE_DEV_HOST; }
+  uint32_t n_devices() const { return (use_gpu() ? 1u : 0u) + (use_host() ? 1u : 0u); }
+  int gpu_index() const { return use_gpu() ? 0 : -1; }
+  int host_index() const { return use_host() ? (use_gpu() ? 1 : 0) : -1; }
+
+  double tick_to_host_s(uint64_t tick) const {
+    const double ns = (double)tick * (1e9 / (double)wallclock_hz) + clock_offset_ns;
+    return (ns - (double)t0_ns) * 1e-9;
+  }
+
+  // ------------------------------------------------------------ geometry
+  uint64_t granules() const {
+    switch (kernel_id) {
+      case CE_KERNEL_ESCAPE: return esc.h;
+      case CE_KERNEL_BLUR5: return blur.h;
+      case CE_KERNEL_NBODY_ACC: return ceil_div(nb.n, kNbodyGranule);
+    }
+    return 0;
+  }
+  uint64_t items_in(uint64_t g0, uint64_t g1) const {
+    switch (kernel_id) {
+      case CE_KERNEL_ESCAPE: return (g1 - g0) * esc.w;
+      case CE_KERNEL_BLUR5: return (g1 - g0) * blur.w;
+      case CE_KERNEL_NBODY_ACC: {
+        const uint64_t a = g0 * kNbodyGranule, b = std::min<uint64_t>(g1 * kNbodyGranule, nb.n);
+        return b > a ? b - a : 0;
+      }
+    }
+    return 0;
+  }
+  size_t out_elem_bytes() const { return kernel_id == CE_KERNEL_NBODY_ACC ? 16 : 4; }
+  uint64_t item_offset(uint64_t g) const {
+    return kernel_id == CE_KERNEL_NBODY_ACC ? std::min<uint64_t>(g * kNbodyGranule, nb.n) : g * gws[0];
+  }
+  size_t in_bytes(int slot) const {
+    switch (kernel_id) {
+      case CE_KERNEL_BLUR5:
+        return slot == 0 ? (size_t)blur.w * blur.h * 4 : (slot == 1 ? 25 * 4 : 0);
+      case CE_KERNEL_NBODY_ACC: return slot == 0 ? (size_t)nb.n * 16 : 0;
+    }
+    return 0;
+  }
+  int n_in_slots() const {
+    switch (kernel_id) {
+      case CE_KERNEL_BLUR5: return 2;
+      case CE_KERNEL_NBODY_ACC: return 1;
+    }
+    return 0;
+  }
+  size_t out_bytes() const {
+    switch (kernel_id) {
+      case CE_KERNEL_ESCAPE: return (size_t)esc.w * esc.h * 4;
+      case CE_KERNEL_BLUR5: return (size_t)blur.w * blur.h * 4;
+      case CE_KERNEL_NBODY_ACC: return (size_t)nb.n * 16;
+    }
+    return 0;
+  }
+  uint32_t host_tiles(uint64_t g0, uint64_t g1) const {
+    if (kernel_id == CE_KERNEL_NBODY_ACC) return (uint32_t)ceil_div(items_in(g0, g1), kHostNbodyTile);
+    return (uint32_t)(g1 - g0);
+  }
+
+  // ------------------------------------------------------------ host pool
+  // Threads start from the epoch current before the run that needs them is
+  // published, so a thread created just before a run still takes part in it.
+  void pool_start(int n) {
+    const uint64_t start = epoch.load();
+    for (int i = 0; i < n; ++i) pool.emplace_back([this, i, start] { pool_loop(i + 1, start); });
+  }
+  void pool_stop() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      quit.store(true);
+    }
+    cv.notify_all();
+    for (auto& t : pool) t.join();
+    pool.clear();
+    quit.store(false);
+  }
+  void pool_loop(int tid, uint64_t seen) {
+    for (;;) {
+      // spin briefly for low wake-up latency, then sleep
+      const int64_t spin_until = now_ns() + 20'000'000;
+      uint64_t e;
+      while ((e = epoch.load(std::memory_order_acquire)) == seen && !quit.load(std::memory_order_relaxed)) {
+        if (now_ns() > spin_until) {
+          std::unique_lock<std::mutex> lk(mu);
+          sleeping.fetch_add(1);
+          cv.wait(lk, [&] { return epoch.load() != seen || quit.load(); });
+          sleeping.fetch_sub(1);
+        }
+        cpu_relax();
+      }
+      if (quit.load()) return;
+      seen = e;
+      if (tid < host_threads) host_work();
+      pool_done.fetch_add(1, std::memory_order_acq_rel);
+    }
+  }
+
+  // Claims the next package for the host device from the level-1 dispenser
+  // (or the static plan). Only the host chain's claimer calls this.
+  bool host_claim(uint64_t* g0, uint64_t* g1) {
+    const SchedArgs& s = host_args;
+    if (s.kind == kStatic) {
+      if (s.st_nbands == 0) {
+        if (hq.st_next != 0 || s.st_begin >= s.st_end) return false;
+        *g0 = s.st_begin;
+        *g1 = s.st_end;
+      } else {
+        const uint64_t b = s.st_begin + hq.st_next;
+        if (b >= s.st_end) return false;
+        *g0 = band_edge(b, s.G, s.st_nbands);
+        *g1 = band_edge(b + 1, s.G, s.st_nbands);
+      }
+      hq.st_next++;
+      return true;
+    }
+    if (s.kind == kDynamic) {
+      const uint64_t a = __atomic_fetch_add(&l1->next, s.pkg, __ATOMIC_RELAXED);
+      if (a >= s.G) return false;
+      *g0 = a;
+      *g1 = std::min(a + s.pkg, s.G);
+      return true;
+    }
+    uint64_t cur = __atomic_load_n(&l1->next, __ATOMIC_ACQUIRE);
+    for (;;) {
+      if (cur >= s.G) return false;
+      const uint64_t sz = hguided_size(s.G - cur, s.P_self, s.sumP, s.n_dev, s.k, s.min_self);
+      if (__atomic_compare_exchange_n(&l1->next, &cur, cur + sz, false, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE)) {
+        *g0 = cur;
+        *g1 = cur + sz;
+        return true;
+      }
+    }
+  }
+
+  void host_tile(const HostPkg& p, uint32_t ti) {
+    switch (kernel_id) {
+      case CE_KERNEL_ESCAPE: hp->escape_rows(esc, p.g0 + ti, p.g0 + ti + 1, (uint32_t*)host_out); break;
+      case CE_KERNEL_BLUR5:
+        hp->blur5_rows((const float*)host_in0, blur.w, blur.h, (const float*)host_in1, p.g0 + ti, p.g0 + ti + 1,
+                       (float*)host_out);
+        break;
+      case CE_KERNEL_NBODY_ACC: {
+        const uint64_t i0 = p.g0 * kNbodyGranule + (uint64_t)ti * kHostNbodyTile;
+        const uint64_t end = std::min<uint64_t>(p.g1 * kNbodyGranule, nb.n);
+        const uint64_t i1 = std::min<uint64_t>(i0 + kHostNbodyTile, end);
+        hp->nbody_bodies((const float*)host_in0, nb.n, nb.eps2, (int)nb.strict, i0, i1, (float*)host_out);
+        break;
+      }
+    }
+  }
+
+  // Host side of a run: every pool thread (and the caller) runs this loop.
+  void host_work() {
+    uint32_t p_cache = 0;
+    for (;;) {
+      const uint64_t t = hq.ticket.fetch_add(1, std::memory_order_acq_rel);
+      bool have = false;
+      for (;;) {
+        const uint64_t tot = hq.total.load(std::memory_order_acquire);
+        if (t < tot) {
+          have = true;
+          break;
+        }
+        if (hq.done.load(std::memory_order_acquire)) break;
+        if (t == tot) {
+          uint64_t g0 = 0, g1 = 0;
+          const int64_t tc = now_ns();
+          if (hq.n_pkgs >= hq.cap || !host_claim(&g0, &g1)) {
+            if (hq.n_pkgs >= hq.cap) host_error.store(1);
+            hq.done.store(1, std::memory_order_release);
+            break;
+          }
+          HostPkg& p = hq.pkgs[hq.n_pkgs];
+          p.g0 = g0;
+          p.g1 = g1;
+          p.base = tot;
+          p.ntiles = host_tiles(g0, g1);
+          p.tiles_done.store(0, std::memory_order_relaxed);
+          p.t_claim = tc;
+          p.t_end.store(0, std::memory_order_relaxed);
+          hq.n_pkgs++;
+          hq.granules += g1 - g0;
+          hq.total.store(tot + p.ntiles, std::memory_order_release);
+          have = true;
+          break;
+        }
+        cpu_relax();
+      }
+      if (!have) return;
+      uint32_t p = p_cache;
+      while (t >= hq.pkgs[p].base + hq.pkgs[p].ntiles) ++p;
+      p_cache = p;
+      HostPkg& pk = hq.pkgs[p];
+      host_tile(pk, (uint32_t)(t - pk.base));
+      if (pk.tiles_done.fetch_add(1, std::memory_order_acq_rel) + 1 == pk.ntiles)
+        pk.t_end.store(now_ns(), std::memory_order_release);
+    }
+  }
+
+  ce_status ensure_pool() {
+    const int want = std::max(0, host_threads - 1);  // the caller is worker 0
+    if ((int)pool.size() == want) return CE_OK;
+    pool_stop();
+    pool_start(want);
+    return CE_OK;
+  }
+
+  // ------------------------------------------------------------ scheduler
+  ce_status build_sched(uint64_t G, SchedArgs* gpu_s, SchedArgs* host_s, uint32_t grid, size_t* gpu_max,
+                        size_t* host_max) {
+    const uint32_t n = n_devices();
+    const int gi = gpu_index(), hi = host_index();
+    SchedArgs base{};
+    base.kind = (uint32_t)sched.kind;
+    base.n_dev = n;
+    base.k = sched.k ? sched.k : 2;
+    base.G = G;
+    base.run_id = run_id;
+    base.spin_limit = 1ull << 26;
+    base.l1 = l1_dev;
+    base.l2 = l2;
+    *gpu_s = base;
+    *host_s = base;
+    host_s->l1 = l1;
+    *gpu_max = 1;
+    *host_max = 1;
+    if (sched.kind == CE_SCHED_STATIC) {
+      double props[CE_MAX_DEVICES] = {0, 0};
+      for (uint32_t d = 0; d + 1 < n; ++d) props[d] = sched.props[d];
+      uint32_t order[CE_MAX_DEVICES];
+      if (n == 2) {
+        order[0] = sched.order == CE_ORDER_GPU_FIRST ? (uint32_t)gi : (uint32_t)hi;
+        order[1] = sched.order == CE_ORDER_GPU_FIRST ? (uint32_t)hi : (uint32_t)gi;
+      } else {
+        order[0] = 0;
+      }
+      uint64_t b[CE_MAX_DEVICES], e[CE_MAX_DEVICES];
+      const uint32_t nb = sched.n_packages;
+      if (ce_sched_static_plan(G, n, props, order, nb, b, e) != CE_OK)
+        return fail(CE_E_INVALID, "static plan: invalid proportions or band count");
+      auto fill = [&](SchedArgs* s, int d) {
+        s->st_nbands = nb;
+        if (nb == 0) {
+          s->st_begin = b[d];
+          s->st_end = e[d];
+        } else {
+          // first band index and one past the last band of this device
+          uint64_t bb = 0, be = 0;
+          for (uint64_t k = 0; k <= nb; ++k) {
+            if (band_edge(k, G, nb) == b[d]) { bb = k; break; }
+          }
+          for (uint64_t k = bb; k <= nb; ++k) {
+            if (band_edge(k, G, nb) == e[d]) { be = k; break; }
+          }
+          s->st_begin = bb;
+          s->st_end = be;
+        }
+      };
+      if (gi >= 0) fill(gpu_s, gi);
+      if (hi >= 0) fill(host_s, hi);
+      *gpu_max = *host_max = nb ? nb + 1 : 2;
+      return CE_OK;
+    }
+    if (sched.kind == CE_SCHED_DYNAMIC) {
+      uint64_t pkg = sched.package_granules;
+      if (pkg == 0) {
+        if (sched.n_packages == 0) return fail(CE_E_INVALID, "dynamic: package_granules or n_packages required");
+        pkg = ceil_div(G, sched.n_packages);
+      }
+      gpu_s->pkg = host_s->pkg = pkg;
+      *gpu_max = *host_max = ceil_div(G, pkg) + 1;
+      if (gi >= 0 && gpu_tiles(kargs, 0, std::min(pkg, G)) == 1) gpu_s->direct = 1;
+      return CE_OK;
+    }
+    if (sched.kind == CE_SCHED_HGUIDED) {
+      uint64_t P[CE_MAX_DEVICES];
+      uint64_t sumP = 0;
+      for (uint32_t d = 0; d < n; ++d) {
+        P[d] = sched.power[d];
+        if (P[d] == 0 || P[d] > (1ull << 20)) return fail(CE_E_INVALID, "hguided: power[%u] must be in [1, 2^20]", d);
+        sumP += P[d];
+      }
+      if (G >= (1ull << 40)) return fail(CE_E_INVALID, "hguided: index space too large");
+      auto fill = [&](SchedArgs* s, int d, uint64_t def_min) {
+        s->P_self = P[d];
+        s->sumP = sumP;
+        s->min_self = sched.min_granules[d] ? sched.min_granules[d] : def_min;
+      };
+      if (gi >= 0) {
+        // default minimum: one tile for every resident workgroup
+        const uint32_t tiles_per_g = std::max<uint32_t>(1, gpu_tiles(kargs, 0, 1));
+        uint64_t rows_per_tile = 1;
+        while (rows_per_tile < G && gpu_tiles(kargs, 0, rows_per_tile + 1) == tiles_per_g) ++rows_per_tile;
+        const uint64_t def = std::max<uint64_t>(1, ceil_div((uint64_t)grid, tiles_per_g) * rows_per_tile);
+        fill(gpu_s, gi, std::min<uint64_t>(def, G));
+        *gpu_max = G / std::max<uint64_t>(1, gpu_s->min_self) + 2;
+      }
+      if (hi >= 0) {
+        fill(host_s, hi, 1);
+        *host_max = G / std::max<uint64_t>(1, host_s->min_self) + 2;
+      }
+      return CE_OK;
+    }
+    return fail(CE_E_INVALID, "unknown scheduler kind %d", sched.kind);
+  }
+
+  // ------------------------------------------------------------ run
+  ce_status run() {
+    if (kernel_id == 0) return fail(CE_E_STATE, "run: no kernel bound");
+    if (!sched_set) return fail(CE_E_STATE, "run: no scheduler set");
+    if (ndim == 0) return fail(CE_E_STATE, "run: work_items not set");
+    if (n_devices() == 0) return fail(CE_E_STATE, "run: empty device set");
+    if (use_host() && !hp) return fail(CE_E_UNSUPPORTED, "run: host CPU lacks AVX2/FMA");
+    // index space must match the kernel
+    if (kernel_id == CE_KERNEL_NBODY_ACC) {
+      if (ndim != 1 || gws[0] != nb.n || lws0 != kNbodyGranule)
+        return fail(CE_E_INVALID, "run: n-body needs a 1-D space of n items with lws 256");
+    } else {
+      const uint64_t w = kernel_id == CE_KERNEL_ESCAPE ? esc.w : blur.w;
+      const uint64_t h = kernel_id == CE_KERNEL_ESCAPE ? esc.h : blur.h;
+      if (ndim != 2 || gws[0] != w || gws[1] != h) return fail(CE_E_INVALID, "run: 2-D space must be w x h");
+    }
+    for (int s = 0; s < n_in_slots(); ++s)
+      if (!in[s].bound) return fail(CE_E_STATE, "run: input slot %d not bound", s);
+    if (!out[0].bound) return fail(CE_E_STATE, "run: output slot 0 not bound");
+
+    const uint64_t G = granules();
+    ++run_id;
+    stats_valid = false;
+    trace.clear();
+    hipError_t he;
+
+    // GPU-side pointers
+    kargs = KernelArgs{};
+    kargs.kernel_id = kernel_id;
+    kargs.strict = nb.strict;
+    kargs.esc = esc;
+    kargs.blur = blur;
+    kargs.nb = nb;
+    const void* gin[kMaxSlots] = {nullptr, nullptr};
+    if (use_gpu()) {
+      for (int s = 0; s < n_in_slots(); ++s) {
+        if (in[s].dev) {
+          gin[s] = in[s].dev;
+        } else {
+          if (!in_dev[s].ensure(in[s].bytes)) return fail(CE_E_NOMEM, "run: device staging for input %d", s);
+          if ((he = hipMemcpyAsync(in_dev[s].p, in[s].host, in[s].bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
+            return hip_fail(he, "run: input upload");
+          gin[s] = in_dev[s].p;
+        }
+      }
+    }
+    kargs.in0 = gin[0];
+    kargs.in1 = gin[1];
+    void* gpu_out = out[0].dev_out;
+    if (use_gpu() && !gpu_out) {
+      if (!out_dev_scratch.ensure(out[0].bytes)) return fail(CE_E_NOMEM, "run: device output scratch");
+      gpu_out = out_dev_scratch.p;
+    }
+    kargs.out = gpu_out;
+
+    // host-side pointers
+    host_in0 = host_in1 = nullptr;
+    host_out = nullptr;
+    if (use_host()) {
+      const void* hin[kMaxSlots] = {nullptr, nullptr};
+      for (int s = 0; s < n_in_slots(); ++s) {
+        if (in[s].host) {
+          hin[s] = in[s].host;
+        } else {
+          if (!in_host[s].ensure(in[s].bytes)) return fail(CE_E_NOMEM, "run: host staging for input %d", s);
+          if ((he = hipMemcpyAsync(in_host[s].p, in[s].dev, in[s].bytes, hipMemcpyDeviceToHost, stream)) != hipSuccess)
+            return hip_fail(he, "run: input download");
+          hin[s] = in_host[s].p;
+        }
+      }
+      host_in0 = hin[0];
+      host_in1 = hin[1];
+      host_out = out[0].host_out;
+      if (!host_out) {
+        if (!out_host_scratch.ensure(out[0].bytes)) return fail(CE_E_NOMEM, "run: host output scratch");
+        host_out = out_host_scratch.p;
+      }
+      bool downloaded = false;
+      for (int s = 0; s < n_in_slots(); ++s) downloaded |= (in[s].host == nullptr);
+      if (downloaded) {
+        if ((he = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(he, "run: input download");
+      }
+    }
+
+    // persistent grid
+    uint32_t grid = 0;
+    if (use_gpu()) {
+      int bpc = 0;
+      if ((he = persistent_blocks_per_cu(kargs, &bpc)) != hipSuccess) return hip_fail(he, "run: occupancy");
+      grid = (uint32_t)std::max(1, bpc) * (uint32_t)n_cu;
+      const uint32_t all_tiles = gpu_tiles(kargs, 0, G);
+      if (all_tiles > 0 && grid > all_tiles) grid = all_tiles;
+      if (grid == 0) grid = 1;
+    }
+
+    SchedArgs gs{}, hs{};
+    size_t gmax = 0, hmax = 0;
+    ce_status st = build_sched(G, &gs, &hs, grid, &gmax, &hmax);
+    if (st != CE_OK) return st;
+    host_args = hs;
+    if (use_gpu()) {
+      if (gmax > pkgs_dev_cap) {
+        if (!pkgs_dev.ensure(gmax * sizeof(PkgSlot))) return fail(CE_E_NOMEM, "run: package table");
+        pkgs_dev_cap = (uint32_t)gmax;
+      }
+      gs.pkgs = (PkgSlot*)pkgs_dev.p;
+      gs.max_pkgs = pkgs_dev_cap;
+    }
+    if (use_host()) {
+      if (!hq.ensure(hmax)) return fail(CE_E_NOMEM, "run: host package table");
+    }
+    hq.reset();
+    host_error.store(0);
+
+    // arm the level-1 dispenser
+    __atomic_store_n(&l1->next, 0, __ATOMIC_RELAXED);
+    __atomic_store_n(&l1->gpu_flags, 0, __ATOMIC_RELAXED);
+    __atomic_thread_fence(__ATOMIC_SEQ_CST);
+
+    t0_ns = now_ns();
+    if (use_gpu()) {
+      if (ev_start && (he = hipEventRecord(ev_start, stream)) != hipSuccess) return hip_fail(he, "run: event");
+      if ((he = launch_persistent(kargs, gs, grid, stream)) != hipSuccess) return hip_fail(he, "run: kernel launch");
+      if (ev_stop && (he = hipEventRecord(ev_stop, stream)) != hipSuccess) return hip_fail(he, "run: event");
+    }
+    gpu_grid_last = grid;
+    if (use_host()) {
+      ensure_pool();
+      pool_done.store(0, std::memory_order_relaxed);
+      epoch.fetch_add(1);  // seq_cst pairs with the sleepers' counter
+      if (sleeping.load() > 0) {
+        std::lock_guard<std::mutex> lk(mu);
+        cv.notify_all();
+      }
+      host_work();
+      const uint32_t want = (uint32_t)pool.size();
+      while (pool_done.load(std::memory_order_acquire) < want) cpu_relax();
+    }
+    if (use_gpu()) {
+      // the last workgroup out writes the run id; poll it, then sync
+      const int64_t deadline = now_ns() + 120'000'000'000LL;
+      while (__atomic_load_n(&l1->gpu_run_id, __ATOMIC_ACQUIRE) != run_id) {
+        if (now_ns() > deadline) break;
+        cpu_relax();
+      }
+      if ((he = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(he, "run: kernel");
+      if (__atomic_load_n(&l1->gpu_run_id, __ATOMIC_ACQUIRE) != run_id)
+        return fail(CE_E_TIMEOUT, "run: GPU did not report completion");
+      if (__atomic_load_n(&l1->gpu_flags, __ATOMIC_ACQUIRE))
+        return fail(CE_E_TIMEOUT, "run: GPU dispenser wait exceeded its bound or package table overflow");
+    }
+    if (host_error.load()) return fail(CE_E_DEVICE, "run: host package table overflow");
+
+    // merge outputs so each bound pointer holds the whole result
+    st = merge_outputs(gpu_out);
+    if (st != CE_OK) return st;
+    const int64_t t_end = now_ns();
+    fill_stats(G, t_end);
+    return CE_OK;
+  }
+
+  // Host packages sorted into maximal intervals.
+  std::vector<std::pair<uint64_t, uint64_t>> host_intervals() const {
+    std::vector<std::pair<uint64_t, uint64_t>> v;
+    for (uint32_t i = 0; i < hq.n_pkgs; ++i) v.emplace_back(hq.pkgs[i].g0, hq.pkgs[i].g1);
+    std::sort(v.begin(), v.end());
+    std::vector<std::pair<uint64_t, uint64_t>> m;
+    for (auto& iv : v) {
+      if (!m.empty() && m.back().second == iv.first)
+        m.back().second = iv.second;
+      else
+        m.push_back(iv);
+    }
+    return m;
+  }
+
+  ce_status merge_outputs(void* gpu_out) {
+    hipError_t he;
+    const size_t eb = out_elem_bytes();
+    const uint64_t G = granules();
+    auto bytes_of = [&](uint64_t g0, uint64_t g1, size_t* off, size_t* len) {
+      *off = (size_t)item_offset(g0) * eb;
+      *len = (size_t)(item_offset(g1) - item_offset(g0)) * eb;
+    };
+    const auto hiv = use_host() ? host_intervals() : std::vector<std::pair<uint64_t, uint64_t>>{};
+    bool issued = false;
+    // host-computed ranges into the device output
+    if (use_host() && out[0].dev_out) {
+      for (auto& iv : hiv) {
+        size_t off, len;
+        bytes_of(iv.first, iv.second, &off, &len);
+        if (!len) continue;
+        if ((he = hipMemcpyAsync((char*)out[0].dev_out + off, (const char*)host_out + off, len,
+                                 hipMemcpyHostToDevice, stream)) != hipSuccess)
+          return hip_fail(he, "merge: host ranges to device");
+        issued = true;
+      }
+    }
+    // GPU-computed ranges (the complement of the host's) into the host output
+    if (use_gpu() && out[0].host_out) {
+      uint64_t cur = 0;
+      auto copy = [&](uint64_t a, uint64_t b) -> ce_status {
+        size_t off, len;
+        bytes_of(a, b, &off, &len);
+        if (!len) return CE_OK;
+        hipError_t e2 = hipMemcpyAsync((char*)out[0].host_out + off, (const char*)gpu_out + off, len,
+                                       hipMemcpyDeviceToHost, stream);
+        if (e2 != hipSuccess) return hip_fail(e2, "merge: device ranges to host");
+        issued = true;
+        return CE_OK;
+      };
+      for (auto& iv : hiv) {
+        if (iv.first > cur) {
+          ce_status s = copy(cur, iv.first);
+          if (s != CE_OK) return s;
+        }
+        cur = iv.second;
+      }
+      if (cur < G) {
+        ce_status s = copy(cur, G);
+        if (s != CE_OK) return s;
+      }
+    }
+    // host output came from a scratch buffer while the caller gave a host pointer: impossible
+    // (host workers write into out.host when given). Device output scratch with a dev pointer: impossible.
+    if (issued) {
+      if ((he = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(he, "merge: sync");
+    }
+    return CE_OK;
+  }
+
+  void fill_stats(uint64_t G, int64_t t_end) {
+    ce_run_stats s{};
+    s.t_run = (double)(t_end - t0_ns) * 1e-9;
+    s.n_devices = n_devices();
+    s.total_granules = G;
+    s.gpu_workgroups = use_gpu() ? gpu_grid_last : 0;
+    s.host_threads = use_host() ? (uint32_t)host_threads : 0;
+    const int gi = gpu_index(), hi = host_index();
+    uint64_t host_items = 0;
+    if (gi >= 0) {
+      s.device_kind[gi] = CE_DEV_GPU;
+      const uint64_t np = __atomic_load_n(&l1->gpu_packages, __ATOMIC_ACQUIRE);
+      const uint64_t gr = __atomic_load_n(&l1->gpu_granules, __ATOMIC_ACQUIRE);
+      const uint64_t tf = __atomic_load_n(&l1->gpu_t_first, __ATOMIC_ACQUIRE);
+      const uint64_t tl = __atomic_load_n(&l1->gpu_t_last, __ATOMIC_ACQUIRE);
+      s.packages[gi] = np;
+      s.granules[gi] = gr;
+      s.t_device[gi] = np ? std::max(0.0, tick_to_host_s(tl)) : 0.0;
+      s.t_gpu_kernel = np ? (double)(tl - tf) / (double)wallclock_hz : 0.0;
+      gpu_pkgs_last = np;
+    }
+    if (hi >= 0) {
+      s.device_kind[hi] = CE_DEV_HOST;
+      s.packages[hi] = hq.n_pkgs;
+      s.granules[hi] = hq.granules;
+      int64_t last = 0;
+      for (uint32_t i = 0; i < hq.n_pkgs; ++i) {
+        last = std::max(last, hq.pkgs[i].t_end.load());
+        host_items += items_in(hq.pkgs[i].g0, hq.pkgs[i].g1);
+      }
+      s.t_device[hi] = hq.n_pkgs ? (double)(last - t0_ns) * 1e-9 : 0.0;
+      s.items[hi] = host_items;
+    }
+    s.total_items = items_in(0, G);
+    if (gi >= 0) s.items[gi] = s.total_items - host_items;
+    double mn = 1e300, mx = 0.0;
+    for (uint32_t d = 0; d < s.n_devices; ++d) {
+      mn = std::min(mn, s.t_device[d]);
+      mx = std::max(mx, s.t_device[d]);
+    }
+    s.balance = mx > 0.0 ? mn / mx : 0.0;
+    stats = s;
+    stats_valid = true;
+  }
+
+  size_t build_trace() {
+    trace.clear();
+    const int gi = gpu_index(), hi = host_index();
+    if (gi >= 0 && gpu_pkgs_last) {
+      std::vector<PkgSlot> v(std::min<uint64_t>(gpu_pkgs_last, pkgs_dev_cap));
+      if (hipMemcpy(v.data(), pkgs_dev.p, v.size() * sizeof(PkgSlot), hipMemcpyDeviceToHost) == hipSuccess) {
+        for (auto& p : v)
+          trace.push_back(ce_package_rec{(uint32_t)gi, 0, p.g0, p.g1, tick_to_host_s(p.t_claim), tick_to_host_s(p.t_end)});
+      }
+    }
+    if (hi >= 0) {
+      for (uint32_t i = 0; i < hq.n_pkgs; ++i) {
+        const HostPkg& p = hq.pkgs[i];
+        trace.push_back(ce_package_rec{(uint32_t)hi, 0, p.g0, p.g1, (double)(p.t_claim - t0_ns) * 1e-9,
+                                       (double)(p.t_end.load() - t0_ns) * 1e-9});
+      }
+    }
+    return trace.size();
+  }
+
+  // ------------------------------------------------------------ init
+  ce_status init() {
+    hipError_t he;
+    int count = 0;
+    if ((he = hipGetDeviceCount(&count)) != hipSuccess || count <= 0)
+      return fail(CE_E_DEVICE, "create: no HIP device (%s)", hipGetErrorString(he));
+    if ((he = hipGetDevice(&gpu)) != hipSuccess) return hip_fail(he, "create: hipGetDevice");
+    hipDeviceProp_t prop;
+    if ((he = hipGetDeviceProperties(&prop, gpu)) != hipSuccess) return hip_fail(he, "create: properties");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      return fail(CE_E_DEVICE, "create: GPU %s is not gfx950", prop.gcnArchName);
+    n_cu = prop.multiProcessorCount;
+    int clk = 0;
+    if (hipDeviceGetAttribute(&clk, hipDeviceAttributeWallClockRate, gpu) == hipSuccess && clk > 0)
+      wallclock_hz = (uint32_t)clk * 1000u;
+    if ((he = hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(he, "create: stream");
+    stream = own_stream;
+    void* p = nullptr;
+    if ((he = hipHostMalloc(&p, sizeof(L1State), hipHostMallocCoherent | hipHostMallocMapped)) != hipSuccess)
+      return hip_fail(he, "create: coherent host memory");
+    l1 = (L1State*)p;
+    memset(l1, 0, sizeof(L1State));
+    if ((he = hipHostGetDevicePointer((void**)&l1_dev, l1, 0)) != hipSuccess)
+      return hip_fail(he, "create: device view of host memory");
+    if ((he = hipMalloc((void**)&l2, sizeof(L2State))) != hipSuccess) return hip_fail(he, "create: queue state");
+    if ((he = hipMemset(l2, 0, sizeof(L2State))) != hipSuccess) return hip_fail(he, "create: queue state");
+    hp = host_payloads();
+    host_threads = (int)std::max(1u, std::thread::hardware_concurrency());
+    calibrate_clock();
+    return CE_OK;
+  }
+
+  // GPU tick -> host clock: the GPU answers pings through host-coherent
+  // memory; the round trip with the smallest latency gives the offset.
+  void calibrate_clock() {
+    const uint32_t rounds = 64;
+    __atomic_store_n(&l1->ping, 0, __ATOMIC_RELEASE);
+    __atomic_store_n(&l1->pong, 0, __ATOMIC_RELEASE);
+    if (launch_calibrate(l1_dev, rounds, 1ull << 24, stream) != hipSuccess) return;
+    double best_rt = 1e300, best_off = 0.0;
+    bool ok = true;
+    for (uint32_t i = 1; i <= rounds && ok; ++i) {
+      const int64_t ta = now_ns();
+      __atomic_store_n(&l1->ping, (uint64_t)i, __ATOMIC_RELEASE);
+      for (;;) {
+        if (__atomic_load_n(&l1->pong, __ATOMIC_ACQUIRE) == i) break;
+        if (now_ns() - ta > 2'000'000'000LL) {
+          ok = false;
+          break;
+        }
+        cpu_relax();
+      }
+      const int64_t tb = now_ns();
+      if (!ok) break;
+      const uint64_t tick = __atomic_load_n(&l1->tick, __ATOMIC_ACQUIRE);
+      const double rt = (double)(tb - ta);
+      if (rt < best_rt) {
+        best_rt = rt;
+        best_off = 0.5 * (double)(ta + tb) - (double)tick * (1e9 / (double)wallclock_hz);
+      }
+    }
+    // unblock the kernel if the host gave up early
+    __atomic_store_n(&l1->ping, 0xFFFFFFFFull, __ATOMIC_RELEASE);
+    (void)hipStreamSynchronize(stream);
+    clock_ok = ok;
+    if (ok) clock_offset_ns = best_off;
+    else errors.emplace_back("create: GPU clock calibration failed; GPU times are unmapped");
+  }
+
+  ~ce_engine() {
+    pool_stop();
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (own_stream) (void)hipStreamDestroy(own_stream);
+    if (l2) (void)hipFree(l2);
+    if (l1) (void)hipHostFree(l1);
+  }
+};
+
+// =================================================================== C ABI
+extern "C" {
+
+ce_status ce_engine_create(ce_engine** out) {
+  if (!out) return CE_E_INVALID;
+  *out = nullptr;
+  try {
+    ce_engine* e = new ce_engine();
+    ce_status st = e->init();
+    if (st != CE_OK) {
+      delete e;
+      return st;
+    }
+    *out = e;
+    return CE_OK;
+  } catch (...) {
+    return CE_E_NOMEM;
+  }
+}
+
+void ce_engine_destroy(ce_engine* e) { delete e; }
+
+ce_status ce_engine_use(ce_engine* e, uint32_t dev_mask, int gpu_ordinal, int host_threads) {
+  if (!e) return CE_E_INVALID;
+  if (dev_mask == 0 || (dev_mask & ~(CE_DEV_GPU | CE_DEV_HOST)))
+    return e->fail(CE_E_INVALID, "use: device mask 0x%x", dev_mask);
+  if ((dev_mask & CE_DEV_GPU) && gpu_ordinal != e->gpu)
+    return e->fail(CE_E_INVALID, "use: GPU ordinal %d is not the engine's GPU %d", gpu_ordinal, e->gpu);
+  if ((dev_mask & CE_DEV_HOST) && !e->hp) return e->fail(CE_E_UNSUPPORTED, "use: host CPU lacks AVX2/FMA");
+  e->dev_mask = dev_mask;
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  e->host_threads = host_threads <= 0 ? hw : std::min(host_threads, 1024);
+  return CE_OK;
+}
+
+ce_status ce_engine_work_items(ce_engine* e, uint32_t ndim, const uint64_t* gws, const uint32_t* lws) {
+  if (!e) return CE_E_INVALID;
+  if (ndim < 1 || ndim > 2 || !gws) return e->fail(CE_E_INVALID, "work_items: ndim must be 1 or 2");
+  for (uint32_t d = 0; d < ndim; ++d)
+    if (gws[d] == 0 || gws[d] > 0xFFFFFFFFull) return e->fail(CE_E_INVALID, "work_items: gws[%u] out of range", d);
+  e->ndim = ndim;
+  e->gws[0] = gws[0];
+  e->gws[1] = ndim > 1 ? gws[1] : 1;
+  e->lws0 = (lws && lws[0]) ? lws[0] : 256;
+  return CE_OK;
+}
+
+ce_status ce_engine_scheduler(ce_engine* e, const ce_sched_desc* s) {
+  if (!e) return CE_E_INVALID;
+  if (!s) return e->fail(CE_E_INVALID, "scheduler: NULL descriptor");
+  if (s->kind < CE_SCHED_STATIC || s->kind > CE_SCHED_HGUIDED)
+    return e->fail(CE_E_INVALID, "scheduler: unknown kind %d", s->kind);
+  if (s->order != CE_ORDER_HOST_FIRST && s->order != CE_ORDER_GPU_FIRST)
+    return e->fail(CE_E_INVALID, "scheduler: unknown order %d", s->order);
+  if (s->n_packages > (1u << 20)) return e->fail(CE_E_INVALID, "scheduler: too many packages");
+  e->sched = *s;
+  e->sched_set = true;
+  return CE_OK;
+}
+
+ce_status ce_engine_stream(ce_engine* e, void* hip_stream) {
+  if (!e) return CE_E_INVALID;
+  e->stream = hip_stream ? (hipStream_t)hip_stream : e->own_stream;
+  return CE_OK;
+}
+
+ce_status ce_engine_kernel_events(ce_engine* e, void* start_event, void* stop_event) {
+  if (!e) return CE_E_INVALID;
+  if ((start_event == nullptr) != (stop_event == nullptr))
+    return e->fail(CE_E_INVALID, "kernel_events: give both events or neither");
+  e->ev_start = (hipEvent_t)start_event;
+  e->ev_stop = (hipEvent_t)stop_event;
+  return CE_OK;
+}
+
+ce_status ce_program_kernel(ce_engine* e, int kernel_id, const void* params, size_t params_size) {
+  if (!e) return CE_E_INVALID;
+  if (!params) return e->fail(CE_E_INVALID, "kernel: NULL params");
+  switch (kernel_id) {
+    case CE_KERNEL_ESCAPE: {
+      if (params_size != sizeof(ce_escape_params)) return e->fail(CE_E_INVALID, "kernel: escape params size");
+      ce_escape_params p;
+      memcpy(&p, params, sizeof p);
+      if (p.w == 0 || p.h == 0) return e->fail(CE_E_INVALID, "kernel: empty escape grid");
+      e->esc = p;
+      break;
+    }
+    case CE_KERNEL_BLUR5: {
+      if (params_size != sizeof(ce_blur5_params)) return e->fail(CE_E_INVALID, "kernel: blur params size");
+      ce_blur5_params p;
+      memcpy(&p, params, sizeof p);
+      if (p.w == 0 || p.h == 0) return e->fail(CE_E_INVALID, "kernel: empty image");
+      e->blur = p;
+      break;
+    }
+    case CE_KERNEL_NBODY_ACC: {
+      if (params_size != sizeof(ce_nbody_params)) return e->fail(CE_E_INVALID, "kernel: n-body params size");
+      ce_nbody_params p;
+      memcpy(&p, params, sizeof p);
+      if (p.n == 0) return e->fail(CE_E_INVALID, "kernel: no bodies");
+      if (!(p.eps2 >= 1.17549435e-38f) || !std::isfinite(p.eps2))
+        return e->fail(CE_E_INVALID, "kernel: eps2 must be a positive normal float");
+      e->nb = p;
+      break;
+    }
+    default: return e->fail(CE_E_INVALID, "kernel: unknown kernel id %d", kernel_id);
+  }
+  e->kernel_id = kernel_id;
+  for (auto& b : e->in) b = Binding{};
+  e->out[0] = Binding{};
+  return CE_OK;
+}
+
+ce_status ce_program_in(ce_engine* e, uint32_t slot, const void* host_ptr, const void* dev_ptr, size_t bytes) {
+  if (!e) return CE_E_INVALID;
+  if (e->kernel_id == 0) return e->fail(CE_E_STATE, "in: bind a kernel first");
+  if ((int)slot >= e->n_in_slots()) return e->fail(CE_E_INVALID, "in: kernel has no input slot %u", slot);
+  if (!host_ptr && !dev_ptr) return e->fail(CE_E_INVALID, "in: slot %u needs a host or device pointer", slot);
+  if (bytes != e->in_bytes((int)slot))
+    return e->fail(CE_E_INVALID, "in: slot %u expects %zu bytes, got %zu", slot, e->in_bytes((int)slot), bytes);
+  e->in[slot] = Binding{host_ptr, dev_ptr, nullptr, nullptr, bytes, true};
+  return CE_OK;
+}
+
+ce_status ce_program_out(ce_engine* e, uint32_t slot, void* host_ptr, void* dev_ptr, size_t bytes) {
+  if (!e) return CE_E_INVALID;
+  if (e->kernel_id == 0) return e->fail(CE_E_STATE, "out: bind a kernel first");
+  if (slot != 0) return e->fail(CE_E_INVALID, "out: kernel has one output slot");
+  if (!host_ptr && !dev_ptr) return e->fail(CE_E_INVALID, "out: needs a host or device pointer");
+  if (bytes != e->out_bytes()) return e->fail(CE_E_INVALID, "out: expects %zu bytes, got %zu", e->out_bytes(), bytes);
+  e->out[0] = Binding{nullptr, nullptr, host_ptr, dev_ptr, bytes, true};
+  return CE_OK;
+}
+
+ce_status ce_program_out_pattern(ce_engine* e, uint32_t outs, uint32_t items) {
+  if (!e) return CE_E_INVALID;
+  if (outs == 0 || items == 0) return e->fail(CE_E_INVALID, "out_pattern: zero term");
+  if (outs != items) return e->fail(CE_E_UNSUPPORTED, "out_pattern: only 1:1 payloads are built");
+  e->pat_outs = 1;
+  e->pat_items = 1;
+  return CE_OK;
+}
+
+ce_status ce_engine_run(ce_engine* e) {
+  if (!e) return CE_E_INVALID;
+  try {
+    return e->run();
+  } catch (const std::exception& ex) {
+    return e->fail(CE_E_NOMEM, "run: %s", ex.what());
+  } catch (...) {
+    return e->fail(CE_E_NOMEM, "run: unknown exception");
+  }
+}
+
+ce_status ce_engine_stats(const ce_engine* e, ce_run_stats* out) {
+  if (!e || !out) return CE_E_INVALID;
+  if (!e->stats_valid) return CE_E_STATE;
+  *out = e->stats;
+  return CE_OK;
+}
+
+size_t ce_engine_trace(const ce_engine* ce, ce_package_rec* buf, size_t cap) {
+  if (!ce) return 0;
+  ce_engine* e = const_cast<ce_engine*>(ce);
+  if (!e->stats_valid) return 0;
+  size_t n = 0;
+  try {
+    n = e->build_trace();
+  } catch (...) {
+    return 0;
+  }
+  if (buf)
+    for (size_t i = 0; i < std::min(n, cap); ++i) buf[i] = e->trace[i];
+  return n;
+}
+
+int ce_engine_has_errors(const ce_engine* e) { return e && !e->errors.empty(); }
+int ce_engine_error_count(const ce_engine* e) { return e ? (int)e->errors.size() : 0; }
+const char* ce_engine_error(const ce_engine* e, int i) {
+  if (!e || i < 0 || i >= (int)e->errors.size()) return nullptr;
+  return e->errors[(size_t)i].c_str();
+}
+void ce_engine_clear_errors(ce_engine* e) {
+  if (e) e->errors.clear();
+}
+
+ce_status ce_bare_run(int kernel_id, const void* params, size_t params_size, const void* const* ins, void* out,
+                      void* hip_stream, int sync) {
+  if (!params || !out) return CE_E_INVALID;
+  KernelArgs a{};
+  a.kernel_id = kernel_id;
+  switch (kernel_id) {
+    case CE_KERNEL_ESCAPE:
+      if (params_size != sizeof(ce_escape_params)) return CE_E_INVALID;
+      memcpy(&a.esc, params, sizeof a.esc);
+      if (a.esc.w == 0 || a.esc.h == 0) return CE_E_INVALID;
+      break;
+    case CE_KERNEL_BLUR5:
+      if (params_size != sizeof(ce_blur5_params) || !ins || !ins[0] || !ins[1]) return CE_E_INVALID;
+      memcpy(&a.blur, params, sizeof a.blur);
+      if (a.blur.w == 0 || a.blur.h == 0) return CE_E_INVALID;
+      a.in0 = ins[0];
+      a.in1 = ins[1];
+      break;
+    case CE_KERNEL_NBODY_ACC:
+      if (params_size != sizeof(ce_nbody_params) || !ins || !ins[0]) return CE_E_INVALID;
+      memcpy(&a.nb, params, sizeof a.nb);
+      if (a.nb.n == 0 || !(a.nb.eps2 >= 1.17549435e-38f)) return CE_E_INVALID;
+      a.strict = a.nb.strict;
+      a.in0 = ins[0];
+      break;
+    default: return CE_E_INVALID;
+  }
+  a.out = out;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return CE_E_DEVICE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (launch_bare(a, st) != hipSuccess) return CE_E_DEVICE;
+  if (sync && hipStreamSynchronize(st) != hipSuccess) return CE_E_DEVICE;
+  return CE_OK;
+}
+
+ce_status ce_sched_static_plan(uint64_t G, uint32_t n, const double* props, const uint32_t* order, uint32_t n_bands,
+                               uint64_t* begin, uint64_t* end) {
+  if (n == 0 || n > CE_MAX_DEVICES || !order || !begin || !end || (n > 1 && !props)) return CE_E_INVALID;
+  double share[CE_MAX_DEVICES];
+  double rest = 1.0;
+  for (uint32_t d = 0; d + 1 < n; ++d) {
+    if (!(props[d] >= 0.0) || props[d] > 1.0) return CE_E_INVALID;
+    share[d] = props[d];
+    rest -= props[d];
+  }
+  if (rest < -1e-12) return CE_E_INVALID;
+  share[n - 1] = rest < 0.0 ? 0.0 : rest;
+  bool seen[CE_MAX_DEVICES] = {false, false};
+  for (uint32_t k = 0; k < n; ++k) {
+    if (order[k] >= n || seen[order[k]]) return CE_E_INVALID;
+    seen[order[k]] = true;
+  }
+  if (n_bands == 0) {
+    double cum = 0.0;
+    uint64_t prev = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+      const uint32_t d = order[k];
+      cum += share[d];
+      uint64_t b = (k + 1 == n) ? G : (uint64_t)std::floor(cum * (double)G);
+      b = std::min(b, G);
+      b = std::max(b, prev);
+      begin[d] = prev;
+      end[d] = b;
+      prev = b;
+    }
+    return CE_OK;
+  }
+  if (n_bands < n || (uint64_t)n_bands > G) return CE_E_INVALID;
+  uint64_t nb[CE_MAX_DEVICES];
+  uint64_t used = 0;
+  for (uint32_t d = 0; d + 1 < n; ++d) {
+    const double r = std::floor(share[d] * (double)n_bands + 0.5);
+    const uint64_t want = r < 1.0 ? 1 : (uint64_t)r;
+    const uint64_t cap = n_bands - used - (n - 1 - d);
+    nb[d] = std::min(want, cap);
+    used += nb[d];
+  }
+  nb[n - 1] = n_bands - used;
+  uint64_t band = 0;
+  for (uint32_t k = 0; k < n; ++k) {
+    const uint32_t d = order[k];
+    begin[d] = band_edge(band, G, n_bands);
+    band += nb[d];
+    end[d] = band_edge(band, G, n_bands);
+  }
+  return CE_OK;
+}
+
+uint64_t ce_sched_hguided_size(uint64_t G_r, const uint64_t* power, uint32_t n, uint32_t k, uint32_t i,
+                               uint64_t min_i) {
+  if (!power || n == 0 || i >= n) return 0;
+  uint64_t sumP = 0;
+  for (uint32_t j = 0; j < n; ++j) sumP += power[j];
+  return hguided_size(G_r, power[i], sumP, n, k, min_i);
+}
+
+ce_status ce_gauss5_weights(double sigma, float* w25) {
+  if (!w25 || !(sigma > 0.0)) return CE_E_INVALID;
+  double e[25], sum = 0.0;
+  for (int dy = -2; dy <= 2; ++dy)
+    for (int dx = -2; dx <= 2; ++dx) {
+      const double v = std::exp(-(double)(dx * dx + dy * dy) / (2.0 * sigma * sigma));
+      e[(dy + 2) * 5 + dx + 2] = v;
+      sum += v;
+    }
+  for (int k = 0; k < 25; ++k) w25[k] = (float)(e[k] / sum);
+  return CE_OK;
+}
+
+const char* ce_version(void) { return "coexec-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

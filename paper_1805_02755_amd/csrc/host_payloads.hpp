@@ -1,0 +1,28 @@
+// Host-side payload workers. Each function computes a sub-range of the index
+// space with the same FP32 operation sequence per work-item as the GPU
+// kernels, so the bits do not depend on which device computed an item.
+#pragma once
+
+#include <stdint.h>
+
+#include "../../include/coexec.h"
+
+namespace ce {
+
+struct HostPayloadFns {
+  // rows [r0, r1) of the escape-time image; out is the image base
+  void (*escape_rows)(const ce_escape_params& p, uint64_t r0, uint64_t r1, uint32_t* out);
+  // rows [r0, r1) of the blurred image
+  void (*blur5_rows)(const float* in, uint32_t w, uint32_t h, const float* wt, uint64_t r0, uint64_t r1,
+                     float* out);
+  // bodies [i0, i1)
+  void (*nbody_bodies)(const float* pos4, uint32_t n, float eps2, int strict, uint64_t i0, uint64_t i1,
+                       float* out4);
+  const char* isa;
+};
+
+// Picks the widest instruction set the running CPU supports (AVX-512 or
+// AVX2+FMA); returns nullptr if the CPU lacks FMA.
+const HostPayloadFns* host_payloads();
+
+}  // namespace ce

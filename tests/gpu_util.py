@@ -1,0 +1,84 @@
+"""Helpers for the GPU tests: run one payload through the C ABI with a given
+device set, scheduler and buffer residency."""
+import numpy as np
+import torch
+
+import paper_1805_02755_amd as ce
+
+DEV = torch.device("cuda:0")
+BOTH = ce.CE_DEV_GPU | ce.CE_DEV_HOST
+
+SCHEDULES = {
+    "static": dict(kind=ce.CE_SCHED_STATIC, props=[0.75], order=ce.CE_ORDER_HOST_FIRST),
+    "static_rev": dict(kind=ce.CE_SCHED_STATIC, props=[0.75], order=ce.CE_ORDER_GPU_FIRST),
+    "static8": dict(kind=ce.CE_SCHED_STATIC, props=[0.875], order=ce.CE_ORDER_HOST_FIRST, n_packages=8),
+    "dynamic": dict(kind=ce.CE_SCHED_DYNAMIC, package_granules=4),
+    "dynamic50": dict(kind=ce.CE_SCHED_DYNAMIC, n_packages=50),
+    "hguided": dict(kind=ce.CE_SCHED_HGUIDED, power=[16, 1], k=2, min_granules=[8, 1]),
+    "hguided_default": dict(kind=ce.CE_SCHED_HGUIDED, power=[40, 1], k=2),
+}
+
+
+def _sched_for(name, devs):
+    s = dict(SCHEDULES[name])
+    if devs != BOTH:
+        # one device: drop the per-device arrays down to one entry
+        for key in ("props",):
+            s.pop(key, None)
+        for key in ("power", "min_granules"):
+            if key in s:
+                s[key] = s[key][:1]
+    return s
+
+
+def run_payload(eng, kernel_id, params, gws, lws, inputs, out_shape, out_dtype, devs, sched, mode="dev",
+                host_threads=0):
+    """inputs: list of numpy arrays. mode: 'dev' (device-resident in and out,
+    host mirror of inputs), 'host' (host pointers only), 'both' (everything
+    bound on both sides). Returns (output ndarray, stats, trace)."""
+    eng.use(devs, 0, host_threads)
+    eng.work_items(gws, lws)
+    eng.scheduler(**_sched_for(sched, devs))
+    eng.program_kernel(kernel_id, params)
+    keep = []
+    for slot, a in enumerate(inputs):
+        if mode == "host":
+            eng.program_in(slot, host=a)
+        else:
+            d = torch.from_numpy(a).to(DEV)
+            keep.append(d)
+            eng.program_in(slot, host=a, dev=d, nbytes=a.nbytes)
+    torch.cuda.synchronize()
+    out_h = np.full(out_shape, 0xFF, dtype=np.uint8).view(out_dtype) if mode in ("host", "both") else None
+    out_d = None
+    if mode in ("dev", "both"):
+        nbytes = int(np.prod(out_shape)) * np.dtype(out_dtype).itemsize
+        out_d = torch.full((nbytes,), 0xFF, dtype=torch.uint8, device=DEV)
+        torch.cuda.synchronize()
+    eng.program_out(0, host=out_h, dev=out_d,
+                    nbytes=(out_h.nbytes if out_h is not None else out_d.numel()))
+    eng.run()
+    st = eng.stats()
+    tr = eng.trace()
+    if mode == "host":
+        res = out_h
+    else:
+        res = out_d.cpu().numpy().view(out_dtype).reshape(out_shape)
+        if mode == "both":
+            assert np.array_equal(res.view(np.uint8), out_h.view(np.uint8)), "host and device copies differ"
+    del keep
+    return res, st, tr
+
+
+def check_trace(tr, G, n_dev):
+    """Packages of the trace cover [0, G) exactly once; devices are valid."""
+    cnt = np.zeros(G, dtype=np.int32)
+    for d, b, e, tc, te in tr:
+        assert 0 <= d < n_dev
+        assert 0 <= b < e <= G
+        cnt[b:e] += 1
+    assert np.all(cnt == 1), (int((cnt == 0).sum()), int((cnt > 1).sum()))
+
+
+def escape_params(p):
+    return ce.ce_escape_params(p.w, p.h, *p.as_f32(), p.max_iter)

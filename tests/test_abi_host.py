@@ -1,0 +1,87 @@
+"""CPU-only checks of the C ABI library: it loads, exports every symbol the
+header declares, and its host-side scheduler helpers agree with the oracle.
+No payload is computed here."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1805_02755_amd as ce
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "coexec.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ce_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ce.lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", ce.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    declared = _declared()
+    assert declared, "no declarations parsed"
+    missing = [s for s in declared if s not in exported]
+    assert not missing, missing
+    for s in declared:
+        assert hasattr(lib, s)
+    assert set(ce.EXPORTED_SYMBOLS) <= set(declared)
+
+
+def test_version_and_no_oracle_linkage():
+    assert "gfx950" in ce.ce_version()
+    out = subprocess.run(["nm", "-D", ce.LIB_PATH], capture_output=True, text=True).stdout
+    assert "orc_" not in out
+    ldd = subprocess.run(["ldd", ce.LIB_PATH], capture_output=True, text=True).stdout
+    assert "liboracle" not in ldd
+
+
+def test_static_plan_matches_oracle():
+    rng = np.random.default_rng(0)
+    for _ in range(300):
+        n = int(rng.integers(1, 3))
+        G = int(rng.integers(n, 20000))
+        props = list(rng.random(n - 1) * 0.999)
+        order = list(rng.permutation(n))
+        nb = int(rng.choice([0, 0, n, 8, 50]))
+        if nb > G:
+            nb = 0
+        assert ce.ce_sched_static_plan(G, props, order, nb) == O.static_plan(G, props, order, nb)
+
+
+def test_static_plan_listing_example():
+    # two-device form of the section 6.2 proportions: GPU 0.7, host the rest, host first
+    assert ce.ce_sched_static_plan(1000, [0.7], [1, 0]) == O.static_plan(1000, [0.7], [1, 0]) == [(300, 1000), (0, 300)]
+    assert ce.ce_sched_static_plan(1000, [1.5], [0, 1]) is None
+
+
+def test_hguided_size_matches_oracle():
+    rng = np.random.default_rng(1)
+    for _ in range(2000):
+        n = int(rng.integers(1, 3))
+        P = [int(x) for x in rng.integers(1, 1 << 20, n)]
+        G_r = int(rng.integers(0, 1 << 39))
+        k = int(rng.integers(1, 8))
+        i = int(rng.integers(0, n))
+        m = int(rng.integers(0, 1000))
+        assert ce.ce_sched_hguided_size(G_r, P, k, i, m) == O.hguided_size(G_r, P, k, i, m)
+
+
+def test_gauss_weights_match_oracle_bitwise():
+    for sigma in (0.5, 1.0, 1.7):
+        assert np.array_equal(ce.ce_gauss5_weights(sigma), O.gauss5_weights(sigma))
+
+
+def test_create_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(ce.CoexecError) as ei:
+        ce.Engine()
+    assert ei.value.status == ce.CE_E_DEVICE

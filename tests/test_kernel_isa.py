@@ -1,0 +1,78 @@
+"""Static checks of the gfx950 code the compiler emits for the persistent
+kernels (CPU only: hipcc cross-compiles).
+
+A workgroup barrier inside a loop whose exit is decided per lane (an exec-mask
+update followed by a branch on an empty mask) lets some lanes leave the loop
+while the rest of the wave keeps executing the barrier; the workgroup then
+never makes progress. The persistent loops are written so that every branch
+around a barrier is uniform; this test keeps it that way."""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "paper_1805_02755_amd", "csrc", "kernels.hip")
+HIPCC = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
+
+
+@pytest.fixture(scope="module")
+def asm(tmp_path_factory):
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    out = tmp_path_factory.mktemp("isa") / "kernels.s"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang", "-target-feature",
+           "-Xclang", "-packed-fp32-ops", "--cuda-device-only", "-S", "-o", str(out), SRC]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return out.read_text()
+
+
+def _functions(text):
+    funcs = {}
+    for m in re.finditer(r"^(_Z\w+):.*?$(.*?)^\s*s_endpgm", text, flags=re.S | re.M):
+        funcs[m.group(1)] = m.group(2)
+    return funcs
+
+
+def _blocks(body):
+    """(label, loop header or None, lines) per basic block."""
+    blocks = []
+    cur = None
+    for ln in body.splitlines():
+        m = re.match(r"^(\.LBB\w+|; %bb\.\d+):(.*)$", ln)
+        if m:
+            hdr = re.search(r"Header=(BB\w+)", m.group(2))
+            own = re.search(r"This (?:Inner )?Loop Header", m.group(2))
+            label = m.group(1).lstrip(".").removeprefix("L")
+            cur = [label, hdr.group(1) if hdr else (label if own else None), []]
+            blocks.append(cur)
+            continue
+        if "This Loop Header" in ln or "This Inner Loop Header" in ln:
+            if cur is not None and cur[1] is None:
+                cur[1] = cur[0]
+        if cur is not None:
+            cur[2].append(ln.strip())
+    return blocks
+
+
+def test_persistent_loops_have_uniform_exits_around_barriers(asm):
+    funcs = {k: v for k, v in _functions(asm).items() if "k_persistent" in k}
+    assert len(funcs) == 4, sorted(funcs)
+    for name, body in funcs.items():
+        blocks = _blocks(body)
+        barrier_loops = {hdr for _, hdr, lines in blocks if hdr and any(l.startswith("s_barrier") for l in lines)}
+        for label, hdr, lines in blocks:
+            if hdr not in barrier_loops:
+                continue
+            txt = "\n".join(lines)
+            bad = re.search(r"s_andn2_b64 exec, exec, s\[\d+:\d+\]\s*\n\s*s_cbranch_execz", txt)
+            assert not bad, f"{name}: loop {hdr} holds a barrier and a per-lane exit in {label}"
+
+
+def test_no_packed_fp32_and_no_spills(asm):
+    for name, body in _functions(asm).items():
+        for op in ("v_pk_fma_f32", "v_pk_mul_f32", "v_pk_add_f32"):
+            assert op not in body, (name, op)
+    assert "scratch_store" not in asm
