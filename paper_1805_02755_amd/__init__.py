@@ -96,7 +96,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
                           "python -m paper_1805_02755_amd._build")
-    L = C.CDLL(LIB_PATH)
+    _lib = load(LIB_PATH)
+    return _lib
+
+
+def load(path: str):
+    """Opens a library exporting the C ABI and declares its signatures."""
+    L = C.CDLL(path)
     vp, sz, u32, u64, i32 = C.c_void_p, C.c_size_t, C.c_uint32, C.c_uint64, C.c_int32
     sigs = {
         "ce_engine_create": (i32, [C.POINTER(vp)]),
@@ -128,7 +134,6 @@ def lib():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
-    _lib = L
     return L
 
 
@@ -218,9 +223,10 @@ def stream_handle(stream) -> Optional[int]:
 class Engine:
     """Owns one ce_engine; methods mirror the C calls one to one."""
 
-    def __init__(self):
+    def __init__(self, library=None):
+        self._L = library if library is not None else lib()
         h = C.c_void_p()
-        st = lib().ce_engine_create(C.byref(h))
+        st = self._L.ce_engine_create(C.byref(h))
         if st != CE_OK:
             raise CoexecError(st, "ce_engine_create")
         self._h = h
@@ -228,7 +234,7 @@ class Engine:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().ce_engine_destroy(self._h)
+            self._L.ce_engine_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -244,11 +250,11 @@ class Engine:
         self.close()
 
     def errors(self):
-        L = lib()
+        L = self._L
         return [L.ce_engine_error(self._h, i).decode() for i in range(L.ce_engine_error_count(self._h))]
 
     def clear_errors(self):
-        lib().ce_engine_clear_errors(self._h)
+        self._L.ce_engine_clear_errors(self._h)
 
     def _check(self, st, where):
         if st != CE_OK:
@@ -256,12 +262,12 @@ class Engine:
         return st
 
     def use(self, dev_mask: int, gpu_ordinal: int = 0, host_threads: int = 0):
-        return self._check(lib().ce_engine_use(self._h, dev_mask, gpu_ordinal, host_threads), "ce_engine_use")
+        return self._check(self._L.ce_engine_use(self._h, dev_mask, gpu_ordinal, host_threads), "ce_engine_use")
 
     def work_items(self, gws, lws=None):
         g = (C.c_uint64 * len(gws))(*gws)
         l = (C.c_uint32 * len(lws))(*lws) if lws else None
-        return self._check(lib().ce_engine_work_items(self._h, len(gws), g, l), "ce_engine_work_items")
+        return self._check(self._L.ce_engine_work_items(self._h, len(gws), g, l), "ce_engine_work_items")
 
     def scheduler(self, kind: int, order: int = CE_ORDER_HOST_FIRST, n_packages: int = 0, k: int = 2,
                   package_granules: int = 0, props=(), power=(), min_granules=()):
@@ -273,48 +279,48 @@ class Engine:
             d.power[i] = v
         for i, v in enumerate(min_granules):
             d.min_granules[i] = v
-        return self._check(lib().ce_engine_scheduler(self._h, C.byref(d)), "ce_engine_scheduler")
+        return self._check(self._L.ce_engine_scheduler(self._h, C.byref(d)), "ce_engine_scheduler")
 
     def stream(self, hip_stream):
-        return self._check(lib().ce_engine_stream(self._h, hip_stream), "ce_engine_stream")
+        return self._check(self._L.ce_engine_stream(self._h, hip_stream), "ce_engine_stream")
 
     def kernel_events(self, start=None, stop=None):
         """Records torch.cuda.Event objects (or raw hipEvent_t) around the GPU kernel."""
         a = None if start is None else int(getattr(start, "cuda_event", start))
         b = None if stop is None else int(getattr(stop, "cuda_event", stop))
-        return self._check(lib().ce_engine_kernel_events(self._h, a, b), "ce_engine_kernel_events")
+        return self._check(self._L.ce_engine_kernel_events(self._h, a, b), "ce_engine_kernel_events")
 
     def program_kernel(self, kernel_id: int, params):
         self._params = params
-        return self._check(lib().ce_program_kernel(self._h, kernel_id, C.byref(params), C.sizeof(params)),
+        return self._check(self._L.ce_program_kernel(self._h, kernel_id, C.byref(params), C.sizeof(params)),
                            "ce_program_kernel")
 
     def program_in(self, slot: int, host=None, dev=None, nbytes: Optional[int] = None):
         nb = nbytes if nbytes is not None else _nbytes(host if host is not None else dev)
         self._keep += [host, dev]
-        return self._check(lib().ce_program_in(self._h, slot, _ptr(host), _ptr(dev), nb), "ce_program_in")
+        return self._check(self._L.ce_program_in(self._h, slot, _ptr(host), _ptr(dev), nb), "ce_program_in")
 
     def program_out(self, slot: int, host=None, dev=None, nbytes: Optional[int] = None):
         nb = nbytes if nbytes is not None else _nbytes(host if host is not None else dev)
         self._keep += [host, dev]
-        return self._check(lib().ce_program_out(self._h, slot, _ptr(host), _ptr(dev), nb), "ce_program_out")
+        return self._check(self._L.ce_program_out(self._h, slot, _ptr(host), _ptr(dev), nb), "ce_program_out")
 
     def program_out_pattern(self, outs: int, items: int):
-        return self._check(lib().ce_program_out_pattern(self._h, outs, items), "ce_program_out_pattern")
+        return self._check(self._L.ce_program_out_pattern(self._h, outs, items), "ce_program_out_pattern")
 
     def run(self):
-        return self._check(lib().ce_engine_run(self._h), "ce_engine_run")
+        return self._check(self._L.ce_engine_run(self._h), "ce_engine_run")
 
     def run_status(self) -> int:
-        return int(lib().ce_engine_run(self._h))
+        return int(self._L.ce_engine_run(self._h))
 
     def stats(self) -> ce_run_stats:
         s = ce_run_stats()
-        self._check(lib().ce_engine_stats(self._h, C.byref(s)), "ce_engine_stats")
+        self._check(self._L.ce_engine_stats(self._h, C.byref(s)), "ce_engine_stats")
         return s
 
     def trace(self):
-        n = lib().ce_engine_trace(self._h, None, 0)
+        n = self._L.ce_engine_trace(self._h, None, 0)
         buf = (ce_package_rec * max(1, n))()
-        n = lib().ce_engine_trace(self._h, buf, n)
+        n = self._L.ce_engine_trace(self._h, buf, n)
         return [(r.device, r.begin, r.end, r.t_claim, r.t_end) for r in buf[:n]]

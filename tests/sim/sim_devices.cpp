@@ -1,0 +1,239 @@
+// Fake devices for CPU tests of the host engine (engine.cpp).
+//
+// The real engine is compiled against a stub HIP runtime in which:
+//  - device memory is host memory;
+//  - the "GPU" persistent kernel is one CPU thread that claims packages from
+//    the same level-1 dispenser with the same rules as the device code
+//    (Static bands, Dynamic fetch-add, HGuided compare-and-swap) and fills
+//    the GPU package table, the summary and the completion run id;
+//  - payloads do no arithmetic: every work-item's first output word is set
+//    to the item's index (so the output merges can be checked), a per-run
+//    coverage counter of the item is incremented, and the worker spins for
+//    a configurable time per item, so device speeds are set by the test.
+// Nothing here is part of the product library.
+#include <hip/hip_runtime_api.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <thread>
+
+#include "../../paper_1805_02755_amd/csrc/host_payloads.hpp"
+#include "../../paper_1805_02755_amd/csrc/kernels.hpp"
+
+namespace {
+std::thread g_gpu;
+double g_gpu_ns_per_item = 1.0;
+double g_host_ns_per_item = 10.0;
+double g_gpu_claim_ns = 1000.0;
+std::atomic<uint32_t>* g_cov = nullptr;
+size_t g_cov_n = 0;
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+void spin_until(int64_t until) {
+  while (now_ns() < until) {
+  }
+}
+void join_gpu() {
+  if (g_gpu.joinable()) g_gpu.join();
+}
+}  // namespace
+
+extern "C" void sim_reset(size_t n_items) {
+  delete[] g_cov;
+  g_cov = new std::atomic<uint32_t>[n_items];
+  for (size_t i = 0; i < n_items; ++i) g_cov[i].store(0);
+  g_cov_n = n_items;
+}
+
+extern "C" void sim_coverage(uint32_t* dst, size_t n) {
+  for (size_t i = 0; i < n && i < g_cov_n; ++i) dst[i] = g_cov[i].load();
+}
+
+extern "C" void sim_set_rates(double gpu_ns_per_item, double host_ns_per_item, double gpu_claim_ns) {
+  g_gpu_ns_per_item = gpu_ns_per_item;
+  g_host_ns_per_item = host_ns_per_item;
+  g_gpu_claim_ns = gpu_claim_ns;
+}
+
+// ------------------------------------------------------------- HIP stubs
+hipError_t hipGetDeviceCount(int* c) { *c = 1; return hipSuccess; }
+hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int) {
+  strcpy(p->gcnArchName, "gfx950:sim");
+  p->multiProcessorCount = 8;
+  return hipSuccess;
+}
+hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t, int) { *v = 100000; return hipSuccess; }
+hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) { *s = (hipStream_t)0x1; return hipSuccess; }
+hipError_t hipStreamDestroy(hipStream_t) { return hipSuccess; }
+hipError_t hipStreamSynchronize(hipStream_t) { join_gpu(); return hipSuccess; }
+hipError_t hipMalloc(void** p, size_t n) { *p = calloc(1, n ? n : 1); return *p ? hipSuccess : 2; }
+hipError_t hipFree(void* p) { free(p); return hipSuccess; }
+hipError_t hipHostMalloc(void** p, size_t n, unsigned) { *p = calloc(1, n ? n : 1); return *p ? hipSuccess : 2; }
+hipError_t hipHostFree(void* p) { free(p); return hipSuccess; }
+hipError_t hipHostGetDevicePointer(void** d, void* h, unsigned) { *d = h; return hipSuccess; }
+hipError_t hipMemset(void* p, int v, size_t n) { memset(p, v, n); return hipSuccess; }
+hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) { join_gpu(); memcpy(d, s, n); return hipSuccess; }
+hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) {
+  join_gpu();  // stream order: after the kernel
+  memcpy(d, s, n);
+  return hipSuccess;
+}
+hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
+const char* hipGetErrorString(hipError_t) { return "sim"; }
+
+namespace ce {
+
+// ------------------------------------------------ coverage-marking payloads
+namespace {
+size_t item_words(int kernel_id) { return kernel_id == CE_KERNEL_NBODY_ACC ? 4 : 1; }
+void mark(uint32_t* out, uint64_t i0, uint64_t i1, size_t words) {
+  for (uint64_t i = i0; i < i1; ++i) {
+    out[i * words] = (uint32_t)i;
+    if (i < g_cov_n) g_cov[i].fetch_add(1, std::memory_order_relaxed);
+  }
+}
+// Each call takes ns_per_item per item in total, marking included.
+void h_escape(const ce_escape_params& p, uint64_t r0, uint64_t r1, uint32_t* out) {
+  const int64_t until = now_ns() + (int64_t)(g_host_ns_per_item * (double)((r1 - r0) * p.w));
+  mark(out, r0 * p.w, r1 * p.w, 1);
+  spin_until(until);
+}
+void h_blur(const float*, uint32_t w, uint32_t, const float*, uint64_t r0, uint64_t r1, float* out) {
+  const int64_t until = now_ns() + (int64_t)(g_host_ns_per_item * (double)((r1 - r0) * w));
+  mark((uint32_t*)out, r0 * w, r1 * w, 1);
+  spin_until(until);
+}
+void h_nbody(const float*, uint32_t, float, int, uint64_t i0, uint64_t i1, float* out4) {
+  const int64_t until = now_ns() + (int64_t)(g_host_ns_per_item * (double)(i1 - i0));
+  mark((uint32_t*)out4, i0, i1, 4);
+  spin_until(until);
+}
+const HostPayloadFns kSim = {h_escape, h_blur, h_nbody, "sim"};
+
+uint64_t items_of(const KernelArgs& a, uint64_t g0, uint64_t g1) {
+  if (a.kernel_id == CE_KERNEL_ESCAPE) return (g1 - g0) * a.esc.w;
+  if (a.kernel_id == CE_KERNEL_BLUR5) return (g1 - g0) * a.blur.w;
+  const uint64_t lo = g0 * 256, hi = std::min<uint64_t>(g1 * 256, a.nb.n);
+  return hi > lo ? hi - lo : 0;
+}
+uint64_t first_item(const KernelArgs& a, uint64_t g) {
+  if (a.kernel_id == CE_KERNEL_ESCAPE) return g * a.esc.w;
+  if (a.kernel_id == CE_KERNEL_BLUR5) return g * a.blur.w;
+  return std::min<uint64_t>(g * 256, a.nb.n);
+}
+}  // namespace
+
+const HostPayloadFns* host_payloads() { return &kSim; }
+
+// ------------------------------------------------------ fake GPU kernels
+uint64_t gpu_granules(const KernelArgs& a) {
+  if (a.kernel_id == CE_KERNEL_ESCAPE) return a.esc.h;
+  if (a.kernel_id == CE_KERNEL_BLUR5) return a.blur.h;
+  return (a.nb.n + 255) / 256;
+}
+uint32_t gpu_tiles(const KernelArgs& a, uint64_t g0, uint64_t g1) {
+  if (a.kernel_id == CE_KERNEL_ESCAPE) return (uint32_t)(ceil_div(g1 - g0, kEscapeTileRows) * ceil_div(a.esc.w, kEscapeTileCols));
+  if (a.kernel_id == CE_KERNEL_BLUR5) return (uint32_t)(ceil_div(g1 - g0, kBlurTileRows) * ceil_div(a.blur.w, kBlurTileCols));
+  return (uint32_t)(g1 - g0);
+}
+hipError_t persistent_blocks_per_cu(const KernelArgs&, int* b) {
+  *b = 2;
+  return hipSuccess;
+}
+
+hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, hipStream_t) {
+  join_gpu();
+  g_gpu = std::thread([a, s] {
+    uint64_t np = 0, gr = 0, stn = 0, t_first = 0, t_last = 0;
+    for (;;) {
+      uint64_t g0 = 0, g1 = 0;
+      spin_until(now_ns() + (int64_t)g_gpu_claim_ns);
+      if (s.kind == kStatic) {
+        if (s.st_nbands == 0) {
+          if (stn || s.st_begin >= s.st_end) break;
+          g0 = s.st_begin;
+          g1 = s.st_end;
+        } else {
+          const uint64_t b = s.st_begin + stn;
+          if (b >= s.st_end) break;
+          g0 = band_edge(b, s.G, s.st_nbands);
+          g1 = band_edge(b + 1, s.G, s.st_nbands);
+        }
+        ++stn;
+      } else if (s.kind == kDynamic) {
+        const uint64_t x = __atomic_fetch_add(&s.l1->next, s.pkg, __ATOMIC_RELAXED);
+        if (x >= s.G) break;
+        g0 = x;
+        g1 = std::min(x + s.pkg, s.G);
+      } else {
+        uint64_t cur = __atomic_load_n(&s.l1->next, __ATOMIC_ACQUIRE);
+        bool ok = false;
+        while (cur < s.G) {
+          const uint64_t sz = hguided_size(s.G - cur, s.P_self, s.sumP, s.n_dev, s.k, s.min_self);
+          if (__atomic_compare_exchange_n(&s.l1->next, &cur, cur + sz, false, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE)) {
+            ok = true;
+            g0 = cur;
+            g1 = cur + sz;
+            break;
+          }
+        }
+        if (!ok) break;
+      }
+      if (np >= s.max_pkgs) {
+        __atomic_store_n(&s.l1->gpu_flags, 1, __ATOMIC_RELEASE);
+        break;
+      }
+      const uint64_t tc = (uint64_t)(now_ns() / 10);
+      if (!np) t_first = tc;
+      const uint64_t n = items_of(a, g0, g1);
+      const int64_t until = now_ns() + (int64_t)(g_gpu_ns_per_item * (double)n);
+      mark((uint32_t*)a.out, first_item(a, g0), first_item(a, g0) + n, item_words(a.kernel_id));
+      spin_until(until);
+      PkgSlot& ps = s.pkgs[np];
+      ps.g0 = g0;
+      ps.g1 = g1;
+      ps.base = 0;
+      ps.ntiles = 1;
+      ps.tiles_done = 1;
+      ps.t_claim = tc;
+      ps.t_end = t_last = (uint64_t)(now_ns() / 10);
+      ++np;
+      gr += g1 - g0;
+    }
+    __atomic_store_n(&s.l1->gpu_t_first, t_first, __ATOMIC_RELEASE);
+    __atomic_store_n(&s.l1->gpu_t_last, t_last, __ATOMIC_RELEASE);
+    __atomic_store_n(&s.l1->gpu_granules, gr, __ATOMIC_RELEASE);
+    __atomic_store_n(&s.l1->gpu_packages, np, __ATOMIC_RELEASE);
+    __atomic_store_n(&s.l1->gpu_run_id, s.run_id, __ATOMIC_RELEASE);
+  });
+  return hipSuccess;
+}
+
+hipError_t launch_bare(const KernelArgs& a, hipStream_t) {
+  const uint64_t G = gpu_granules(a);
+  mark((uint32_t*)a.out, 0, items_of(a, 0, G), item_words(a.kernel_id));
+  return hipSuccess;
+}
+
+hipError_t launch_calibrate(L1State* l1, uint32_t rounds, uint64_t, hipStream_t) {
+  join_gpu();
+  g_gpu = std::thread([l1, rounds] {
+    for (uint32_t i = 1; i <= rounds; ++i) {
+      const int64_t t0 = now_ns();
+      while (__atomic_load_n(&l1->ping, __ATOMIC_ACQUIRE) != i)
+        if (now_ns() - t0 > 1000000000LL) return;
+      __atomic_store_n(&l1->tick, (uint64_t)(now_ns() / 10), __ATOMIC_RELEASE);
+      __atomic_store_n(&l1->pong, i, __ATOMIC_RELEASE);
+    }
+  });
+  return hipSuccess;
+}
+
+}  // namespace ce

@@ -1,0 +1,219 @@
+"""CPU tests of the host engine with fake devices (SURVEY §4 "tests/sim").
+
+engine.cpp is compiled against a stub HIP runtime (tests/sim) whose "GPU" is
+a CPU thread claiming from the same level-1 dispenser, and whose payloads do
+no arithmetic: they count how often each work-item was produced and spin for
+a set time per item. This exercises the real dispenser, host pool, output
+merges, statistics and trace on the CPU; the oracle supplies the scheduler
+arithmetic the packages must follow."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1805_02755_amd as ce
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SIM = os.path.join(ROOT, "tests", "sim")
+CSRC = os.path.join(ROOT, "paper_1805_02755_amd", "csrc")
+BOTH = ce.CE_DEV_GPU | ce.CE_DEV_HOST
+
+
+@pytest.fixture(scope="module")
+def simlib(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("sim") / "libcoexec_sim.so")
+    cmd = ["g++", "-O1", "-std=c++17", "-fPIC", "-shared", "-pthread", "-ffp-contract=off", "-I", SIM,
+           "-o", out, os.path.join(SIM, "sim_devices.cpp"), os.path.join(CSRC, "engine.cpp")]
+    subprocess.run(cmd, check=True, capture_output=True)
+    L = ce.load(out)
+    L.sim_set_rates.restype = None
+    L.sim_set_rates.argtypes = [C.c_double, C.c_double, C.c_double]
+    L.sim_reset.restype = None
+    L.sim_reset.argtypes = [C.c_size_t]
+    L.sim_coverage.restype = None
+    L.sim_coverage.argtypes = [C.c_void_p, C.c_size_t]
+    return L
+
+
+def _coverage(L, n):
+    cov = np.zeros(n, np.uint32)
+    L.sim_coverage(cov.ctypes.data, n)
+    return cov
+
+
+def _run(L, kind, size, devs, sched, host_threads=4, rates=(0.0, 0.0, 0.0)):
+    L.sim_set_rates(*rates)
+    eng = ce.Engine(L)
+    eng.use(devs, 0, host_threads)
+    if kind == "escape":
+        w, h = size
+        eng.work_items([w, h])
+        eng.program_kernel(ce.CE_KERNEL_ESCAPE, ce.ce_escape_params(w, h, -2.0, -1.5, 0.01, 0.01, 10))
+        out = np.zeros((h, w), np.uint32)
+        G, per = h, w
+    elif kind == "blur":
+        w, h = size
+        eng.work_items([w, h])
+        eng.program_kernel(ce.CE_KERNEL_BLUR5, ce.ce_blur5_params(w, h))
+        img = np.zeros((h, w), np.float32)
+        eng.program_in(0, host=img, dev=img)
+        wt = np.zeros(25, np.float32)
+        eng.program_in(1, host=wt, dev=wt)
+        out = np.zeros((h, w), np.uint32)
+        G, per = h, w
+    else:
+        n = size
+        eng.work_items([n], [256])
+        eng.program_kernel(ce.CE_KERNEL_NBODY_ACC, ce.ce_nbody_params(n, 1e-6, 1))
+        pos = np.zeros((n, 4), np.float32)
+        eng.program_in(0, host=pos, dev=pos)
+        out = np.zeros((n, 4), np.uint32)
+        G, per = (n + 255) // 256, 256
+    eng.scheduler(**sched)
+    eng.program_out(0, dev=out)
+    n_items = out.shape[0] if kind == "nbody" else out.size
+    L.sim_reset(n_items)
+    eng.run()
+    st = eng.stats()
+    tr = eng.trace()
+    eng.close()
+    vals = out[:, 0] if kind == "nbody" else out.reshape(-1)
+    # every item written with its own index: the merges moved the right ranges
+    assert np.array_equal(vals, np.arange(n_items, dtype=np.uint32))
+    cnt = _coverage(L, n_items)
+    return cnt, st, tr, G
+
+
+SCHEDS = {
+    "static": dict(kind=ce.CE_SCHED_STATIC, props=[0.7], order=ce.CE_ORDER_HOST_FIRST),
+    "static_rev8": dict(kind=ce.CE_SCHED_STATIC, props=[0.8], order=ce.CE_ORDER_GPU_FIRST, n_packages=8),
+    "dynamic": dict(kind=ce.CE_SCHED_DYNAMIC, package_granules=3),
+    "dynamic_count": dict(kind=ce.CE_SCHED_DYNAMIC, n_packages=17),
+    "hguided": dict(kind=ce.CE_SCHED_HGUIDED, power=[7, 2], k=2, min_granules=[4, 1]),
+}
+
+
+def _one_dev(sched):
+    s = dict(sched)
+    s.pop("props", None)
+    for key in ("power", "min_granules"):
+        if key in s:
+            s[key] = s[key][:1]
+    return s
+
+
+@pytest.mark.parametrize("kind,size", [("escape", (37, 53)), ("blur", (1000, 61)), ("nbody", 3000), ("nbody", 256)])
+@pytest.mark.parametrize("sched", list(SCHEDS))
+@pytest.mark.parametrize("devs", [ce.CE_DEV_GPU, ce.CE_DEV_HOST, BOTH])
+def test_every_item_exactly_once(simlib, kind, size, sched, devs):
+    s = SCHEDS[sched] if devs == BOTH else _one_dev(SCHEDS[sched])
+    G_expected = (size + 255) // 256 if kind == "nbody" else size[1]
+    if s.get("n_packages", 0) > G_expected and s["kind"] == ce.CE_SCHED_STATIC:
+        with pytest.raises(ce.CoexecError) as ei:  # more bands than granules
+            _run(simlib, kind, size, devs, s)
+        assert ei.value.status == ce.CE_E_INVALID
+        return
+    cnt, st, tr, G = _run(simlib, kind, size, devs, s, rates=(0.5, 5.0, 200.0))
+    assert np.all(cnt == 1), (int((cnt == 0).sum()), int((cnt > 1).sum()))
+    n_dev = 2 if devs == BOTH else 1
+    covered = np.zeros(G, np.int32)
+    for d, b, e, tc, te in tr:
+        assert 0 <= d < n_dev and 0 <= b < e <= G
+        covered[b:e] += 1
+    assert np.all(covered == 1)
+    assert sum(st.granules[:n_dev]) == G
+    assert sum(st.items[:n_dev]) == cnt.size
+    assert sum(st.packages[:n_dev]) == len(tr)
+
+
+def test_hguided_packages_follow_the_equation(simlib):
+    s = SCHEDS["hguided"]
+    for rates in ((0.2, 4.0, 100.0), (2.0, 2.0, 50.0), (0.05, 20.0, 1000.0)):
+        cnt, st, tr, G = _run(simlib, "blur", (500, 400), BOTH, s, rates=rates)
+        assert np.all(cnt == 1)
+        # the size of each package is fixed by the pending granules at its claim
+        for d, b, e, tc, te in tr:
+            want = O.hguided_size(G - b, s["power"], s["k"], d, s["min_granules"][d])
+            assert e - b == want, (d, b, e, want)
+
+
+def test_dynamic_packages_are_equal_and_aligned(simlib):
+    cnt, st, tr, G = _run(simlib, "escape", (64, 301), BOTH, SCHEDS["dynamic"], rates=(1.0, 3.0, 100.0))
+    for d, b, e, tc, te in tr:
+        assert b % 3 == 0 and e - b == min(3, G - b)
+
+
+def test_static_packages_follow_the_plan(simlib):
+    s = SCHEDS["static_rev8"]
+    cnt, st, tr, G = _run(simlib, "blur", (128, 1024), BOTH, s, rates=(0.1, 0.5, 10.0))
+    plan = O.static_plan(G, s["props"], [0, 1], n_bands=8)  # GPU first
+    for d in (0, 1):
+        pk = sorted((b, e) for dd, b, e, tc, te in tr if dd == d)
+        assert pk[0][0] == plan[d][0] and pk[-1][1] == plan[d][1]
+        assert all(e - b == 128 for b, e in pk)
+
+
+def test_balance_with_known_device_speeds(simlib):
+    # GPU 10 ns/item; host 4 threads at 160 ns/item -> the host device is 4x slower.
+    rates = (10.0, 160.0, 2000.0)
+    size = (1024, 256)
+    _, st_g, _, _ = _run(simlib, "blur", size, ce.CE_DEV_GPU, dict(kind=ce.CE_SCHED_STATIC), rates=rates)
+    _, st_h, _, _ = _run(simlib, "blur", size, ce.CE_DEV_HOST, dict(kind=ce.CE_SCHED_STATIC), rates=rates)
+    t_g, t_h = st_g.t_run, st_h.t_run
+    assert t_h > 2.0 * t_g
+    smax = O.s_max([t_g, t_h])
+    for sched in (dict(kind=ce.CE_SCHED_HGUIDED, power=[4, 1], k=2, min_granules=[4, 1]),
+                  dict(kind=ce.CE_SCHED_DYNAMIC, package_granules=4),
+                  dict(kind=ce.CE_SCHED_STATIC, props=[0.8], order=ce.CE_ORDER_HOST_FIRST)):
+        cnt, st, tr, G = _run(simlib, "blur", size, BOTH, sched, rates=rates)
+        assert np.all(cnt == 1)
+        eff = O.efficiency(t_g / st.t_run, smax)
+        assert st.balance > 0.6, (sched, st.balance)
+        assert eff > 0.6, (sched, eff)
+        assert st.packages[0] > 0 and st.packages[1] > 0
+
+
+def test_many_runs_reuse_pool_and_state(simlib):
+    eng = ce.Engine(simlib)
+    simlib.sim_set_rates(0.1, 1.0, 10.0)
+    for it in range(60):
+        ht = (1, 3, 8)[it % 3]
+        eng.use(BOTH if it % 4 else ce.CE_DEV_HOST, 0, ht)
+        w, h = 16 + it, 40 + (it * 7) % 50
+        eng.work_items([w, h])
+        eng.program_kernel(ce.CE_KERNEL_ESCAPE, ce.ce_escape_params(w, h, -2.0, -1.5, 0.01, 0.01, 10))
+        out = np.zeros((h, w), np.uint32)
+        eng.program_out(0, dev=out)
+        two = bool(it % 4)
+        sched = SCHEDS[list(SCHEDS)[it % len(SCHEDS)]]
+        eng.scheduler(**(sched if two else _one_dev(sched)))
+        simlib.sim_reset(w * h)
+        eng.run()
+        assert np.array_equal(out.reshape(-1), np.arange(w * h, dtype=np.uint32)), it
+        assert np.all(_coverage(simlib, w * h) == 1), it
+    eng.close()
+
+
+def test_error_list_and_states(simlib):
+    eng = ce.Engine(simlib)
+    assert eng.run_status() == ce.CE_E_STATE
+    assert eng.errors()
+    eng.clear_errors()
+    assert not eng.errors()
+    with pytest.raises(ce.CoexecError):
+        eng.work_items([0, 4])
+    with pytest.raises(ce.CoexecError):
+        eng.scheduler(kind=7)
+    eng.use(ce.CE_DEV_GPU)
+    eng.work_items([8, 8])
+    eng.program_kernel(ce.CE_KERNEL_ESCAPE, ce.ce_escape_params(8, 8, 0, 0, 1, 1, 1))
+    eng.program_out(0, host=np.zeros((8, 8), np.uint32))
+    assert eng.run_status() == ce.CE_E_STATE  # no scheduler
+    eng.scheduler(kind=ce.CE_SCHED_HGUIDED, power=[0])
+    assert eng.run_status() == ce.CE_E_INVALID  # power out of range
+    eng.scheduler(kind=ce.CE_SCHED_DYNAMIC)
+    assert eng.run_status() == ce.CE_E_INVALID  # neither size nor count
+    eng.close()
