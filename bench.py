@@ -51,6 +51,35 @@ def parse():
     return ap.parse_args()
 
 
+class HipEvents:
+    """Raw hipEvent_t handles from the HIP runtime, recorded by the engine on
+    the stream its kernel runs on."""
+
+    def __init__(self):
+        import ctypes as C
+        self.C = C
+        self.L = C.CDLL("libamdhip64.so")
+        self.L.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        self.L.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.L.hipEventSynchronize.argtypes = [C.c_void_p]
+        self.L.hipEventDestroy.argtypes = [C.c_void_p]
+
+    def create(self):
+        ev = self.C.c_void_p()
+        if self.L.hipEventCreate(self.C.byref(ev)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+        return ev.value
+
+    def elapsed_ms(self, a, b):
+        f = self.C.c_float()
+        if self.L.hipEventSynchronize(b) != 0 or self.L.hipEventElapsedTime(self.C.byref(f), a, b) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(f.value)
+
+    def destroy(self, ev):
+        self.L.hipEventDestroy(ev)
+
+
 def timed_runs(fn, warmup, steps, sync):
     for _ in range(warmup):
         fn()
@@ -199,8 +228,9 @@ def main():
     log(f"co-execution {coexec}")
     for _ in range(W):
         eng.run()
-    ev_s = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    ev_e = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    hev = HipEvents()
+    ev_s = [hev.create() for _ in range(K)]
+    ev_e = [hev.create() for _ in range(K)]
     per_run, stats = [], []
     sync()
     t0 = time.perf_counter()
@@ -215,7 +245,9 @@ def main():
     eng.kernel_events(None, None)
     trace = eng.trace()
 
-    kern_ms = [ev_s[i].elapsed_time(ev_e[i]) for i in range(K)]
+    kern_ms = [hev.elapsed_ms(ev_s[i], ev_e[i]) for i in range(K)]
+    for ev in ev_s + ev_e:
+        hev.destroy(ev)
     gpu_items = [s.items[0] for s in stats]
     host_items = [s.items[1] for s in stats]
     T_co = T_total / K

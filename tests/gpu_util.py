@@ -49,7 +49,9 @@ def run_payload(eng, kernel_id, params, gws, lws, inputs, out_shape, out_dtype, 
             keep.append(d)
             eng.program_in(slot, host=a, dev=d, nbytes=a.nbytes)
     torch.cuda.synchronize()
-    out_h = np.full(out_shape, 0xFF, dtype=np.uint8).view(out_dtype) if mode in ("host", "both") else None
+    nbytes_out = int(np.prod(out_shape)) * np.dtype(out_dtype).itemsize
+    out_h = (np.full(nbytes_out, 0xFF, dtype=np.uint8).view(out_dtype).reshape(out_shape)
+             if mode in ("host", "both") else None)
     out_d = None
     if mode in ("dev", "both"):
         nbytes = int(np.prod(out_shape)) * np.dtype(out_dtype).itemsize
