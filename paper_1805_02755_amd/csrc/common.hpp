@@ -41,7 +41,21 @@ struct alignas(64) L1State {
   uint64_t pong;
   uint64_t tick;
   uint64_t pad2[5];
+  // host completion ring (device-resident output): once the host device has
+  // finished it publishes the number of ring entries of the run
+  uint64_t host_final;  // host_final_word(run id, entries), written once per run
+  uint64_t pad3[7];
 };
+
+// The host's final ring size and the run it belongs to, in one word so the
+// GPU reads both with one atomic load: run id low 24 bits over a 40-bit count.
+CE_HD uint64_t host_final_word(uint64_t run_id, uint64_t count) { return ((run_id & 0xFFFFFFull) << 40) | count; }
+
+// A host tile whose output the GPU must copy into HBM: byte length in the top
+// 24 bits, byte offset in the low 40 bits; 0 means "not published yet".
+CE_HD uint64_t ring_word(uint64_t off, uint64_t len) { return (len << 40) | off; }
+CE_HD uint64_t ring_off(uint64_t w) { return w & ((1ull << 40) - 1); }
+CE_HD uint64_t ring_len(uint64_t w) { return w >> 40; }
 
 // Per-run GPU queue state in HBM (device-scope atomics only). The last
 // workgroup to leave a run resets it to zero for the next run.
@@ -55,8 +69,18 @@ struct alignas(64) L2State {
   uint64_t granules;    // granules published
   uint64_t t_first;     // first claim tick
   uint64_t t_last;      // latest package end tick
-  uint64_t pad[2];
+  uint32_t lock;        // held by the workgroup claiming the next package
+  uint32_t pad0;
+  uint64_t gather_next; // next host completion-ring entry to copy
 };
+
+// A published GPU package as one 64-bit word: granule count in the top 24
+// bits, first granule in the low 40 bits; 0 means "not published yet".
+constexpr uint64_t kPubG0Bits = 40;
+constexpr uint64_t kPubMaxSize = (1ull << 24) - 1;
+CE_HD uint64_t pub_word(uint64_t g0, uint64_t size) { return (size << kPubG0Bits) | g0; }
+CE_HD uint64_t pub_g0(uint64_t w) { return w & ((1ull << kPubG0Bits) - 1); }
+CE_HD uint64_t pub_size(uint64_t w) { return w >> kPubG0Bits; }
 
 // One GPU package as published to the workgroups; also its trace record.
 struct alignas(64) PkgSlot {
@@ -86,9 +110,17 @@ struct SchedArgs {
   uint64_t spin_limit;  // bound on any wait inside the kernel (iterations)
   L1State* l1;          // device address of the host-coherent dispenser
   L2State* l2;          // HBM
-  PkgSlot* pkgs;
+  PkgSlot* pkgs;        // trace records of the GPU's packages
+  uint64_t* pub;        // publication words, zero between runs
   uint32_t max_pkgs;
-  uint32_t pad;
+  uint32_t lookahead;   // claim the next package this many tiles early
+  // gather of host-computed output into HBM (gather_wgs == 0: off)
+  const uint64_t* ring; // device view of the host completion ring
+  const char* gsrc;     // device view of the host output buffer
+  char* gdst;           // device output buffer
+  uint32_t gather_wgs;  // workgroups 0 .. gather_wgs-1 only gather
+  uint32_t ring_cap;    // entries in the ring
+  uint64_t wait_ticks;  // longest wait for the host, in s_memrealtime ticks
 };
 
 // HGuided package size (section 5.3 equation), integer only. Callers keep

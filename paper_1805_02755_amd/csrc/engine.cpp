@@ -72,15 +72,17 @@ struct DevBuf {
 struct PinnedBuf {
   void* p = nullptr;
   size_t n = 0;
+  unsigned flags = hipHostMallocDefault;
   ~PinnedBuf() {
     if (p) (void)hipHostFree(p);
   }
-  bool ensure(size_t bytes) {
+  bool ensure(size_t bytes, bool zero = false) {
     if (bytes <= n) return true;
     if (p) (void)hipHostFree(p);
     p = nullptr;
     n = 0;
-    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return false;
+    if (hipHostMalloc(&p, bytes, flags) != hipSuccess) return false;
+    if (zero) memset(p, 0, bytes);
     n = bytes;
     return true;
   }
@@ -137,6 +139,7 @@ struct ce_engine {
   L1State* l1_dev = nullptr;   // device view
   L2State* l2 = nullptr;
   DevBuf pkgs_dev;
+  DevBuf pub_dev;  // publication words of the GPU's packages, zero between runs
   uint32_t pkgs_dev_cap = 0;
   double clock_offset_ns = 0.0;  // host_ns = tick * period + offset
   bool clock_ok = false;
@@ -162,7 +165,10 @@ struct ce_engine {
   DevBuf in_dev[kMaxSlots];
   PinnedBuf in_host[kMaxSlots];
   DevBuf out_dev_scratch;
-  PinnedBuf out_host_scratch;
+  PinnedBuf out_host_scratch;   // host output when only a device output is bound
+  PinnedBuf ring_buf;           // host completion ring read by the GPU's gatherers
+  bool gather = false;          // this run's host tiles are copied into HBM by the GPU
+  std::atomic<uint64_t> ring_count{0};
 
   // ---- host pool
   std::vector<std::thread> pool;
@@ -361,6 +367,29 @@ struct ce_engine {
     }
   }
 
+  // Byte range of the output written by host tile ti of package p.
+  void host_tile_bytes(const HostPkg& p, uint32_t ti, uint64_t* off, uint64_t* len) const {
+    if (kernel_id == CE_KERNEL_NBODY_ACC) {
+      const uint64_t i0 = p.g0 * kNbodyGranule + (uint64_t)ti * kHostNbodyTile;
+      const uint64_t end = std::min<uint64_t>(p.g1 * kNbodyGranule, nb.n);
+      const uint64_t i1 = std::min<uint64_t>(i0 + kHostNbodyTile, end);
+      *off = i0 * 16;
+      *len = (i1 - i0) * 16;
+    } else {
+      *off = (p.g0 + ti) * gws[0] * 4;
+      *len = gws[0] * 4;
+    }
+  }
+  // Makes a finished host tile visible to the GPU's gatherers (x86 stores
+  // are seen in program order, so the data precede the ring entry).
+  void publish_host_tile(const HostPkg& p, uint32_t ti) {
+    uint64_t off, len;
+    host_tile_bytes(p, ti, &off, &len);
+    const uint64_t k = ring_count.fetch_add(1, std::memory_order_relaxed);
+    uint64_t* ring = (uint64_t*)ring_buf.p;
+    __atomic_store_n(&ring[k], ring_word(off, len), __ATOMIC_RELEASE);
+  }
+
   // Host side of a run: every pool thread (and the caller) runs this loop.
   void host_work() {
     uint32_t p_cache = 0;
@@ -404,6 +433,7 @@ struct ce_engine {
       p_cache = p;
       HostPkg& pk = hq.pkgs[p];
       host_tile(pk, (uint32_t)(t - pk.base));
+      if (gather) publish_host_tile(pk, (uint32_t)(t - pk.base));
       if (pk.tiles_done.fetch_add(1, std::memory_order_acq_rel) + 1 == pk.ntiles)
         pk.t_end.store(now_ns(), std::memory_order_release);
     }
@@ -479,6 +509,7 @@ struct ce_engine {
         if (sched.n_packages == 0) return fail(CE_E_INVALID, "dynamic: package_granules or n_packages required");
         pkg = ceil_div(G, sched.n_packages);
       }
+      if (pkg > kPubMaxSize) return fail(CE_E_INVALID, "dynamic: package larger than 2^24-1 granules");
       gpu_s->pkg = host_s->pkg = pkg;
       *gpu_max = *host_max = ceil_div(G, pkg) + 1;
       if (gi >= 0 && gpu_tiles(kargs, 0, std::min(pkg, G)) == 1) gpu_s->direct = 1;
@@ -590,6 +621,8 @@ struct ce_engine {
       host_in1 = hin[1];
       host_out = out[0].host_out;
       if (!host_out) {
+        // host-coherent so the GPU's gatherers can read it over PCIe
+        out_host_scratch.flags = hipHostMallocCoherent | hipHostMallocMapped;
         if (!out_host_scratch.ensure(out[0].bytes)) return fail(CE_E_NOMEM, "run: host output scratch");
         host_out = out_host_scratch.p;
       }
@@ -600,15 +633,18 @@ struct ce_engine {
       }
     }
 
-    // persistent grid
-    uint32_t grid = 0;
+    // the GPU copies the host's tiles into HBM when the output lives only there
+    gather = use_gpu() && use_host() && out[0].dev_out && !out[0].host_out;
+    // persistent grid: resident workgroups, plus gatherers (one per XCD)
+    uint32_t grid = 0, gather_wgs = 0;
     if (use_gpu()) {
       int bpc = 0;
       if ((he = persistent_blocks_per_cu(kargs, &bpc)) != hipSuccess) return hip_fail(he, "run: occupancy");
       grid = (uint32_t)std::max(1, bpc) * (uint32_t)n_cu;
+      gather_wgs = gather ? std::min<uint32_t>(8, std::max<uint32_t>(1, grid / 4)) : 0;
       const uint32_t all_tiles = gpu_tiles(kargs, 0, G);
-      if (all_tiles > 0 && grid > all_tiles) grid = all_tiles;
-      if (grid == 0) grid = 1;
+      if (all_tiles > 0 && grid > all_tiles + gather_wgs) grid = all_tiles + gather_wgs;
+      if (grid <= gather_wgs) grid = gather_wgs + 1;
     }
 
     SchedArgs gs{}, hs{};
@@ -618,12 +654,38 @@ struct ce_engine {
     host_args = hs;
     if (use_gpu()) {
       if (gmax > pkgs_dev_cap) {
-        if (!pkgs_dev.ensure(gmax * sizeof(PkgSlot))) return fail(CE_E_NOMEM, "run: package table");
+        if (!pkgs_dev.ensure(gmax * sizeof(PkgSlot)) || !pub_dev.ensure(gmax * sizeof(uint64_t)))
+          return fail(CE_E_NOMEM, "run: package table");
+        if ((he = hipMemset(pub_dev.p, 0, gmax * sizeof(uint64_t))) != hipSuccess ||
+            (he = hipMemset(pkgs_dev.p, 0, gmax * sizeof(PkgSlot))) != hipSuccess)
+          return hip_fail(he, "run: package table");
         pkgs_dev_cap = (uint32_t)gmax;
       }
       gs.pkgs = (PkgSlot*)pkgs_dev.p;
+      gs.pub = (uint64_t*)pub_dev.p;
       gs.max_pkgs = pkgs_dev_cap;
+      // claim the next package while a quarter round of tiles is still to be handed out
+      gs.lookahead = std::max<uint32_t>(1, (grid - gather_wgs) / 4);
+      gs.wait_ticks = (uint64_t)wallclock_hz * 60;
+      if (gather) {
+        const uint64_t max_host_tiles =
+            kernel_id == CE_KERNEL_NBODY_ACC ? ceil_div(nb.n, kHostNbodyTile) : G;
+        const size_t cap = (size_t)max_host_tiles + gather_wgs + 1;
+        ring_buf.flags = hipHostMallocCoherent | hipHostMallocMapped;
+        if (!ring_buf.ensure(cap * sizeof(uint64_t), true)) return fail(CE_E_NOMEM, "run: completion ring");
+        void* rdev = nullptr;
+        void* sdev = nullptr;
+        if ((he = hipHostGetDevicePointer(&rdev, ring_buf.p, 0)) != hipSuccess ||
+            (he = hipHostGetDevicePointer(&sdev, host_out, 0)) != hipSuccess)
+          return hip_fail(he, "run: device view of the host output");
+        gs.ring = (const uint64_t*)rdev;
+        gs.gsrc = (const char*)sdev;
+        gs.gdst = (char*)out[0].dev_out;
+        gs.gather_wgs = gather_wgs;
+        gs.ring_cap = (uint32_t)std::min<size_t>(cap, 0xFFFFFFFFu);
+      }
     }
+    ring_count.store(0, std::memory_order_relaxed);
     if (use_host()) {
       if (!hq.ensure(hmax)) return fail(CE_E_NOMEM, "run: host package table");
     }
@@ -653,6 +715,8 @@ struct ce_engine {
       host_work();
       const uint32_t want = (uint32_t)pool.size();
       while (pool_done.load(std::memory_order_acquire) < want) cpu_relax();
+      if (gather)
+        __atomic_store_n(&l1->host_final, host_final_word(run_id, ring_count.load()), __ATOMIC_RELEASE);
     }
     if (use_gpu()) {
       // the last workgroup out writes the run id; poll it, then sync
@@ -664,6 +728,7 @@ struct ce_engine {
       if ((he = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(he, "run: kernel");
       if (__atomic_load_n(&l1->gpu_run_id, __ATOMIC_ACQUIRE) != run_id)
         return fail(CE_E_TIMEOUT, "run: GPU did not report completion");
+      if (gather) memset(ring_buf.p, 0, ring_count.load() * sizeof(uint64_t));  // ready for the next run
       if (__atomic_load_n(&l1->gpu_flags, __ATOMIC_ACQUIRE))
         return fail(CE_E_TIMEOUT, "run: GPU dispenser wait exceeded its bound or package table overflow");
     }
@@ -702,8 +767,8 @@ struct ce_engine {
     };
     const auto hiv = use_host() ? host_intervals() : std::vector<std::pair<uint64_t, uint64_t>>{};
     bool issued = false;
-    // host-computed ranges into the device output
-    if (use_host() && out[0].dev_out) {
+    // host-computed ranges into the device output (unless the GPU gathered them)
+    if (use_host() && out[0].dev_out && !gather) {
       for (auto& iv : hiv) {
         size_t off, len;
         bytes_of(iv.first, iv.second, &off, &len);

@@ -207,6 +207,26 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, 
       ++np;
       gr += g1 - g0;
     }
+    // gather: copy the host's finished tiles into the device output
+    if (s.gather_wgs) {
+      const uint64_t want = host_final_word(s.run_id, 0) >> 40;
+      for (uint64_t j = 0;; ++j) {
+        uint64_t w = 0;
+        const int64_t t0 = now_ns();
+        for (;;) {
+          if (j < s.ring_cap) w = __atomic_load_n(&s.ring[j], __ATOMIC_ACQUIRE);
+          if (w) break;
+          const uint64_t f = __atomic_load_n(&s.l1->host_final, __ATOMIC_ACQUIRE);
+          if ((f >> 40) == want && j >= (f & ((1ull << 40) - 1))) break;
+          if (now_ns() - t0 > 10000000000LL) {
+            __atomic_store_n(&s.l1->gpu_flags, 2, __ATOMIC_RELEASE);
+            break;
+          }
+        }
+        if (!w) break;
+        memcpy(s.gdst + ring_off(w), s.gsrc + ring_off(w), ring_len(w));
+      }
+    }
     __atomic_store_n(&s.l1->gpu_t_first, t_first, __ATOMIC_RELEASE);
     __atomic_store_n(&s.l1->gpu_t_last, t_last, __ATOMIC_RELEASE);
     __atomic_store_n(&s.l1->gpu_granules, gr, __ATOMIC_RELEASE);
