@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["blur", "escape", "nbody"], default="blur")
+    ap.add_argument("--workload", choices=["blur", "escape", "nbody", "batch", "serve"], default="blur")
+    ap.add_argument("--serve-jobs", type=int, default=2000)
     ap.add_argument("--mode", choices=["device", "host"], default="device",
                     help="device: inputs and output resident in HBM; host: host buffers, PCIe inside the step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -113,6 +114,10 @@ def main():
     stream = torch.cuda.Stream()
     sync = torch.cuda.synchronize
     host_cores = os.cpu_count() or 1
+    if args.workload == "batch":
+        return bench_batch(args, ce, synth, torch, np, stream)
+    if args.workload == "serve":
+        return bench_serve(args, ce, synth, torch, np, stream)
 
     eng = ce.Engine()
     eng.stream(stream.cuda_stream)
@@ -352,6 +357,185 @@ def main():
     }
     print(json.dumps(res), flush=True)
     eng.close()
+
+
+def bench_batch(args, ce, synth, torch, np, stream):
+    """256 escape-time jobs of uneven sizes (sides log-uniform in [64, 2048],
+    max_iter uniform in [64, 4096], seed 0xBA7C4) as one persistent,
+    graph-captured launch with an autotuned tile shape and package size,
+    against one plain launch per job."""
+    K, W = args.steps, args.warmup
+    jobs = synth.batch_jobs()
+    dev = torch.device("cuda:0")
+    outs = [torch.empty((p.h, p.w), dtype=torch.int32, device=dev) for p in jobs]
+    torch.cuda.synchronize()
+    b = ce.Batch(stream.cuda_stream)
+    for p, o in zip(jobs, outs):
+        b.add_escape(ce.ce_escape_params(p.w, p.h, *p.as_f32(), p.max_iter), o)
+    n_items = sum(p.w * p.h for p in jobs)
+    log("separate launches")
+    for _ in range(W):
+        b.run_separate()
+    t_sep, g_sep = [], []
+    for _ in range(K):
+        b.run_separate()
+        st = b.stats()
+        t_sep.append(st.t_run)
+        g_sep.append(st.t_gpu_ms)
+    log("autotune")
+    chosen = b.tune(reps=2)
+    for _ in range(W):
+        b.run()
+    torch.cuda.synchronize()
+    per_run, kern = [], []
+    t0 = time.perf_counter()
+    for _ in range(K):
+        b.run()
+        st = b.stats()
+        per_run.append(st.t_run)
+        kern.append(st.t_gpu_ms)
+    T = time.perf_counter() - t0
+    iters = int(sum(int(o.to(torch.int64).sum().item()) for o in outs))
+    achieved = 8.0 * iters / (med(kern) * 1e-3) / 1e12
+    cpu_base = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        t0 = time.perf_counter()
+        done = 0
+        nj = 0
+        for p in jobs:
+            O.escape(p.w, p.h, *[float(v) for v in p.as_f32()], p.max_iter)
+            done += p.w * p.h
+            nj += 1
+            if time.perf_counter() - t0 > 10.0:
+                break
+        dt = time.perf_counter() - t0
+        cpu_base = {"value": done / dt, "unit": "work-items/s", "cores": 1, "kind": "oracle",
+                    "sample": f"the first {nj} jobs of the batch", "seconds": dt}
+    res = {
+        "metric": METRIC, "value": n_items * K / T, "unit": "work-items/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": T / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic (seeded SplitMix64 inputs; see DESIGN.md)",
+        "config": {"workload": "batched escape-time: 256 jobs, side log-uniform [64,2048], max_iter U[64,4096]",
+                   "form": "one persistent hipGraph launch", "tile_rows": chosen[0], "tile_cols": chosen[1],
+                   "package_tiles": chosen[2]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "TOP/s (FP32 VALU lane-ops)", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "k_batch_escape", "kernel_ms": med(kern), "iterations": iters},
+        "cpu_baseline": cpu_base,
+        "batch": {"separate_launch_ms": med(t_sep) * 1e3, "separate_gpu_ms": med(g_sep),
+                  "graph_launch_ms": med(per_run) * 1e3, "graph_gpu_ms": med(kern),
+                  "speedup_vs_separate": med(t_sep) / med(per_run), "jobs": len(jobs), "items": n_items},
+    }
+    print(json.dumps(res), flush=True)
+    b.close()
+
+
+def bench_serve(args, ce, synth, torch, np, stream):
+    """Serving: a Poisson trace of escape, blur and n-body jobs (200 jobs/s,
+    sizes log-uniform; seed 0x5E2E) replayed in real time against the
+    persistent serving kernel, and against one plain launch per job in
+    arrival order. Inputs come from resident pools in HBM (a job of side s
+    reads the first s*s pixels of one 16384^2 image; a job of n bodies the
+    first n of 131,072); outputs are allocated per job from the HBM budget."""
+    import threading
+    trace = synth.serve_trace(args.serve_jobs)
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(synth.blur_image(16384, 16384, seed=0x5E21)).to(dev)
+    bodies = torch.from_numpy(synth.nbody_bodies(131072, seed=0x5E22)).to(dev)
+    wt = torch.from_numpy(ce.ce_gauss5_weights(1.0)).to(dev)
+    eps2 = 1e-6
+
+    def job_args(j):
+        if j.kind == "escape":
+            p = synth.escape_region(j.size, j.size, *j.region, j.max_iter)
+            return ce.CE_KERNEL_ESCAPE, ce.ce_escape_params(p.w, p.h, *p.as_f32(), p.max_iter), [], j.size * j.size
+        if j.kind == "blur":
+            return ce.CE_KERNEL_BLUR5, ce.ce_blur5_params(j.size, j.size), [img, wt], j.size * j.size
+        return ce.CE_KERNEL_NBODY_ACC, ce.ce_nbody_params(j.size, eps2, 0), [bodies], j.size
+
+    specs = [job_args(j) for j in trace]
+    n_items = sum(s[3] for s in specs)
+    out_bytes = max(s[3] for s in specs) * 16
+    torch.cuda.synchronize()
+
+    # --- one plain launch per job, in arrival order (FIFO, no overlap)
+    log(f"serving trace: {len(trace)} jobs over {trace[-1].arrival_s:.1f} s; plain launches first")
+    scratch = torch.empty(out_bytes, dtype=torch.uint8, device=dev)
+    lat_plain = []
+    t0 = time.perf_counter()
+    for j, (kid, prm, ins, _) in zip(trace, specs):
+        now = time.perf_counter() - t0
+        if now < j.arrival_s:
+            time.sleep(j.arrival_s - now)
+        ce.ce_bare_run(kid, prm, ins, scratch, stream=stream.cuda_stream, sync=True)
+        lat_plain.append(time.perf_counter() - t0 - j.arrival_s)
+    wall_plain = time.perf_counter() - t0
+    del scratch
+    torch.cuda.synchronize()
+
+    # --- the serving kernel
+    log("serving kernel")
+    srv = ce.Server(max(4 << 30, 8 * out_bytes), keep_outputs=False, session_timeout_s=600.0)
+    warm = [srv.submit(*specs[i][:2], *specs[i][2]) for i in range(min(8, len(specs)))]
+    for t in warm:
+        srv.wait(t, 120.0)
+    srv.drain(120.0)
+    srv.close()
+    srv = ce.Server(max(4 << 30, 8 * out_bytes), keep_outputs=False, session_timeout_s=600.0)
+    tickets = []
+
+    def client():
+        c0 = time.perf_counter()
+        for j, (kid, prm, ins, _) in zip(trace, specs):
+            now = time.perf_counter() - c0
+            if now < j.arrival_s:
+                time.sleep(j.arrival_s - now)
+            tickets.append(srv.submit(kid, prm, *ins))
+
+    th = threading.Thread(target=client)
+    th.start()
+    th.join()
+    for t in tickets:
+        srv.wait(t, 600.0)
+    srv.drain(120.0)
+    r = srv.stats()
+    srv.close()
+    lat_plain.sort()
+    pct = lambda v, q: float(np.percentile(np.asarray(v), q))
+    cpu_base = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        t0 = time.perf_counter()
+        done = nj = 0
+        for j in trace:
+            if j.kind != "escape":
+                continue
+            p = synth.escape_region(j.size, j.size, *j.region, j.max_iter)
+            O.escape(p.w, p.h, *[float(v) for v in p.as_f32()], p.max_iter)
+            done += p.w * p.h
+            nj += 1
+            if time.perf_counter() - t0 > 10.0:
+                break
+        dt = time.perf_counter() - t0
+        cpu_base = {"value": done / dt, "unit": "work-items/s", "cores": 1, "kind": "oracle",
+                    "sample": f"the first {nj} escape-time jobs of the trace", "seconds": dt}
+    res = {
+        "metric": METRIC, "value": r.items_per_s, "unit": "work-items/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": r.wall_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "mixed (u32 escape, f32 blur and n-body)", "data": "synthetic (seeded SplitMix64 trace; see DESIGN.md)",
+        "config": {"workload": f"serving trace: {len(trace)} Poisson arrivals at 200/s, escape side [256,4096], "
+                               "blur side [1024,16384], n-body [4096,131072]", "form": "persistent serving kernel"},
+        "roofline": None,
+        "cpu_baseline": cpu_base,
+        "serve": {"jobs": int(r.completed), "items": int(r.items), "p50_ms": r.p50_s * 1e3, "p99_ms": r.p99_s * 1e3,
+                  "mean_ms": r.mean_s * 1e3, "max_ms": r.max_s * 1e3, "wall_s": r.wall_s,
+                  "jobs_per_s": r.jobs_per_s, "peak_hbm_bytes": int(r.peak_hbm),
+                  "max_inflight": int(r.max_inflight_seen),
+                  "plain_p50_ms": pct(lat_plain, 50) * 1e3, "plain_p99_ms": pct(lat_plain, 99) * 1e3,
+                  "plain_wall_s": wall_plain, "plain_items_per_s": n_items / wall_plain},
+    }
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

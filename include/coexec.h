@@ -207,6 +207,117 @@ int ce_engine_error_count(const ce_engine* e);
 const char* ce_engine_error(const ce_engine* e, int i);
 void ce_engine_clear_errors(ce_engine* e);
 
+/* ---- batched form ------------------------------------------------------
+ * Many escape-time jobs of uneven sizes run as ONE persistent kernel launch
+ * over the concatenation of their tiles, captured once in a hipGraph and
+ * replayed, instead of one launch per job. The tile shape (tile_rows x
+ * tile_cols, 256 pixels) and the tiles taken per workgroup request
+ * (package_tiles, a Dynamic schedule inside the GPU, section 5.3) are chosen
+ * by ce_batch_tune, which times every candidate on the batch itself. The
+ * per-pixel arithmetic is that of CE_KERNEL_ESCAPE. GPU only. */
+typedef struct ce_batch ce_batch;
+typedef struct {
+  uint32_t tile_rows;     /* 1, 2, 4, 8 or 16; tile_cols = 256 / tile_rows */
+  uint32_t tile_cols;     /* output of ce_batch_get_config / ce_batch_tune  */
+  uint32_t package_tiles; /* tiles per workgroup request, >= 1              */
+} ce_batch_config;
+typedef struct {
+  uint32_t jobs;
+  uint32_t workgroups;    /* persistent grid of the last build             */
+  uint64_t items;         /* pixels over all jobs                          */
+  uint64_t total_tiles;
+  uint32_t tile_rows, tile_cols, package_tiles;
+  uint32_t pad;
+  double t_run;           /* seconds, last ce_batch_run / run_separate call */
+  double t_gpu_ms;        /* GPU time of that call (HIP events)            */
+  uint64_t launches;      /* graph launches so far                         */
+} ce_batch_report;
+/* hip_stream may be NULL (the batch creates its own stream). */
+ce_status ce_batch_create(ce_batch** out, void* hip_stream);
+void ce_batch_destroy(ce_batch* b);
+/* Appends a job; dev_out is a device buffer of h*w uint32, owned by the
+ * caller and valid while the batch uses it. At most 4096 jobs. */
+ce_status ce_batch_add_escape(ce_batch* b, const ce_escape_params* p, void* dev_out, uint32_t* index);
+ce_status ce_batch_clear(ce_batch* b);
+ce_status ce_batch_set_config(ce_batch* b, const ce_batch_config* c);
+ce_status ce_batch_get_config(const ce_batch* b, ce_batch_config* c);
+/* Times every (tile shape, package size) candidate reps times on the
+ * current jobs, keeps the fastest and writes it to *chosen (may be NULL).
+ * Every candidate writes the outputs, so they hold a valid result after. */
+ce_status ce_batch_tune(ce_batch* b, uint32_t reps, ce_batch_config* chosen);
+/* One graph launch of the whole batch, synchronous. The graph is rebuilt
+ * only when jobs or the configuration changed. */
+ce_status ce_batch_run(ce_batch* b);
+/* Baseline: one plain grid launch per job on the same stream, synchronous. */
+ce_status ce_batch_run_separate(ce_batch* b);
+ce_status ce_batch_stats(const ce_batch* b, ce_batch_report* s);
+/* Message of the last failed call (owned by the batch). */
+const char* ce_batch_error(const ce_batch* b);
+
+/* ---- serving form -------------------------------------------------------
+ * Continuous batching of jobs on one persistent serving kernel. Clients
+ * submit jobs from any thread; a server thread admits them in arrival order
+ * as soon as an in-flight slot and enough of the HBM budget are free (the
+ * job's output, and its inputs when given as host pointers, live in one
+ * device arena of hbm_budget bytes), and publishes them to the kernel, which
+ * interleaves the tiles of every admitted job. A job's inputs may instead be
+ * device pointers the caller keeps resident. Latency is measured from
+ * ce_server_submit to the server thread seeing the job's completion word.
+ * A session starts at the first submit and ends at ce_server_drain; while it
+ * lasts the serving kernel occupies the GPU's compute units. The per-item
+ * arithmetic is that of the CE_KERNEL_* payloads. GPU only. */
+#define CE_JOB_QUEUED 0
+#define CE_JOB_ADMITTED 1
+#define CE_JOB_DONE 2
+#define CE_JOB_FAILED 3
+typedef struct ce_server ce_server;
+typedef struct {
+  uint64_t hbm_budget;      /* bytes of device memory for job buffers (> 0)  */
+  uint32_t max_inflight;    /* admitted but unfinished jobs; 0 = 64           */
+  uint32_t keep_outputs;    /* 0: a job's memory is freed when it finishes   */
+  uint32_t max_jobs;        /* jobs per session; 0 = 65536                    */
+  uint32_t workgroups_per_cu; /* serving workgroups per CU; 0 = the occupancy
+                               * limit minus one, which leaves room for copies
+                               * and the caller's own kernels during a session */
+  double session_timeout_s; /* the kernel leaves after this long; 0 = 300 s  */
+} ce_server_config;
+typedef struct {
+  int32_t kernel_id;        /* CE_KERNEL_*                                    */
+  uint32_t pad;
+  ce_escape_params esc;     /* the parameters of kernel_id are used           */
+  ce_blur5_params blur;
+  ce_nbody_params nb;
+  const void* in0_dev;      /* resident device input, or NULL                 */
+  const void* in1_dev;
+  const void* in0_host;     /* host input copied into HBM at admission        */
+  const void* in1_host;
+} ce_job;
+typedef struct {
+  uint64_t submitted, completed, items;
+  double p50_s, p99_s, mean_s, max_s; /* latency, submit -> completion seen   */
+  double wall_s;            /* first submit -> last completion               */
+  double items_per_s, jobs_per_s;
+  uint64_t peak_hbm;        /* largest arena use                             */
+  uint64_t max_inflight_seen;
+} ce_server_report;
+ce_status ce_server_create(const ce_server_config* cfg, void* hip_stream, ce_server** out);
+/* Ends the session (waits up to 30 s) and frees everything. NULL-safe. */
+void ce_server_destroy(ce_server* s);
+/* CE_E_BUDGET if the job alone needs more than the HBM budget. */
+ce_status ce_server_submit(ce_server* s, const ce_job* job, uint64_t* ticket);
+ce_status ce_server_status(ce_server* s, uint64_t ticket, int32_t* state);
+ce_status ce_server_wait(ce_server* s, uint64_t ticket, double timeout_s);
+/* Device output of a finished job (keep_outputs only); valid until release. */
+ce_status ce_server_output(ce_server* s, uint64_t ticket, void** dev_ptr, size_t* bytes);
+/* Copies a finished job's output (keep_outputs only) into host memory on the
+ * server's copy stream and waits for it; bytes must equal the output size. */
+ce_status ce_server_copy_output(ce_server* s, uint64_t ticket, void* host_dst, size_t bytes);
+ce_status ce_server_release(ce_server* s, uint64_t ticket);
+/* Waits for every submitted job, then ends the session. */
+ce_status ce_server_drain(ce_server* s, double timeout_s);
+ce_status ce_server_stats(const ce_server* s, ce_server_report* r);
+const char* ce_server_error(const ce_server* s);
+
 /* ---- plain single-GPU launch (the "native" side of the overhead metric,
  * section 7.3): one grid launch of the same payload over the whole index
  * space with no dispenser, on `hip_stream` (NULL = default stream). Device

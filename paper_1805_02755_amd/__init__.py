@@ -48,8 +48,17 @@ EXPORTED_SYMBOLS = (
     "ce_engine_stream", "ce_engine_kernel_events", "ce_program_kernel", "ce_program_in", "ce_program_out", "ce_program_out_pattern",
     "ce_engine_run", "ce_engine_stats", "ce_engine_trace", "ce_engine_has_errors", "ce_engine_error_count",
     "ce_engine_error", "ce_engine_clear_errors", "ce_bare_run", "ce_sched_static_plan", "ce_sched_hguided_size",
-    "ce_gauss5_weights", "ce_version",
+    "ce_gauss5_weights", "ce_version", "ce_batch_create", "ce_batch_destroy", "ce_batch_add_escape",
+    "ce_batch_clear", "ce_batch_set_config", "ce_batch_get_config", "ce_batch_tune", "ce_batch_run",
+    "ce_batch_run_separate", "ce_batch_stats", "ce_batch_error", "ce_server_create", "ce_server_destroy",
+    "ce_server_submit", "ce_server_status", "ce_server_wait", "ce_server_output", "ce_server_copy_output",
+    "ce_server_release", "ce_server_drain", "ce_server_stats", "ce_server_error",
 )
+
+CE_JOB_QUEUED = 0
+CE_JOB_ADMITTED = 1
+CE_JOB_DONE = 2
+CE_JOB_FAILED = 3
 
 
 class ce_escape_params(C.Structure):
@@ -78,6 +87,35 @@ class ce_run_stats(C.Structure):
                 ("device_kind", C.c_uint32 * CE_MAX_DEVICES), ("balance", C.c_double),
                 ("total_granules", C.c_uint64), ("total_items", C.c_uint64), ("gpu_workgroups", C.c_uint32),
                 ("host_threads", C.c_uint32)]
+
+
+class ce_batch_config(C.Structure):
+    _fields_ = [("tile_rows", C.c_uint32), ("tile_cols", C.c_uint32), ("package_tiles", C.c_uint32)]
+
+
+class ce_batch_report(C.Structure):
+    _fields_ = [("jobs", C.c_uint32), ("workgroups", C.c_uint32), ("items", C.c_uint64),
+                ("total_tiles", C.c_uint64), ("tile_rows", C.c_uint32), ("tile_cols", C.c_uint32),
+                ("package_tiles", C.c_uint32), ("pad", C.c_uint32), ("t_run", C.c_double),
+                ("t_gpu_ms", C.c_double), ("launches", C.c_uint64)]
+
+
+class ce_server_config(C.Structure):
+    _fields_ = [("hbm_budget", C.c_uint64), ("max_inflight", C.c_uint32), ("keep_outputs", C.c_uint32),
+                ("max_jobs", C.c_uint32), ("workgroups_per_cu", C.c_uint32), ("session_timeout_s", C.c_double)]
+
+
+class ce_job(C.Structure):
+    _fields_ = [("kernel_id", C.c_int32), ("pad", C.c_uint32), ("esc", ce_escape_params), ("blur", ce_blur5_params),
+                ("nb", ce_nbody_params), ("in0_dev", C.c_void_p), ("in1_dev", C.c_void_p),
+                ("in0_host", C.c_void_p), ("in1_host", C.c_void_p)]
+
+
+class ce_server_report(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("items", C.c_uint64),
+                ("p50_s", C.c_double), ("p99_s", C.c_double), ("mean_s", C.c_double), ("max_s", C.c_double),
+                ("wall_s", C.c_double), ("items_per_s", C.c_double), ("jobs_per_s", C.c_double),
+                ("peak_hbm", C.c_uint64), ("max_inflight_seen", C.c_uint64)]
 
 
 class ce_package_rec(C.Structure):
@@ -129,9 +167,36 @@ def load(path: str):
         "ce_sched_hguided_size": (u64, [u64, C.POINTER(u64), u32, u32, u32, u64]),
         "ce_gauss5_weights": (i32, [C.c_double, C.POINTER(C.c_float)]),
         "ce_version": (C.c_char_p, []),
+        "ce_batch_create": (i32, [C.POINTER(vp), vp]),
+        "ce_batch_destroy": (None, [vp]),
+        "ce_batch_add_escape": (i32, [vp, C.POINTER(ce_escape_params), vp, C.POINTER(u32)]),
+        "ce_batch_clear": (i32, [vp]),
+        "ce_batch_set_config": (i32, [vp, C.POINTER(ce_batch_config)]),
+        "ce_batch_get_config": (i32, [vp, C.POINTER(ce_batch_config)]),
+        "ce_batch_tune": (i32, [vp, u32, C.POINTER(ce_batch_config)]),
+        "ce_batch_run": (i32, [vp]),
+        "ce_batch_run_separate": (i32, [vp]),
+        "ce_batch_stats": (i32, [vp, C.POINTER(ce_batch_report)]),
+        "ce_batch_error": (C.c_char_p, [vp]),
+        "ce_server_create": (i32, [C.POINTER(ce_server_config), vp, C.POINTER(vp)]),
+        "ce_server_destroy": (None, [vp]),
+        "ce_server_submit": (i32, [vp, C.POINTER(ce_job), C.POINTER(u64)]),
+        "ce_server_status": (i32, [vp, u64, C.POINTER(i32)]),
+        "ce_server_wait": (i32, [vp, u64, C.c_double]),
+        "ce_server_output": (i32, [vp, u64, C.POINTER(vp), C.POINTER(sz)]),
+        "ce_server_copy_output": (i32, [vp, u64, vp, sz]),
+        "ce_server_release": (i32, [vp, u64]),
+        "ce_server_drain": (i32, [vp, C.c_double]),
+        "ce_server_stats": (i32, [vp, C.POINTER(ce_server_report)]),
+        "ce_server_error": (C.c_char_p, [vp]),
     }
     for name, (res, args) in sigs.items():
-        f = getattr(L, name)
+        try:
+            f = getattr(L, name)
+        except AttributeError:
+            if path == LIB_PATH:
+                raise
+            continue  # a test build with part of the ABI
         f.restype = res
         f.argtypes = args
     return L
@@ -324,3 +389,176 @@ class Engine:
         buf = (ce_package_rec * max(1, n))()
         n = self._L.ce_engine_trace(self._h, buf, n)
         return [(r.device, r.begin, r.end, r.t_claim, r.t_end) for r in buf[:n]]
+
+
+class Batch:
+    """Owns one ce_batch (the batched form); methods mirror the C calls."""
+
+    def __init__(self, stream=None, library=None):
+        self._L = library if library is not None else lib()
+        h = C.c_void_p()
+        st = self._L.ce_batch_create(C.byref(h), stream)
+        if st != CE_OK:
+            raise CoexecError(st, "ce_batch_create")
+        self._h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.ce_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, where):
+        if st != CE_OK:
+            msg = self._L.ce_batch_error(self._h)
+            raise CoexecError(st, where, [msg.decode()] if msg else [])
+        return st
+
+    def add_escape(self, params, dev_out) -> int:
+        idx = C.c_uint32()
+        self._keep.append(dev_out)
+        self._check(self._L.ce_batch_add_escape(self._h, C.byref(params), _ptr(dev_out), C.byref(idx)),
+                    "ce_batch_add_escape")
+        return int(idx.value)
+
+    def clear(self):
+        self._keep = []
+        return self._check(self._L.ce_batch_clear(self._h), "ce_batch_clear")
+
+    def set_config(self, tile_rows: int, package_tiles: int):
+        c = ce_batch_config(tile_rows, 0, package_tiles)
+        return self._check(self._L.ce_batch_set_config(self._h, C.byref(c)), "ce_batch_set_config")
+
+    def get_config(self):
+        c = ce_batch_config()
+        self._check(self._L.ce_batch_get_config(self._h, C.byref(c)), "ce_batch_get_config")
+        return (c.tile_rows, c.tile_cols, c.package_tiles)
+
+    def tune(self, reps: int = 3):
+        c = ce_batch_config()
+        self._check(self._L.ce_batch_tune(self._h, reps, C.byref(c)), "ce_batch_tune")
+        return (c.tile_rows, c.tile_cols, c.package_tiles)
+
+    def run(self):
+        return self._check(self._L.ce_batch_run(self._h), "ce_batch_run")
+
+    def run_separate(self):
+        return self._check(self._L.ce_batch_run_separate(self._h), "ce_batch_run_separate")
+
+    def stats(self) -> ce_batch_report:
+        s = ce_batch_report()
+        self._check(self._L.ce_batch_stats(self._h, C.byref(s)), "ce_batch_stats")
+        return s
+
+
+class Server:
+    """Owns one ce_server (the serving form); methods mirror the C calls.
+
+    Host inputs passed to ``submit`` are kept alive until the job finishes.
+    """
+
+    def __init__(self, hbm_budget: int, max_inflight: int = 0, keep_outputs: bool = False, max_jobs: int = 0,
+                 workgroups_per_cu: int = 0, session_timeout_s: float = 0.0, stream=None, library=None):
+        self._L = library if library is not None else lib()
+        cfg = ce_server_config(hbm_budget, max_inflight, 1 if keep_outputs else 0, max_jobs, workgroups_per_cu,
+                               session_timeout_s)
+        h = C.c_void_p()
+        st = self._L.ce_server_create(C.byref(cfg), stream, C.byref(h))
+        if st != CE_OK:
+            raise CoexecError(st, "ce_server_create")
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.ce_server_destroy(self._h)
+            self._h = None
+            self._keep = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st, where):
+        if st != CE_OK:
+            msg = self._L.ce_server_error(self._h)
+            raise CoexecError(st, where, [msg.decode()] if msg else [])
+        return st
+
+    def submit(self, kernel_id: int, params, in0=None, in1=None) -> int:
+        """Submits one job. Inputs that are device tensors stay resident and
+        are read in place; numpy arrays are copied into HBM at admission."""
+        j = ce_job()
+        j.kernel_id = kernel_id
+        if kernel_id == CE_KERNEL_ESCAPE:
+            j.esc = params
+        elif kernel_id == CE_KERNEL_BLUR5:
+            j.blur = params
+        elif kernel_id == CE_KERNEL_NBODY_ACC:
+            j.nb = params
+        keep = []
+        for slot, x in ((0, in0), (1, in1)):
+            if x is None:
+                continue
+            keep.append(x)
+            is_dev = hasattr(x, "is_cuda") and x.is_cuda
+            if is_dev:
+                setattr(j, f"in{slot}_dev", _ptr(x))
+            else:
+                setattr(j, f"in{slot}_host", _ptr(x))
+        t = C.c_uint64()
+        self._check(self._L.ce_server_submit(self._h, C.byref(j), C.byref(t)), "ce_server_submit")
+        if keep:
+            self._keep[int(t.value)] = keep
+        return int(t.value)
+
+    def status(self, ticket: int) -> int:
+        v = C.c_int32()
+        self._check(self._L.ce_server_status(self._h, ticket, C.byref(v)), "ce_server_status")
+        return int(v.value)
+
+    def wait(self, ticket: int, timeout_s: float = 60.0):
+        try:
+            return self._check(self._L.ce_server_wait(self._h, ticket, timeout_s), "ce_server_wait")
+        finally:
+            if self.status(ticket) in (CE_JOB_DONE, CE_JOB_FAILED):
+                self._keep.pop(ticket, None)
+
+    def output(self, ticket: int):
+        p, n = C.c_void_p(), C.c_size_t()
+        self._check(self._L.ce_server_output(self._h, ticket, C.byref(p), C.byref(n)), "ce_server_output")
+        return p.value, int(n.value)
+
+    def copy_output(self, ticket: int, dst):
+        """Copies a finished job's output into the numpy array ``dst``."""
+        self._check(self._L.ce_server_copy_output(self._h, ticket, _ptr(dst), _nbytes(dst)), "ce_server_copy_output")
+        return dst
+
+    def release(self, ticket: int):
+        self._keep.pop(ticket, None)
+        return self._check(self._L.ce_server_release(self._h, ticket), "ce_server_release")
+
+    def drain(self, timeout_s: float = 120.0):
+        try:
+            return self._check(self._L.ce_server_drain(self._h, timeout_s), "ce_server_drain")
+        finally:
+            self._keep = {}
+
+    def stats(self) -> ce_server_report:
+        r = ce_server_report()
+        self._check(self._L.ce_server_stats(self._h, C.byref(r)), "ce_server_stats")
+        return r

@@ -37,11 +37,11 @@ def _run(cmd, verbose):
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
-    for src in ("kernels.hip",):
+    for src in ("kernels.hip", "batch_kernels.hip", "serve_kernels.hip"):
         o = os.path.join(BUILD, src + ".o")
         _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], verbose)
         objs.append(o)
-    for src in ("host_payloads.cpp", "engine.cpp"):
+    for src in ("host_payloads.cpp", "engine.cpp", "batch.cpp", "serve.cpp"):
         o = os.path.join(BUILD, src + ".o")
         _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], verbose)
         objs.append(o)

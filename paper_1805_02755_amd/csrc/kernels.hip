@@ -16,307 +16,12 @@
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
+#include "device_payloads.hpp"
+#include "device_atomics.hpp"
+#include "device_tiles.hpp"
 #include "kernels.hpp"
 
 namespace ce {
-
-// ---------------------------------------------------------------- utilities
-__device__ __forceinline__ uint64_t now_tick() { return __builtin_amdgcn_s_memrealtime(); }
-
-// Memory ordering. On gfx950 each XCD has its own L2, so an agent-scope
-// acquire or release invalidates or writes back the L2; doing that per tile
-// would throttle the streaming payloads. The dispenser therefore uses relaxed
-// atomics on its hot path (agent- and system-scope atomics are performed at
-// the coherent memory side, so every access sees the latest value of its
-// location) and publishes package descriptors as single 64-bit words that
-// readers spin on. Acquire/release is used only for the claim lock (once
-// per package) and when a workgroup leaves (once per run).
-__device__ __forceinline__ uint64_t sys_load(uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-__device__ __forceinline__ void sys_store(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-__device__ __forceinline__ void sys_store_release(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-__device__ __forceinline__ uint64_t sys_fetch_add(uint64_t* p, uint64_t v) {
-  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-__device__ __forceinline__ bool sys_cas(uint64_t* p, uint64_t* expected, uint64_t desired) {
-  return __hip_atomic_compare_exchange_strong(p, expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_SYSTEM);
-}
-template <class U>
-__device__ __forceinline__ U dev_load(U* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <class U>
-__device__ __forceinline__ void dev_store(U* p, U v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <class U>
-__device__ __forceinline__ U dev_add(U* p, U v) {
-  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// ----------------------------------------------------------------- payloads
-// Escape-time count (Mandelbrot program, section 7.2): z <- z^2 + c from 0,
-// first n >= 1 with |z_n|^2 > 4, capped at max_iter.
-__device__ __forceinline__ uint32_t escape_count(float cr, float ci, uint32_t max_iter) {
-  float zr = 0.0f, zi = 0.0f;
-  uint32_t n = 0;
-  while (n < max_iter) {
-    const float x2 = zr * zr;
-    const float y2 = zi * zi;
-    if (x2 + y2 > 4.0f) break;
-    const float t = zr + zr;
-    zi = __builtin_fmaf(t, zi, ci);
-    zr = (x2 - y2) + cr;
-    ++n;
-  }
-  return n;
-}
-
-struct EscapeTile {
-  ce_escape_params p;
-  uint32_t* out;
-  __device__ void load_constants() {}
-  __host__ __device__ uint32_t ncb() const { return (uint32_t)ceil_div(p.w, kEscapeTileCols); }
-  __host__ __device__ uint64_t granules() const { return p.h; }
-  __host__ __device__ uint32_t ntiles(uint64_t g0, uint64_t g1) const {
-    return (uint32_t)(ceil_div(g1 - g0, kEscapeTileRows) * ncb());
-  }
-  // A tile is 16 rows x 64 columns; each wave covers four 8 x 8 blocks so
-  // the lanes of a wave iterate over neighbouring pixels.
-  __device__ void run(uint64_t g0, uint64_t g1, uint32_t t) const {
-    const uint32_t nc = ncb();
-    const uint64_t rb = g0 + (uint64_t)(t / nc) * kEscapeTileRows;
-    const uint32_t cb = (t % nc) * kEscapeTileCols;
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-#pragma unroll 1
-    for (uint32_t i = 0; i < 4; ++i) {
-      const uint32_t b = wave * 4u + i;
-      const uint64_t r = rb + (b >> 3) * 8u + (lane >> 3);
-      const uint32_t c = cb + (b & 7u) * 8u + (lane & 7u);
-      if (r < g1 && c < p.w) {
-        const float cr = p.x0 + (float)c * p.dx;
-        const float ci = p.y0 + (float)r * p.dy;
-        out[r * p.w + c] = escape_count(cr, ci, p.max_iter);
-      }
-    }
-  }
-};
-
-// 5x5 blur (Gaussian program, section 7.2): out(y,x) = sum over dy, dx of
-// w(dy,dx) in(clamp(y+dy), clamp(x+dx)), accumulated by fma with dy outer,
-// dx inner, ascending. Each thread owns 4 adjacent columns and walks down the
-// tile's rows with a 5-row window of 8 columns (x-2 .. x+5) in registers.
-// DPP controls (GFX9 data-parallel primitives): whole-wave shift by one lane.
-constexpr int kDppWaveShl1 = 0x130;  // lane i reads lane i+1
-constexpr int kDppWaveShr1 = 0x138;  // lane i reads lane i-1
-__device__ __forceinline__ float dpp_from_left(float edge, float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), kDppWaveShr1, 0xF, 0xF,
-                                                    false));
-}
-__device__ __forceinline__ float dpp_from_right(float edge, float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), kDppWaveShl1, 0xF, 0xF,
-                                                    false));
-}
-
-struct Blur5Tile {
-  ce_blur5_params p;
-  const float* in;
-  const float* wt;
-  float* out;
-  float w[25];
-  // Weights are read once per workgroup in uniform control flow, so they
-  // live in scalar registers and feed the FMAs as scalar operands.
-  __device__ void load_constants() {
-#pragma unroll
-    for (int k = 0; k < 25; ++k) w[k] = wt[k];
-  }
-  __host__ __device__ uint32_t ncb() const { return (uint32_t)ceil_div(p.w, kBlurTileCols); }
-  __host__ __device__ uint64_t granules() const { return p.h; }
-  __host__ __device__ uint32_t ntiles(uint64_t g0, uint64_t g1) const {
-    return (uint32_t)(ceil_div(g1 - g0, kBlurTileRows) * ncb());
-  }
-  __device__ __forceinline__ const float* row_ptr(int64_t yy) const {
-    yy = yy < 0 ? 0 : (yy >= (int64_t)p.h ? (int64_t)p.h - 1 : yy);
-    return in + (size_t)yy * p.w;
-  }
-  // One output row for this lane's 4 columns from a 5-row window of the 8
-  // input columns x-2 .. x+5, in the fixed tap order.
-  __device__ __forceinline__ void out4(const float* r0, const float* r1, const float* r2, const float* r3,
-                                       const float* r4, float o[4]) const {
-    const float* r[5] = {r0, r1, r2, r3, r4};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      float acc = 0.0f;
-#pragma unroll
-      for (int dy = 0; dy < 5; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 5; ++dx) acc = __builtin_fmaf(w[dy * 5 + dx], r[dy][q + dx], acc);
-      o[q] = acc;
-    }
-  }
-
-  // Fast path: the wave's 256 columns lie inside the image and rows are
-  // 16-byte aligned. Each lane loads its float4; the two columns on either
-  // side come from the neighbouring lanes by DPP, and the wave's outer halo
-  // from four uniform (scalar) loads clamped to the image.
-  struct Raw {
-    float4 c;
-    float l0, l1, r0, r1;
-  };
-  __device__ __forceinline__ void load_raw(int64_t yy, uint32_t x, uint32_t xw, Raw& a) const {
-    const float* row = row_ptr(yy);
-    a.c = *reinterpret_cast<const float4*>(row + x);
-    a.l0 = row[xw >= 2 ? xw - 2 : 0];
-    a.l1 = row[xw >= 1 ? xw - 1 : 0];
-    a.r0 = row[xw + 256 < p.w ? xw + 256 : p.w - 1];
-    a.r1 = row[xw + 257 < p.w ? xw + 257 : p.w - 1];
-  }
-  __device__ __forceinline__ void expand(const Raw& a, float v[8]) const {
-    v[0] = dpp_from_left(a.l0, a.c.z);
-    v[1] = dpp_from_left(a.l1, a.c.w);
-    v[2] = a.c.x;
-    v[3] = a.c.y;
-    v[4] = a.c.z;
-    v[5] = a.c.w;
-    v[6] = dpp_from_right(a.r0, a.c.x);
-    v[7] = dpp_from_right(a.r1, a.c.y);
-  }
-  __device__ void run_fast(uint64_t r0, uint64_t r1, uint32_t x, uint32_t xw) const {
-    // Rotating window of 6 rows: row y lives in slot (y - r0 + 2) mod 6; the
-    // row two below the current one is requested one step ahead.
-    float v[6][8];
-    Raw pend;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      Raw a;
-      load_raw((int64_t)r0 - 2 + j, x, xw, a);
-      expand(a, v[j]);
-    }
-    load_raw((int64_t)r0 + 2, x, xw, pend);
-    for (uint64_t yb = r0; yb < r1; yb += 6) {
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        const uint64_t y = yb + k;
-        if (y >= r1) break;
-        expand(pend, v[(k + 4) % 6]);  // row y + 2
-        if (y + 1 < r1) load_raw((int64_t)y + 3, x, xw, pend);
-        float o[4];
-        out4(v[k % 6], v[(k + 1) % 6], v[(k + 2) % 6], v[(k + 3) % 6], v[(k + 4) % 6], o);
-        *reinterpret_cast<float4*>(out + (size_t)y * p.w + x) = make_float4(o[0], o[1], o[2], o[3]);
-      }
-    }
-  }
-
-  // General path (ragged widths, the wave holding the image's right edge when
-  // the width is not a multiple of 4): per-element clamped loads.
-  __device__ void load8(int64_t yy, uint32_t x, float v[8]) const {
-    const float* row = row_ptr(yy);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      int64_t xx = (int64_t)x - 2 + k;
-      xx = xx < 0 ? 0 : (xx >= (int64_t)p.w ? (int64_t)p.w - 1 : xx);
-      v[k] = row[xx];
-    }
-  }
-  __device__ void run_general(uint64_t r0, uint64_t r1, uint32_t x) const {
-    if (x >= p.w) return;
-    float win[5][8];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) load8((int64_t)r0 - 2 + j, x, win[j + 1]);
-    for (uint64_t y = r0; y < r1; ++y) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int k = 0; k < 8; ++k) win[j][k] = win[j + 1][k];
-      load8((int64_t)y + 2, x, win[4]);
-      float o[4];
-      out4(win[0], win[1], win[2], win[3], win[4], o);
-      float* orow = out + (size_t)y * p.w;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (x + q < p.w) orow[x + q] = o[q];
-    }
-  }
-
-  __device__ void run(uint64_t g0, uint64_t g1, uint32_t t) const {
-    const uint32_t nc = ncb();
-    const uint64_t r0 = g0 + (uint64_t)(t / nc) * kBlurTileRows;
-    const uint64_t r1 = (r0 + kBlurTileRows < g1) ? r0 + kBlurTileRows : g1;
-    // first column of this wave (uniform) and of this lane
-    const uint32_t xw = (t % nc) * kBlurTileCols + (__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u) * 4u;
-    const uint32_t x = xw + (threadIdx.x & 63u) * 4u;
-    if (xw >= p.w) return;
-    if ((p.w & 3u) == 0 && xw + 256 <= p.w)
-      run_fast(r0, r1, x, xw);
-    else
-      run_general(r0, r1, x);
-  }
-};
-
-// Lomont, "Fast Inverse Square Root" (2003): integer estimate then three
-// Newton-Raphson steps y <- y (1.5 - (x/2) y^2) written as t = y*y,
-// u = fma(-(x/2), t, 1.5), y = y*u. Same operation sequence as the host.
-__device__ __forceinline__ float rsqrt_lomont(float x) {
-  const uint32_t b = 0x5f375a86u - (__float_as_uint(x) >> 1);
-  float y = __uint_as_float(b);
-  const float hx = 0.5f * x;
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    const float t = y * y;
-    const float u = __builtin_fmaf(-hx, t, 1.5f);
-    y = y * u;
-  }
-  return y;
-}
-
-// All-pairs acceleration (NBody program, force part): body i accumulates
-// m_j d_ij / (|d_ij|^2 + eps2)^(3/2) over j ascending in one FP32 sum per
-// component. A granule is 256 bodies, one per thread; positions of the j
-// bodies are staged through LDS 256 at a time.
-template <bool STRICT>
-struct NbodyTile {
-  ce_nbody_params p;
-  const float4* pos;
-  float4* out;
-  __device__ void load_constants() {}
-  __host__ __device__ uint64_t granules() const { return ceil_div(p.n, kNbodyGranule); }
-  __host__ __device__ uint32_t ntiles(uint64_t g0, uint64_t g1) const { return (uint32_t)(g1 - g0); }
-  __device__ void run(uint64_t g0, uint64_t, uint32_t t) const {
-    __shared__ float4 sh[kNbodyGranule];
-    const uint64_t i = (g0 + t) * kNbodyGranule + threadIdx.x;
-    const bool active = i < p.n;
-    const float4 pi = active ? pos[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-    const float eps2 = p.eps2;
-    float ax = 0.0f, ay = 0.0f, az = 0.0f;
-    for (uint32_t j0 = 0; j0 < p.n; j0 += kNbodyGranule) {
-      __syncthreads();
-      if (j0 + threadIdx.x < p.n) sh[threadIdx.x] = pos[j0 + threadIdx.x];
-      __syncthreads();
-      const uint32_t m = (p.n - j0 < kNbodyGranule) ? p.n - j0 : kNbodyGranule;
-#pragma unroll 8
-      for (uint32_t jj = 0; jj < m; ++jj) {
-        const float4 pj = sh[jj];
-        const float dx = pj.x - pi.x;
-        const float dy = pj.y - pi.y;
-        const float dz = pj.z - pi.z;
-        const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
-        const float rinv = STRICT ? rsqrt_lomont(r2) : __builtin_amdgcn_rsqf(r2);
-        const float s = (rinv * rinv) * rinv;
-        const float f = pj.w * s;
-        ax = __builtin_fmaf(f, dx, ax);
-        ay = __builtin_fmaf(f, dy, ay);
-        az = __builtin_fmaf(f, dz, az);
-      }
-    }
-    if (active) out[i] = make_float4(ax, ay, az, 0.0f);
-  }
-};
 
 // ---------------------------------------------------------------- dispenser
 // Claims the next level-1 package for the GPU. Only the holder of the claim

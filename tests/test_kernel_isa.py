@@ -1,5 +1,6 @@
 """Static checks of the gfx950 code the compiler emits for the persistent
-kernels (CPU only: hipcc cross-compiles).
+kernels of the co-execution, batched and serving forms (CPU only: hipcc
+cross-compiles).
 
 A workgroup barrier inside a loop whose exit is decided per lane (an exec-mask
 update followed by a branch on an empty mask) lets some lanes leave the loop
@@ -14,19 +15,27 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SRC = os.path.join(ROOT, "paper_1805_02755_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1805_02755_amd", "csrc")
 HIPCC = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
+# source file -> (persistent kernel name fragment, number of instantiations)
+SOURCES = {"kernels.hip": ("k_persistent", 4), "batch_kernels.hip": ("k_batch_escape", 5),
+           "serve_kernels.hip": ("k_serve", 1)}
 
 
 @pytest.fixture(scope="module")
 def asm(tmp_path_factory):
     if not os.path.exists(HIPCC):
         pytest.skip("hipcc not available")
-    out = tmp_path_factory.mktemp("isa") / "kernels.s"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang", "-target-feature",
-           "-Xclang", "-packed-fp32-ops", "--cuda-device-only", "-S", "-o", str(out), SRC]
-    subprocess.run(cmd, check=True, capture_output=True)
-    return out.read_text()
+    d = tmp_path_factory.mktemp("isa")
+    texts = {}
+    for src in SOURCES:
+        out = d / (src + ".s")
+        cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang",
+               "-target-feature", "-Xclang", "-packed-fp32-ops", "--cuda-device-only", "-S", "-o", str(out),
+               os.path.join(CSRC, src)]
+        subprocess.run(cmd, check=True, capture_output=True)
+        texts[src] = out.read_text()
+    return texts
 
 
 def _functions(text):
@@ -57,9 +66,11 @@ def _blocks(body):
     return blocks
 
 
-def test_persistent_loops_have_uniform_exits_around_barriers(asm):
-    funcs = {k: v for k, v in _functions(asm).items() if "k_persistent" in k}
-    assert len(funcs) == 4, sorted(funcs)
+@pytest.mark.parametrize("src", sorted(SOURCES))
+def test_persistent_loops_have_uniform_exits_around_barriers(asm, src):
+    frag, count = SOURCES[src]
+    funcs = {k: v for k, v in _functions(asm[src]).items() if frag in k}
+    assert len(funcs) == count, sorted(funcs)
     for name, body in funcs.items():
         blocks = _blocks(body)
         barrier_loops = {hdr for _, hdr, lines in blocks if hdr and any(l.startswith("s_barrier") for l in lines)}
@@ -71,8 +82,16 @@ def test_persistent_loops_have_uniform_exits_around_barriers(asm):
             assert not bad, f"{name}: loop {hdr} holds a barrier and a per-lane exit in {label}"
 
 
-def test_no_packed_fp32_and_no_spills(asm):
-    for name, body in _functions(asm).items():
+@pytest.mark.parametrize("src", sorted(SOURCES))
+def test_no_packed_fp32_and_no_spills(asm, src):
+    for name, body in _functions(asm[src]).items():
         for op in ("v_pk_fma_f32", "v_pk_mul_f32", "v_pk_add_f32"):
             assert op not in body, (name, op)
-    assert "scratch_store" not in asm
+    assert "scratch_store" not in asm[src]
+
+
+def test_serving_kernel_drops_stale_lines_at_job_switch(asm):
+    """Inputs copied in during a session are read after a system-scope
+    invalidate (the job-switch acquire)."""
+    body = next(v for k, v in _functions(asm["serve_kernels.hip"]).items() if "k_serve" in k)
+    assert "buffer_inv sc0 sc1" in body
