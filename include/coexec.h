@@ -305,7 +305,7 @@ ce_status ce_server_create(const ce_server_config* cfg, void* hip_stream, ce_ser
 void ce_server_destroy(ce_server* s);
 /* CE_E_BUDGET if the job alone needs more than the HBM budget. */
 ce_status ce_server_submit(ce_server* s, const ce_job* job, uint64_t* ticket);
-ce_status ce_server_status(ce_server* s, uint64_t ticket, int32_t* state);
+ce_status ce_server_poll(ce_server* s, uint64_t ticket, int32_t* state);
 ce_status ce_server_wait(ce_server* s, uint64_t ticket, double timeout_s);
 /* Device output of a finished job (keep_outputs only); valid until release. */
 ce_status ce_server_output(ce_server* s, uint64_t ticket, void** dev_ptr, size_t* bytes);

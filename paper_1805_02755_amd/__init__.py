@@ -51,7 +51,7 @@ EXPORTED_SYMBOLS = (
     "ce_gauss5_weights", "ce_version", "ce_batch_create", "ce_batch_destroy", "ce_batch_add_escape",
     "ce_batch_clear", "ce_batch_set_config", "ce_batch_get_config", "ce_batch_tune", "ce_batch_run",
     "ce_batch_run_separate", "ce_batch_stats", "ce_batch_error", "ce_server_create", "ce_server_destroy",
-    "ce_server_submit", "ce_server_status", "ce_server_wait", "ce_server_output", "ce_server_copy_output",
+    "ce_server_submit", "ce_server_poll", "ce_server_wait", "ce_server_output", "ce_server_copy_output",
     "ce_server_release", "ce_server_drain", "ce_server_stats", "ce_server_error",
 )
 
@@ -181,7 +181,7 @@ def load(path: str):
         "ce_server_create": (i32, [C.POINTER(ce_server_config), vp, C.POINTER(vp)]),
         "ce_server_destroy": (None, [vp]),
         "ce_server_submit": (i32, [vp, C.POINTER(ce_job), C.POINTER(u64)]),
-        "ce_server_status": (i32, [vp, u64, C.POINTER(i32)]),
+        "ce_server_poll": (i32, [vp, u64, C.POINTER(i32)]),
         "ce_server_wait": (i32, [vp, u64, C.c_double]),
         "ce_server_output": (i32, [vp, u64, C.POINTER(vp), C.POINTER(sz)]),
         "ce_server_copy_output": (i32, [vp, u64, vp, sz]),
@@ -526,16 +526,16 @@ class Server:
             self._keep[int(t.value)] = keep
         return int(t.value)
 
-    def status(self, ticket: int) -> int:
+    def poll(self, ticket: int) -> int:
         v = C.c_int32()
-        self._check(self._L.ce_server_status(self._h, ticket, C.byref(v)), "ce_server_status")
+        self._check(self._L.ce_server_poll(self._h, ticket, C.byref(v)), "ce_server_poll")
         return int(v.value)
 
     def wait(self, ticket: int, timeout_s: float = 60.0):
         try:
             return self._check(self._L.ce_server_wait(self._h, ticket, timeout_s), "ce_server_wait")
         finally:
-            if self.status(ticket) in (CE_JOB_DONE, CE_JOB_FAILED):
+            if self.poll(ticket) in (CE_JOB_DONE, CE_JOB_FAILED):
                 self._keep.pop(ticket, None)
 
     def output(self, ticket: int):

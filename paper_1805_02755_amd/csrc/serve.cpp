@@ -498,7 +498,7 @@ ce_status ce_server_submit(ce_server* s, const ce_job* job, uint64_t* ticket) {
   }
 }
 
-ce_status ce_server_status(ce_server* s, uint64_t ticket, int32_t* state) {
+ce_status ce_server_poll(ce_server* s, uint64_t ticket, int32_t* state) {
   if (!s || !state) return CE_E_INVALID;
   std::lock_guard<std::mutex> lk(s->mu);
   if (ticket >= s->jobs.size()) return CE_E_INVALID;
