@@ -58,27 +58,30 @@ __device__ __forceinline__ float dpp_from_right(float edge, float v) {
                                                     false));
 }
 
-struct Blur5Tile {
+// kFresh: the input may have been written after the launch began (the
+// serving kernel reuses memory while it runs), so wave-uniform reads, which
+// the compiler would serve from the scalar cache, use coherent vector loads.
+template <bool kFresh>
+struct Blur5TileT {
   ce_blur5_params p;
   const float* in;
   const float* wt;
   float* out;
   float w[25];
+  __device__ __forceinline__ float uniform_load(const float* a) const {
+    if constexpr (kFresh) {
+      const uint32_t v = __hip_atomic_load(const_cast<uint32_t*>(reinterpret_cast<const uint32_t*>(a)),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return __uint_as_float(__builtin_amdgcn_readfirstlane(v));
+    } else {
+      return *a;
+    }
+  }
   // Weights are read once per workgroup in uniform control flow, so they
   // live in scalar registers and feed the FMAs as scalar operands.
   __device__ void load_constants() {
 #pragma unroll
-    for (int k = 0; k < 25; ++k) w[k] = wt[k];
-  }
-  // Same, with loads that bypass the scalar cache: for weights that may
-  // have been written after the launch began.
-  __device__ void load_constants_coherent() {
-#pragma unroll
-    for (int k = 0; k < 25; ++k) {
-      const uint32_t v = __hip_atomic_load(const_cast<uint32_t*>(reinterpret_cast<const uint32_t*>(wt)) + k, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-      w[k] = __uint_as_float(__builtin_amdgcn_readfirstlane(v));
-    }
+    for (int k = 0; k < 25; ++k) w[k] = uniform_load(wt + k);
   }
   __host__ __device__ uint32_t ncb() const { return (uint32_t)ceil_div(p.w, kBlurTileCols); }
   __host__ __device__ uint64_t granules() const { return p.h; }
@@ -116,10 +119,10 @@ struct Blur5Tile {
   __device__ __forceinline__ void load_raw(int64_t yy, uint32_t x, uint32_t xw, Raw& a) const {
     const float* row = row_ptr(yy);
     a.c = *reinterpret_cast<const float4*>(row + x);
-    a.l0 = row[xw >= 2 ? xw - 2 : 0];
-    a.l1 = row[xw >= 1 ? xw - 1 : 0];
-    a.r0 = row[xw + 256 < p.w ? xw + 256 : p.w - 1];
-    a.r1 = row[xw + 257 < p.w ? xw + 257 : p.w - 1];
+    a.l0 = uniform_load(row + (xw >= 2 ? xw - 2 : 0));
+    a.l1 = uniform_load(row + (xw >= 1 ? xw - 1 : 0));
+    a.r0 = uniform_load(row + (xw + 256 < p.w ? xw + 256 : p.w - 1));
+    a.r1 = uniform_load(row + (xw + 257 < p.w ? xw + 257 : p.w - 1));
   }
   __device__ __forceinline__ void expand(const Raw& a, float v[8]) const {
     v[0] = dpp_from_left(a.l0, a.c.z);
@@ -202,6 +205,9 @@ struct Blur5Tile {
       run_general(r0, r1, x);
   }
 };
+
+using Blur5Tile = Blur5TileT<false>;
+using Blur5TileFresh = Blur5TileT<true>;
 
 // Lomont, "Fast Inverse Square Root" (2003): integer estimate then three
 // Newton-Raphson steps y <- y (1.5 - (x/2) y^2) written as t = y*y,

@@ -102,8 +102,8 @@ __device__ void serve_tile(const ServeDesc& d, uint32_t ti) {
     EscapeTile e{d.esc, (uint32_t*)d.out};
     e.run(0, d.granules, ti);
   } else if (kind == CE_KERNEL_BLUR5) {
-    Blur5Tile b{d.blur, (const float*)d.in0, (const float*)d.in1, (float*)d.out, {}};
-    b.load_constants_coherent();
+    Blur5TileFresh b{d.blur, (const float*)d.in0, (const float*)d.in1, (float*)d.out, {}};
+    b.load_constants();
     b.run(0, d.granules, ti);
   } else if (__builtin_amdgcn_readfirstlane(d.strict)) {
     NbodyTile<true> nbt{d.nb, (const float4*)d.in0, (float4*)d.out};
