@@ -64,6 +64,7 @@ class HipEvents:
         self.L.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
         self.L.hipEventSynchronize.argtypes = [C.c_void_p]
         self.L.hipEventDestroy.argtypes = [C.c_void_p]
+        self.L.hipEventRecord.argtypes = [C.c_void_p, C.c_void_p]
 
     def create(self):
         ev = self.C.c_void_p()
@@ -76,6 +77,10 @@ class HipEvents:
         if self.L.hipEventSynchronize(b) != 0 or self.L.hipEventElapsedTime(self.C.byref(f), a, b) != 0:
             raise RuntimeError("hipEventElapsedTime failed")
         return float(f.value)
+
+    def record(self, ev, stream):
+        if self.L.hipEventRecord(ev, stream) != 0:
+            raise RuntimeError("hipEventRecord failed")
 
     def destroy(self, ev):
         self.L.hipEventDestroy(ev)
@@ -207,12 +212,30 @@ def main():
         ins_dev_b = [torch.empty(a.shape, dtype=torch.from_numpy(a).dtype, device=dev) for a in ins_host]
         out_h_b = np.empty_like(out_h)
     t_bare = timed_runs(bare, W, K, sync)
+    hev = HipEvents()
+    ev_s = [hev.create() for _ in range(K)]
+    ev_e = [hev.create() for _ in range(K)]
+    # kernel time of the plain launch, from events on its stream
+    for i in range(K):
+        hev.record(ev_s[i], stream.cuda_stream)
+        ce.ce_bare_run(kid, params, ins_dev if args.mode != "host" else ins_dev_b, out_d, stream=stream.cuda_stream,
+                       sync=False)
+        hev.record(ev_e[i], stream.cuda_stream)
+    sync()
+    k_bare_ms = med([hev.elapsed_ms(ev_s[i], ev_e[i]) for i in range(K)])
 
     # ------------------------------------------------- engine, GPU alone
     log("engine GPU only")
     eng.use(ce.CE_DEV_GPU, 0, 0)
     eng.scheduler(ce.CE_SCHED_STATIC)
     t_gpu = timed_runs(eng.run, W, K, sync)
+    k_gpu = []
+    for i in range(K):
+        eng.kernel_events(ev_s[i], ev_e[i])
+        eng.run()
+        k_gpu.append(hev.elapsed_ms(ev_s[i], ev_e[i]))
+    eng.kernel_events(None, None)
+    k_gpu_ms = med(k_gpu)
 
     # ------------------------------------------------- engine, host alone
     log("engine host only")
@@ -233,9 +256,6 @@ def main():
     log(f"co-execution {coexec}")
     for _ in range(W):
         eng.run()
-    hev = HipEvents()
-    ev_s = [hev.create() for _ in range(K)]
-    ev_e = [hev.create() for _ in range(K)]
     per_run, stats = [], []
     sync()
     t0 = time.perf_counter()
@@ -342,7 +362,9 @@ def main():
             "efficiency": s_real / s_max,
             "overhead_pct_gpu_only": (T_gpu - T_bare) / T_bare * 100.0,
             "t_bare_ms": T_bare * 1e3,
+            "t_bare_kernel_ms": k_bare_ms,
             "t_engine_gpu_ms": T_gpu * 1e3,
+            "t_engine_gpu_kernel_ms": k_gpu_ms,
             "t_engine_host_ms": T_host * 1e3,
             "t_coexec_ms_median": med(per_run) * 1e3,
             "host_threads": host_threads_used,

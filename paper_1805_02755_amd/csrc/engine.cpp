@@ -169,6 +169,7 @@ struct ce_engine {
   PinnedBuf ring_buf;           // host completion ring read by the GPU's gatherers
   bool gather = false;          // this run's host tiles are copied into HBM by the GPU
   std::atomic<uint64_t> ring_count{0};
+  std::atomic<uint64_t> ring_written{0};  // entries whose ring word is stored
 
   // ---- host pool
   std::vector<std::thread> pool;
@@ -388,6 +389,7 @@ struct ce_engine {
     const uint64_t k = ring_count.fetch_add(1, std::memory_order_relaxed);
     uint64_t* ring = (uint64_t*)ring_buf.p;
     __atomic_store_n(&ring[k], ring_word(off, len), __ATOMIC_RELEASE);
+    ring_written.fetch_add(1, std::memory_order_release);
   }
 
   // Host side of a run: every pool thread (and the caller) runs this loop.
@@ -686,6 +688,7 @@ struct ce_engine {
       }
     }
     ring_count.store(0, std::memory_order_relaxed);
+    ring_written.store(0, std::memory_order_relaxed);
     if (use_host()) {
       if (!hq.ensure(hmax)) return fail(CE_E_NOMEM, "run: host package table");
     }
@@ -713,10 +716,16 @@ struct ce_engine {
         cv.notify_all();
       }
       host_work();
+      if (gather) {
+        // The host chain is closed, so its tile count is final: tell the
+        // gatherers as soon as the last tile is in the ring, without waiting
+        // for pool threads that have not noticed the end yet.
+        const uint64_t n_tiles = hq.total.load(std::memory_order_acquire);
+        while (ring_written.load(std::memory_order_acquire) < n_tiles) cpu_relax();
+        __atomic_store_n(&l1->host_final, host_final_word(run_id, n_tiles), __ATOMIC_RELEASE);
+      }
       const uint32_t want = (uint32_t)pool.size();
       while (pool_done.load(std::memory_order_acquire) < want) cpu_relax();
-      if (gather)
-        __atomic_store_n(&l1->host_final, host_final_word(run_id, ring_count.load()), __ATOMIC_RELEASE);
     }
     if (use_gpu()) {
       // the last workgroup out writes the run id; poll it, then sync

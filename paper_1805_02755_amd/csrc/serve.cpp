@@ -87,6 +87,54 @@ struct Arena {
   }
 };
 
+// Pinned staging for copies between pageable client memory and HBM while
+// the serving kernel runs: the client's buffer is copied through two pinned
+// halves by the CPU, and the DMA side only ever sees pinned memory.
+struct Staging {
+  static constexpr size_t kHalf = 16u << 20;
+  char* buf[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipError_t init() {
+    hipError_t he;
+    for (int i = 0; i < 2; ++i) {
+      if ((he = hipHostMalloc((void**)&buf[i], kHalf, hipHostMallocDefault)) != hipSuccess) return he;
+      if ((he = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming)) != hipSuccess) return he;
+    }
+    return hipSuccess;
+  }
+  void destroy() {
+    for (int i = 0; i < 2; ++i) {
+      if (ev[i]) (void)hipEventDestroy(ev[i]);
+      if (buf[i]) (void)hipHostFree(buf[i]);
+    }
+  }
+  hipError_t to_device(void* dst, const void* src, size_t n, hipStream_t st) {
+    hipError_t he = hipSuccess;
+    bool used[2] = {false, false};
+    for (size_t off = 0, k = 0; off < n; off += kHalf, ++k) {
+      const int b = (int)(k & 1);
+      const size_t len = std::min(kHalf, n - off);
+      if (used[b] && (he = hipEventSynchronize(ev[b])) != hipSuccess) return he;  // this half was sent
+      memcpy(buf[b], (const char*)src + off, len);
+      if ((he = hipMemcpyAsync((char*)dst + off, buf[b], len, hipMemcpyHostToDevice, st)) != hipSuccess) return he;
+      if ((he = hipEventRecord(ev[b], st)) != hipSuccess) return he;
+      used[b] = true;
+    }
+    return hipStreamSynchronize(st);
+  }
+  hipError_t to_host(void* dst, const void* src, size_t n, hipStream_t st) {
+    hipError_t he = hipSuccess;
+    for (size_t off = 0; off < n; off += kHalf) {
+      const size_t len = std::min(kHalf, n - off);
+      if ((he = hipMemcpyAsync(buf[0], (const char*)src + off, len, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+          (he = hipStreamSynchronize(st)) != hipSuccess)
+        return he;
+      memcpy((char*)dst + off, buf[0], len);
+    }
+    return hipSuccess;
+  }
+};
+
 struct JobRec {
   ce_job job{};
   ServeDesc desc{};
@@ -143,7 +191,8 @@ struct ce_server {
   uint64_t* done_dev = nullptr;
 
   std::mutex mu;
-  std::mutex copy_mu;                // serialises use of copy_stream
+  std::mutex copy_mu;                // serialises use of copy_stream and staging
+  Staging staging;
   std::condition_variable cv;
   std::vector<JobRec> jobs;          // by ticket
   std::deque<uint64_t> pending;      // tickets waiting for admission
@@ -195,6 +244,7 @@ struct ce_server {
     }
     if ((he = hipStreamCreateWithFlags(&copy_stream, hipStreamNonBlocking)) != hipSuccess)
       return fail(CE_E_DEVICE, "stream: %s", hipGetErrorString(he));
+    if ((he = staging.init()) != hipSuccess) return fail(CE_E_NOMEM, "pinned staging: %s", hipGetErrorString(he));
     if ((he = hipMalloc((void**)&arena.base, cfg.hbm_budget)) != hipSuccess)
       return fail(CE_E_NOMEM, "HBM budget of %llu bytes: %s", (unsigned long long)cfg.hbm_budget,
                   hipGetErrorString(he));
@@ -228,6 +278,7 @@ struct ce_server {
     cv.notify_all();
     if (worker.joinable()) worker.join();
     if (stream) (void)hipStreamSynchronize(stream);
+    staging.destroy();
     if (copy_stream) (void)hipStreamDestroy(copy_stream);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
     if (arena.base) (void)hipFree(arena.base);
@@ -324,13 +375,10 @@ struct ce_server {
     lk.unlock();
     std::unique_lock<std::mutex> ck(copy_mu);
     bool ok = true;
-    if (copy0 && hipMemcpyAsync((void*)d.in0, r.job.in0_host, in_bytes_of(r.job, 0), hipMemcpyHostToDevice,
-                                copy_stream) != hipSuccess)
+    if (copy0 && staging.to_device((void*)d.in0, r.job.in0_host, in_bytes_of(r.job, 0), copy_stream) != hipSuccess)
       ok = false;
-    if (copy1 && hipMemcpyAsync((void*)d.in1, r.job.in1_host, in_bytes_of(r.job, 1), hipMemcpyHostToDevice,
-                                copy_stream) != hipSuccess)
+    if (ok && copy1 && staging.to_device((void*)d.in1, r.job.in1_host, in_bytes_of(r.job, 1), copy_stream) != hipSuccess)
       ok = false;
-    if ((copy0 || copy1) && hipStreamSynchronize(copy_stream) != hipSuccess) ok = false;
     ck.unlock();
     lk.lock();
     if (ok && !session_on) {  // the session ended while the inputs were copied: retry in the next one
@@ -537,8 +585,7 @@ ce_status ce_server_copy_output(ce_server* s, uint64_t ticket, void* host_dst, s
     src = r.desc.out;
   }
   std::lock_guard<std::mutex> ck(s->copy_mu);
-  hipError_t he = hipMemcpyAsync(host_dst, src, bytes, hipMemcpyDeviceToHost, s->copy_stream);
-  if (he == hipSuccess) he = hipStreamSynchronize(s->copy_stream);
+  const hipError_t he = s->staging.to_host(host_dst, src, bytes, s->copy_stream);
   if (he != hipSuccess) return s->fail(CE_E_DEVICE, "copy_output: %s", hipGetErrorString(he));
   return CE_OK;
 }

@@ -72,6 +72,24 @@ def run_payload(eng, kernel_id, params, gws, lws, inputs, out_shape, out_dtype, 
     return res, st, tr
 
 
+def diff_report(out, ref, tr=None):
+    """Text naming where two 2-D (rows x items) outputs differ, for assertion
+    messages: mismatching rows, whether they hold the untouched fill
+    pattern, and which device's package covered them in the trace."""
+    a = np.ascontiguousarray(out).view(np.uint32).reshape(out.shape[0], -1)
+    b = np.ascontiguousarray(ref).view(np.uint32).reshape(ref.shape[0], -1)
+    bad = np.nonzero((a != b).any(axis=1))[0]
+    lines = [f"{len(bad)} of {a.shape[0]} rows differ: {bad[:24].tolist()}"]
+    for r in bad[:6]:
+        cols = np.nonzero(a[r] != b[r])[0]
+        unfilled = int((a[r, cols] == 0xFFFFFFFF).sum())
+        lines.append(f"row {r}: {len(cols)} items differ (first {cols[:8].tolist()}), {unfilled} still 0xFFFFFFFF, "
+                     f"got {a[r, cols[:3]].tolist()} want {b[r, cols[:3]].tolist()}")
+    if tr is not None:
+        lines.append("trace (device, begin, end): " + str([(d, b_, e) for d, b_, e, _, _ in tr][:64]))
+    return "\n".join(lines)
+
+
 def check_trace(tr, G, n_dev):
     """Packages of the trace cover [0, G) exactly once; devices are valid."""
     cnt = np.zeros(G, dtype=np.int32)

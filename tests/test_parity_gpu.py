@@ -10,7 +10,7 @@ import paper_1805_02755_amd as ce
 from paper_1805_02755_amd import synth
 from oracle import oracle as O
 
-from gpu_util import BOTH, DEV, SCHEDULES, check_trace, escape_params, run_payload
+from gpu_util import BOTH, DEV, SCHEDULES, check_trace, diff_report, escape_params, run_payload
 
 pytestmark = pytest.mark.gpu
 
@@ -37,7 +37,7 @@ def test_escape_1024_all_schedules(eng, escape_small_ref, devs, sched):
     p, ref = escape_small_ref
     out, st, tr = run_payload(eng, ce.CE_KERNEL_ESCAPE, escape_params(p), [p.w, p.h], None, [], (p.h, p.w),
                               np.uint32, DEVSETS[devs], sched)
-    assert np.array_equal(out, ref)
+    assert np.array_equal(out, ref), diff_report(out, ref, tr)
     check_trace(tr, p.h, st.n_devices)
     assert sum(st.granules[:st.n_devices]) == p.h
     assert sum(st.items[:st.n_devices]) == p.w * p.h
@@ -51,7 +51,7 @@ def test_escape_ragged_residency(eng, mode):
     for sched in ("hguided", "dynamic", "static"):
         out, st, tr = run_payload(eng, ce.CE_KERNEL_ESCAPE, escape_params(p), [p.w, p.h], None, [], (p.h, p.w),
                                   np.uint32, BOTH, sched, mode=mode)
-        assert np.array_equal(out, ref), sched
+        assert np.array_equal(out, ref), (sched, diff_report(out, ref, tr))
         check_trace(tr, p.h, 2)
 
 
@@ -76,7 +76,7 @@ def test_blur_shapes(eng, w, h):
         for sched in ("hguided", "dynamic", "static_rev"):
             out, st, tr = run_payload(eng, ce.CE_KERNEL_BLUR5, ce.ce_blur5_params(w, h), [w, h], None, [img, wt],
                                       (h, w), np.float32, DEVSETS[devs], sched)
-            assert np.array_equal(out.view(np.uint32), ref.view(np.uint32)), (devs, sched)
+            assert np.array_equal(out.view(np.uint32), ref.view(np.uint32)), (devs, sched, diff_report(out, ref, tr))
             check_trace(tr, h, st.n_devices)
 
 
@@ -97,7 +97,7 @@ def test_blur_full_size_8192(eng):
     ref = O.blur5(img, O.gauss5_weights(1.0))
     out, st, tr = run_payload(eng, ce.CE_KERNEL_BLUR5, ce.ce_blur5_params(w, h), [w, h], None, [img, wt], (h, w),
                               np.float32, BOTH, "hguided_default")
-    assert np.array_equal(out.view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(out.view(np.uint32), ref.view(np.uint32)), diff_report(out, ref, tr)
     check_trace(tr, h, 2)
 
 
@@ -111,7 +111,7 @@ def test_nbody_strict_bitexact(eng, n):
         for sched in ("dynamic", "hguided", "static"):
             out, st, tr = run_payload(eng, ce.CE_KERNEL_NBODY_ACC, ce.ce_nbody_params(n, 1e-6, 1), [n], [256], [pos],
                                       (n, 4), np.float32, DEVSETS[devs], sched)
-            assert np.array_equal(out.view(np.uint32), ref.view(np.uint32)), (devs, sched)
+            assert np.array_equal(out.view(np.uint32), ref.view(np.uint32)), (devs, sched, diff_report(out, ref, tr))
             check_trace(tr, G, st.n_devices)
 
 
