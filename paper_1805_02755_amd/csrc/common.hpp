@@ -58,20 +58,28 @@ CE_HD uint64_t ring_off(uint64_t w) { return w & ((1ull << 40) - 1); }
 CE_HD uint64_t ring_len(uint64_t w) { return w >> 40; }
 
 // Per-run GPU queue state in HBM (device-scope atomics only). The last
-// workgroup to leave a run resets it to zero for the next run.
-struct alignas(64) L2State {
+// workgroup to leave a run resets it to zero for the next run. Contended
+// atomics on one cache line serialise at the memory side, so the ticket
+// counter, the read-mostly publication state, the claim lock and the
+// bookkeeping each get a line of their own.
+struct alignas(128) L2State {
   uint64_t ticket;      // next tile ticket
+  uint64_t pad_ticket[15];
   uint64_t total;       // tiles of all published packages
-  uint32_t n_pkgs;      // packages published
   uint32_t done;        // no more packages for this device
+  uint32_t pad_done;
+  uint64_t pad_total[14];
+  uint32_t lock;        // held by the workgroup claiming the next package
+  uint32_t pad_lock[31];
+  uint32_t n_pkgs;      // packages published
   uint32_t exit_count;  // workgroups that left
   uint32_t st_next;     // static: next band of this device
+  uint32_t pad0;
   uint64_t granules;    // granules published
   uint64_t t_first;     // first claim tick
   uint64_t t_last;      // latest package end tick
-  uint32_t lock;        // held by the workgroup claiming the next package
-  uint32_t pad0;
   uint64_t gather_next; // next host completion-ring entry to copy
+  uint64_t pad_misc[10];
 };
 
 // A published GPU package as one 64-bit word: granule count in the top 24
@@ -114,6 +122,8 @@ struct SchedArgs {
   uint64_t* pub;        // publication words, zero between runs
   uint32_t max_pkgs;
   uint32_t lookahead;   // claim the next package this many tiles early
+  uint32_t chunk;       // tile tickets taken per atomic
+  uint32_t pad_chunk;
   // gather of host-computed output into HBM (gather_wgs == 0: off)
   const uint64_t* ring; // device view of the host completion ring
   const char* gsrc;     // device view of the host output buffer

@@ -668,6 +668,9 @@ struct ce_engine {
       gs.max_pkgs = pkgs_dev_cap;
       // claim the next package while a quarter round of tiles is still to be handed out
       gs.lookahead = std::max<uint32_t>(1, (grid - gather_wgs) / 4);
+      // several tickets per atomic once there are many tiles per workgroup
+      const uint64_t per_wg = gpu_tiles(kargs, 0, G) / std::max<uint32_t>(1, grid - gather_wgs);
+      gs.chunk = (uint32_t)std::min<uint64_t>(8, std::max<uint64_t>(1, per_wg / 8));
       gs.wait_ticks = (uint64_t)wallclock_hz * 60;
       if (gather) {
         const uint64_t max_host_tiles =

@@ -82,31 +82,63 @@ __device__ void publish(const T& pay, const SchedArgs& s, uint64_t tot, uint64_t
   ps->base = tot;
   ps->ntiles = nt;
   ps->t_claim = tc;
-  ps->t_end = 0;
+  dev_store(&ps->t_end, (uint64_t)0);  // raised by the workgroups' reports
   if (n == 0) dev_store(&q->t_first, tc);
   dev_store(&q->n_pkgs, n + 1);
   dev_store(&q->granules, dev_load(&q->granules) + (g1 - g0));
-  dev_store(&s.pub[n], pub_word(g0, g1 - g0));
+  // release: the cleared end tick is in place before anyone can report to it
+  __hip_atomic_store(&s.pub[n], pub_word(g0, g1 - g0), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   dev_store(&q->total, tot + nt);
 }
 
-// Ticket chain with lookahead. A workgroup takes the next tile ticket; when
-// it is within `lookahead` tiles of the end of the published tiles it tries
-// to take the claim lock and append the next level-1 package, so the PCIe
-// round trip of the claim overlaps the last round of tiles. The GPU thus
-// acts as one device towards the scheduler while its workgroups share each
-// package. Returns false when this workgroup should leave.
+// What one workgroup knows of the ticket chain, held by the lane that talks
+// to the dispenser: tickets taken but not yet run, the published total it
+// last read (it only grows, so it is a safe lower bound), the package of its
+// last ticket, and the tiles of that package it finished but has not
+// reported yet. Reporting once per package instead of once per tile keeps
+// the contended atomics to about one per tile ticket.
+struct Cursor {  // zero-initialised at the start of a run
+  uint64_t t_next, t_end;
+  uint64_t tot_seen;
+  uint64_t base, g0, g1;
+  uint32_t p, nt;  // nt == 0: no package yet
+  uint32_t done_cnt;
+  uint32_t pad;
+  uint64_t last_end;
+};
+
+__device__ __forceinline__ void report(const SchedArgs& s, Cursor& c) {
+  if (c.done_cnt == 0) return;
+  PkgSlot* ps = &s.pkgs[c.p];
+  dev_add(&ps->tiles_done, c.done_cnt);
+  __hip_atomic_fetch_max(&ps->t_end, c.last_end, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_max(&s.l2->t_last, c.last_end, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  c.done_cnt = 0;
+}
+
+// Ticket chain with lookahead. A workgroup takes tile tickets (s.chunk per
+// atomic); when a ticket is within `lookahead` tiles of the end of the
+// published tiles it tries to take the claim lock and append the next
+// level-1 package, so the PCIe round trip of the claim overlaps the last
+// round of tiles. The GPU thus acts as one device towards the scheduler while
+// its workgroups share each package. Returns false when this workgroup
+// should leave (its finished tiles are reported by then).
 template <class T>
-__device__ bool next_tile(const T& pay, const SchedArgs& s, uint32_t* p_cache, uint64_t* base_cache, uint32_t* p_out,
-                          uint32_t* ti_out, uint64_t* g0_out, uint64_t* g1_out, uint32_t* nt_out) {
+__device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t* ti_out) {
   L2State* q = s.l2;
-  const uint64_t t = dev_add(&q->ticket, (uint64_t)1);
+  if (c.t_next == c.t_end) {
+    c.t_next = dev_add(&q->ticket, (uint64_t)s.chunk);
+    c.t_end = c.t_next + s.chunk;
+  }
+  const uint64_t t = c.t_next++;
   uint64_t spins = 0;
-  for (;;) {
+  while (t + s.lookahead >= c.tot_seen) {
     const uint64_t tot = dev_load(&q->total);
+    c.tot_seen = tot;
     if (t + s.lookahead < tot) break;
     if (dev_load(&q->done)) {
       if (t < tot) break;
+      report(s, c);
       return false;
     }
     uint32_t unlocked = 0;
@@ -131,40 +163,46 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, uint32_t* p_cache, u
     if (++spins > s.spin_limit) {
       sys_store(&s.l1->gpu_flags, 1);
       dev_store(&q->done, 1u);
+      report(s, c);
       return false;
     }
     __builtin_amdgcn_s_sleep(2);
   }
-  // Locate the package holding ticket t: walk the publication words from the
-  // last package this workgroup used, accumulating tile bases.
-  uint32_t p = *p_cache;
-  uint64_t base = *base_cache;
-  for (uint64_t spins2 = 0;;) {
-    const uint64_t w = dev_load(&s.pub[p]);
-    if (w == 0) {  // published by the claimer but not visible here yet
-      if (++spins2 > s.spin_limit) {
-        sys_store(&s.l1->gpu_flags, 1);
-        return false;
+  if (c.nt == 0 || t >= c.base + c.nt) {
+    // Walk the publication words forward from the last package used; a
+    // workgroup's tickets only grow, so it never walks back.
+    uint32_t p = c.nt ? c.p : 0;
+    uint64_t base = c.nt ? c.base : 0;
+    for (uint64_t spins2 = 0;;) {
+      const uint64_t w = dev_load(&s.pub[p]);
+      if (w == 0) {  // published by the claimer but not visible here yet
+        if (++spins2 > s.spin_limit) {
+          sys_store(&s.l1->gpu_flags, 1);
+          report(s, c);
+          return false;
+        }
+        continue;
       }
-      continue;
+      const uint64_t g0 = pub_g0(w), g1 = g0 + pub_size(w);
+      const uint32_t nt = pay.ntiles(g0, g1);
+      if (t < base + nt) {
+        if (p != c.p || c.nt == 0) report(s, c);
+        c.p = p;
+        c.base = base;
+        c.g0 = g0;
+        c.g1 = g1;
+        c.nt = nt;
+        break;
+      }
+      base += nt;
+      ++p;
     }
-    const uint64_t g0 = pub_g0(w), g1 = g0 + pub_size(w);
-    const uint32_t nt = pay.ntiles(g0, g1);
-    if (t < base + nt) {
-      *p_cache = p;
-      *base_cache = base;
-      *p_out = p;
-      *ti_out = (uint32_t)(t - base);
-      *g0_out = g0;
-      *g1_out = g1;
-      *nt_out = nt;
-      return true;
-    }
-    base += nt;
-    ++p;
   }
+  *ti_out = (uint32_t)(t - c.base);
+  return true;
 }
 
+// Direct mode: a package is one tile run by the workgroup that claimed it.
 __device__ __forceinline__ void tile_done(const SchedArgs& s, uint32_t p, uint32_t nt) {
   PkgSlot* ps = &s.pkgs[p];
   const uint32_t d = dev_add(&ps->tiles_done, 1u);
@@ -291,14 +329,19 @@ __device__ void gather_copy(const SchedArgs& s, uint64_t off, uint32_t len) {
 // rotate the loop so that lane 0 leaves an inner loop through an exec-mask
 // update while the other lanes keep passing the barriers, which never ends.
 template <class T>
-__global__ __launch_bounds__(kBlockThreads) void k_persistent(T pay, SchedArgs s) {
+__global__ __launch_bounds__(kBlockThreads, 5) void k_persistent(T pay, SchedArgs s) {
   __shared__ uint32_t sh_go, sh_p, sh_ti, sh_nt;
   __shared__ uint64_t sh_g0, sh_g1;
   const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) == 0;
   const bool lane0 = threadIdx.x == 0;
   pay.load_constants();
-  uint32_t p_cache = 0;
-  uint64_t base_cache = 0;
+  // The cursor lives in LDS: only lane 0 of wave 0 uses it, and keeping it
+  // in registers across the tile loop would cost the payload occupancy.
+  __shared__ Cursor sh_cursor;
+  Cursor& c = sh_cursor;
+  if (wave0) {
+    if (lane0) c = Cursor{};
+  }
   uint32_t prev_p = 0xFFFFFFFFu, prev_nt = 0;
   if (blockIdx.x < s.gather_wgs) {
     __shared__ uint64_t sh_off;
@@ -328,14 +371,23 @@ __global__ __launch_bounds__(kBlockThreads) void k_persistent(T pay, SchedArgs s
   for (;;) {
     if (wave0) {
       if (lane0) {
-        if (prev_p != 0xFFFFFFFFu) tile_done(s, prev_p, prev_nt);
         uint32_t p = 0, ti = 0, nt = 1;
         uint64_t g0 = 0, g1 = 0;
         bool go;
-        if (s.direct)
+        if (s.direct) {
+          if (prev_p != 0xFFFFFFFFu) tile_done(s, prev_p, prev_nt);
           go = direct_claim(s, &p, &g0, &g1);
-        else
-          go = next_tile(pay, s, &p_cache, &base_cache, &p, &ti, &g0, &g1, &nt);
+        } else {
+          if (prev_p != 0xFFFFFFFFu) {
+            ++c.done_cnt;
+            c.last_end = now_tick();
+          }
+          go = next_tile(pay, s, c, &ti);
+          p = c.p;
+          g0 = c.g0;
+          g1 = c.g1;
+          nt = c.nt;
+        }
         sh_go = go ? 1u : 0u;
         sh_p = p;
         sh_ti = ti;

@@ -194,7 +194,7 @@ struct ce_server {
   std::mutex copy_mu;                // serialises use of copy_stream and staging
   Staging staging;
   std::condition_variable cv;
-  std::vector<JobRec> jobs;          // by ticket
+  std::deque<JobRec> jobs;           // by ticket; a deque so references stay valid as jobs are added
   std::deque<uint64_t> pending;      // tickets waiting for admission
   std::vector<uint64_t> inflight;    // tickets admitted, not finished
   std::vector<uint64_t> seq_ticket;  // session sequence -> ticket
