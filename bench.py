@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["blur", "escape", "nbody", "batch", "serve"], default="blur")
+    ap.add_argument("--workload", choices=["blur", "escape", "nbody", "batch", "serve", "copy"], default="blur")
     ap.add_argument("--serve-jobs", type=int, default=2000)
     ap.add_argument("--mode", choices=["device", "host"], default="device",
                     help="device: inputs and output resident in HBM; host: host buffers, PCIe inside the step")
@@ -123,6 +123,8 @@ def main():
         return bench_batch(args, ce, synth, torch, np, stream)
     if args.workload == "serve":
         return bench_serve(args, ce, synth, torch, np, stream)
+    if args.workload == "copy":
+        return bench_copy(args, torch, stream)
 
     eng = ce.Engine()
     eng.stream(stream.cuda_stream)
@@ -451,6 +453,29 @@ def bench_batch(args, ce, synth, torch, np, stream):
     }
     print(json.dumps(res), flush=True)
     b.close()
+
+
+def bench_copy(args, torch, stream):
+    """Reference for the HBM counters and the achievable stream rate: a plain
+    device copy of 256 MiB (the blur image's size), timed with HIP events."""
+    dev = torch.device("cuda:0")
+    a = torch.rand(8192 * 8192, device=dev)
+    b = torch.empty_like(a)
+    hev = HipEvents()
+    s0, s1 = hev.create(), hev.create()
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(args.steps):
+            hev.record(s0, stream.cuda_stream)
+            b.copy_(a)
+            hev.record(s1, stream.cuda_stream)
+            ms.append(hev.elapsed_ms(s0, s1))
+    nbytes = 2 * a.numel() * 4
+    print(json.dumps({"workload": "device copy 256 MiB fp32", "bytes_per_copy": nbytes, "steps": args.steps,
+                      "ms_median": med(ms), "GBps": nbytes / (med(ms) * 1e-3) / 1e9}), flush=True)
 
 
 def bench_serve(args, ce, synth, torch, np, stream):

@@ -123,7 +123,7 @@ struct SchedArgs {
   uint32_t max_pkgs;
   uint32_t lookahead;   // claim the next package this many tiles early
   uint32_t chunk;       // tile tickets taken per atomic
-  uint32_t pad_chunk;
+  uint32_t stride;      // 1: workgroup w runs tickets w, w + n, w + 2n ... (uniform-cost tiles)
   // gather of host-computed output into HBM (gather_wgs == 0: off)
   const uint64_t* ring; // device view of the host completion ring
   const char* gsrc;     // device view of the host output buffer

@@ -637,13 +637,13 @@ struct ce_engine {
 
     // the GPU copies the host's tiles into HBM when the output lives only there
     gather = use_gpu() && use_host() && out[0].dev_out && !out[0].host_out;
-    // persistent grid: resident workgroups, plus gatherers (one per XCD)
+    // persistent grid: resident workgroups, plus gatherers (two per XCD)
     uint32_t grid = 0, gather_wgs = 0;
     if (use_gpu()) {
       int bpc = 0;
       if ((he = persistent_blocks_per_cu(kargs, &bpc)) != hipSuccess) return hip_fail(he, "run: occupancy");
       grid = (uint32_t)std::max(1, bpc) * (uint32_t)n_cu;
-      gather_wgs = gather ? std::min<uint32_t>(8, std::max<uint32_t>(1, grid / 4)) : 0;
+      gather_wgs = gather ? std::min<uint32_t>(16, std::max<uint32_t>(1, grid / 4)) : 0;
       const uint32_t all_tiles = gpu_tiles(kargs, 0, G);
       if (all_tiles > 0 && grid > all_tiles + gather_wgs) grid = all_tiles + gather_wgs;
       if (grid <= gather_wgs) grid = gather_wgs + 1;
@@ -671,6 +671,9 @@ struct ce_engine {
       // several tickets per atomic once there are many tiles per workgroup
       const uint64_t per_wg = gpu_tiles(kargs, 0, G) / std::max<uint32_t>(1, grid - gather_wgs);
       gs.chunk = (uint32_t)std::min<uint64_t>(8, std::max<uint64_t>(1, per_wg / 8));
+      // blur and n-body tiles all cost the same: a fixed round-robin needs no
+      // atomics; escape-time tiles vary a lot, so they are dealt dynamically
+      gs.stride = kernel_id == CE_KERNEL_ESCAPE ? 0u : 1u;
       gs.wait_ticks = (uint64_t)wallclock_hz * 60;
       if (gather) {
         const uint64_t max_host_tiles =

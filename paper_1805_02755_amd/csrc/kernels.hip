@@ -116,8 +116,11 @@ __device__ __forceinline__ void report(const SchedArgs& s, Cursor& c) {
   c.done_cnt = 0;
 }
 
-// Ticket chain with lookahead. A workgroup takes tile tickets (s.chunk per
-// atomic); when a ticket is within `lookahead` tiles of the end of the
+// Ticket chain with lookahead. Every workgroup's first ticket is its own
+// index among the n computing workgroups. After that, with uniform-cost
+// tiles (s.stride) workgroup w simply runs tickets w + n, w + 2n, ... with no
+// atomic at all; otherwise it takes s.chunk tickets per atomic from a
+// counter that starts past the first round. When a ticket is within `lookahead` tiles of the end of the
 // published tiles it tries to take the claim lock and append the next
 // level-1 package, so the PCIe round trip of the claim overlaps the last
 // round of tiles. The GPU thus acts as one device towards the scheduler while
@@ -127,8 +130,14 @@ template <class T>
 __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t* ti_out) {
   L2State* q = s.l2;
   if (c.t_next == c.t_end) {
-    c.t_next = dev_add(&q->ticket, (uint64_t)s.chunk);
-    c.t_end = c.t_next + s.chunk;
+    const uint64_t n = gridDim.x - s.gather_wgs;
+    if (s.stride) {
+      c.t_next = c.t_end - 1 + n;
+      c.t_end = c.t_next + 1;
+    } else {
+      c.t_next = n + dev_add(&q->ticket, (uint64_t)s.chunk);
+      c.t_end = c.t_next + s.chunk;
+    }
   }
   const uint64_t t = c.t_next++;
   uint64_t spins = 0;
@@ -303,21 +312,47 @@ __device__ bool gather_entry(const SchedArgs& s, uint64_t* off, uint32_t* len) {
   }
 }
 
+// Host memory is reached over PCIe with a latency of microseconds, so each
+// thread issues a batch of independent loads before it stores any of them.
 __device__ void gather_copy(const SchedArgs& s, uint64_t off, uint32_t len) {
+  constexpr uint32_t kBatch = 8;
   const char* src = s.gsrc + off;
   char* dst = s.gdst + off;
   if (((off | len) & 15u) == 0) {
-    const uint4* a = reinterpret_cast<const uint4*>(src);
-    uint4* b = reinterpret_cast<uint4*>(dst);
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));  // a native vector stays in registers
+    const u32x4* a = reinterpret_cast<const u32x4*>(src);
+    u32x4* b = reinterpret_cast<u32x4*>(dst);
     const uint32_t n = len / 16;
-#pragma unroll 8
-    for (uint32_t i = threadIdx.x; i < n; i += kBlockThreads) b[i] = a[i];
+    for (uint32_t i0 = 0; i0 < n; i0 += kBlockThreads * kBatch) {
+      u32x4 v[kBatch];
+#pragma unroll
+      for (uint32_t k = 0; k < kBatch; ++k) {
+        const uint32_t i = i0 + k * kBlockThreads + threadIdx.x;
+        if (i < n) v[k] = a[i];
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < kBatch; ++k) {
+        const uint32_t i = i0 + k * kBlockThreads + threadIdx.x;
+        if (i < n) b[i] = v[k];
+      }
+    }
   } else {
     const uint32_t* a = reinterpret_cast<const uint32_t*>(src);
     uint32_t* b = reinterpret_cast<uint32_t*>(dst);
     const uint32_t n = len / 4;
-#pragma unroll 8
-    for (uint32_t i = threadIdx.x; i < n; i += kBlockThreads) b[i] = a[i];
+    for (uint32_t i0 = 0; i0 < n; i0 += kBlockThreads * kBatch) {
+      uint32_t v[kBatch];
+#pragma unroll
+      for (uint32_t k = 0; k < kBatch; ++k) {
+        const uint32_t i = i0 + k * kBlockThreads + threadIdx.x;
+        if (i < n) v[k] = a[i];
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < kBatch; ++k) {
+        const uint32_t i = i0 + k * kBlockThreads + threadIdx.x;
+        if (i < n) b[i] = v[k];
+      }
+    }
   }
 }
 
@@ -340,7 +375,11 @@ __global__ __launch_bounds__(kBlockThreads, 5) void k_persistent(T pay, SchedArg
   __shared__ Cursor sh_cursor;
   Cursor& c = sh_cursor;
   if (wave0) {
-    if (lane0) c = Cursor{};
+    if (lane0) {
+      c = Cursor{};
+      c.t_next = blockIdx.x - s.gather_wgs;  // the first ticket needs no atomic
+      c.t_end = c.t_next + 1;
+    }
   }
   uint32_t prev_p = 0xFFFFFFFFu, prev_nt = 0;
   if (blockIdx.x < s.gather_wgs) {
