@@ -226,7 +226,11 @@ __device__ __forceinline__ void tile_done(const SchedArgs& s, uint32_t p, uint32
 // publication words and resets the level-2 state for the next run.
 __device__ void leave(const SchedArgs& s) {
   L2State* q = s.l2;
-  const uint32_t ex = __hip_atomic_fetch_add(&q->exit_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+  // This workgroup's dispenser atomics are performed before it counts itself
+  // out (a workgroup-scope release only waits for them; an agent-scope one
+  // would also write back this XCD's L2, once per workgroup).
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  const uint32_t ex = dev_add(&q->exit_count, 1u);
   if (ex + 1 != gridDim.x) return;
   const uint64_t tf = dev_load(&q->t_first);
   const uint64_t tl = dev_load(&q->t_last);

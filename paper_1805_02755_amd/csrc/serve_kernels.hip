@@ -165,7 +165,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_serve(ServeArgs a) {
   }
   if (wave0) {
     if (lane0) {
-      const uint32_t ex = __hip_atomic_fetch_add(&a.q->exit_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      const uint32_t ex = dev_add(&a.q->exit_count, 1u);
       if (ex + 1 == gridDim.x) {
         if (dev_load(&a.q->flags)) sys_store(&a.ctl->flags, 1);
         sys_store_release(&a.ctl->exited, a.session);
