@@ -79,7 +79,9 @@ struct alignas(128) L2State {
   uint64_t t_first;     // first claim tick
   uint64_t t_last;      // latest package end tick
   uint64_t gather_next; // next host completion-ring entry to copy
-  uint64_t pad_misc[10];
+  uint64_t t_pre;       // start tick of the package claimed before the launch
+  uint64_t t_end0;      // latest end tick reported for that package
+  uint64_t pad_misc[8];
 };
 
 // A published GPU package as one 64-bit word: granule count in the top 24
@@ -124,6 +126,11 @@ struct SchedArgs {
   uint32_t lookahead;   // claim the next package this many tiles early
   uint32_t chunk;       // tile tickets taken per atomic
   uint32_t stride;      // 1: workgroup w runs tickets w, w + n, w + 2n ... (uniform-cost tiles)
+  // The GPU's first package, claimed by the host just before the launch
+  // (pre_nt == 0: none), so the workgroups start without a claim race.
+  uint64_t pre_g0, pre_g1;
+  uint32_t pre_nt;      // its tiles
+  uint32_t st_first;    // static: bands taken by that claim
   // gather of host-computed output into HBM (gather_wgs == 0: off)
   const uint64_t* ring; // device view of the host completion ring
   const char* gsrc;     // device view of the host output buffer

@@ -314,6 +314,47 @@ struct ce_engine {
     }
   }
 
+  // Claims the GPU's first package on the host just before the launch, with
+  // the same arithmetic the kernel's claimer uses, so that the workgroups find
+  // work published when they start instead of racing for the claim lock.
+  void gpu_preclaim(SchedArgs& gs) {
+    gs.pre_nt = 0;
+    gs.st_first = 0;
+    if (gs.direct) return;
+    uint64_t g0 = 0, g1 = 0;
+    if (gs.kind == kStatic) {
+      if (gs.st_begin >= gs.st_end) return;
+      if (gs.st_nbands == 0) {
+        g0 = gs.st_begin;
+        g1 = (gs.st_end - g0 > kPubMaxSize) ? g0 + kPubMaxSize : gs.st_end;
+      } else {
+        g0 = band_edge(gs.st_begin, gs.G, gs.st_nbands);
+        g1 = band_edge(gs.st_begin + 1, gs.G, gs.st_nbands);
+      }
+      gs.st_first = 1;
+    } else if (gs.kind == kDynamic) {
+      const uint64_t a = __atomic_fetch_add(&l1->next, gs.pkg, __ATOMIC_RELAXED);
+      if (a >= gs.G) return;
+      g0 = a;
+      g1 = std::min(a + gs.pkg, gs.G);
+    } else {
+      uint64_t cur = __atomic_load_n(&l1->next, __ATOMIC_ACQUIRE);
+      for (;;) {
+        if (cur >= gs.G) return;
+        uint64_t sz = hguided_size(gs.G - cur, gs.P_self, gs.sumP, gs.n_dev, gs.k, gs.min_self);
+        if (sz > kPubMaxSize) sz = kPubMaxSize;
+        if (__atomic_compare_exchange_n(&l1->next, &cur, cur + sz, false, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE)) {
+          g0 = cur;
+          g1 = cur + sz;
+          break;
+        }
+      }
+    }
+    gs.pre_g0 = g0;
+    gs.pre_g1 = g1;
+    gs.pre_nt = gpu_tiles(kargs, g0, g1);
+  }
+
   // Claims the next package for the host device from the level-1 dispenser
   // (or the static plan). Only the host chain's claimer calls this.
   bool host_claim(uint64_t* g0, uint64_t* g1) {
@@ -708,6 +749,7 @@ struct ce_engine {
 
     t0_ns = now_ns();
     if (use_gpu()) {
+      gpu_preclaim(gs);
       if (ev_start && (he = hipEventRecord(ev_start, stream)) != hipSuccess) return hip_fail(he, "run: event");
       if ((he = launch_persistent(kargs, gs, grid, stream)) != hipSuccess) return hip_fail(he, "run: kernel launch");
       if (ev_stop && (he = hipEventRecord(ev_stop, stream)) != hipSuccess) return hip_fail(he, "run: event");

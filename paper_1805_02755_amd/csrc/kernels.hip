@@ -23,13 +23,16 @@
 
 namespace ce {
 
+__device__ __forceinline__ uint64_t max_u64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
 // ---------------------------------------------------------------- dispenser
 // Claims the next level-1 package for the GPU. Only the holder of the claim
 // lock runs this.
 __device__ bool claim_package(const SchedArgs& s, uint64_t* g0, uint64_t* g1, bool* timed_out) {
   L2State* q = s.l2;
   if (s.kind == kStatic) {
-    const uint32_t b = dev_load(&q->st_next);
+    const uint32_t bk = dev_load(&q->st_next);
+    const uint32_t b = bk + s.st_first;
     if (s.st_nbands == 0) {
       // one package per device, cut only if it exceeds the descriptor's size field
       const uint64_t a = s.st_begin + (uint64_t)b * kPubMaxSize;
@@ -42,7 +45,7 @@ __device__ bool claim_package(const SchedArgs& s, uint64_t* g0, uint64_t* g1, bo
       *g0 = band_edge(b0, s.G, s.st_nbands);
       *g1 = band_edge(b0 + 1, s.G, s.st_nbands);
     }
-    dev_store(&q->st_next, b + 1);
+    dev_store(&q->st_next, bk + 1);
     return true;
   }
   if (s.kind == kDynamic) {
@@ -74,7 +77,8 @@ __device__ bool claim_package(const SchedArgs& s, uint64_t* g0, uint64_t* g1, bo
 template <class T>
 __device__ void publish(const T& pay, const SchedArgs& s, uint64_t tot, uint64_t g0, uint64_t g1, uint64_t tc) {
   L2State* q = s.l2;
-  const uint32_t n = dev_load(&q->n_pkgs);
+  const uint32_t nk = dev_load(&q->n_pkgs);   // packages published by the kernel
+  const uint32_t n = nk + (s.pre_nt ? 1u : 0u);  // slot 0 holds the pre-claimed one
   const uint32_t nt = pay.ntiles(g0, g1);
   PkgSlot* ps = &s.pkgs[n];  // trace record, read by the host after the run;
   ps->g0 = g0;               // its tile counter was cleared at the end of the last run
@@ -84,7 +88,7 @@ __device__ void publish(const T& pay, const SchedArgs& s, uint64_t tot, uint64_t
   ps->t_claim = tc;
   dev_store(&ps->t_end, (uint64_t)0);  // raised by the workgroups' reports
   if (n == 0) dev_store(&q->t_first, tc);
-  dev_store(&q->n_pkgs, n + 1);
+  dev_store(&q->n_pkgs, nk + 1);
   dev_store(&q->granules, dev_load(&q->granules) + (g1 - g0));
   // release: the cleared end tick is in place before anyone can report to it
   __hip_atomic_store(&s.pub[n], pub_word(g0, g1 - g0), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -111,7 +115,8 @@ __device__ __forceinline__ void report(const SchedArgs& s, Cursor& c) {
   if (c.done_cnt == 0) return;
   PkgSlot* ps = &s.pkgs[c.p];
   dev_add(&ps->tiles_done, c.done_cnt);
-  __hip_atomic_fetch_max(&ps->t_end, c.last_end, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint64_t* te = (c.p == 0 && s.pre_nt) ? &s.l2->t_end0 : &ps->t_end;
+  __hip_atomic_fetch_max(te, c.last_end, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_fetch_max(&s.l2->t_last, c.last_end, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   c.done_cnt = 0;
 }
@@ -142,7 +147,7 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
   const uint64_t t = c.t_next++;
   uint64_t spins = 0;
   while (t + s.lookahead >= c.tot_seen) {
-    const uint64_t tot = dev_load(&q->total);
+    const uint64_t tot = max_u64(dev_load(&q->total), s.pre_nt);
     c.tot_seen = tot;
     if (t + s.lookahead < tot) break;
     if (dev_load(&q->done)) {
@@ -150,10 +155,14 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
       report(s, c);
       return false;
     }
+    // Only two tickets may claim: the one `lookahead` before the end of the
+    // published tiles and the first one past it. Each belongs to exactly one
+    // workgroup, so the lock is never stormed.
     uint32_t unlocked = 0;
-    if (__hip_atomic_compare_exchange_strong(&q->lock, &unlocked, 1u, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
+    if ((t + s.lookahead == tot || t == tot) &&
+        __hip_atomic_compare_exchange_strong(&q->lock, &unlocked, 1u, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT)) {
-      const uint64_t tot2 = dev_load(&q->total);
+      const uint64_t tot2 = max_u64(dev_load(&q->total), s.pre_nt);
       if (!dev_load(&q->done) && t + s.lookahead >= tot2) {
         uint64_t g0 = 0, g1 = 0;
         bool timed_out = false;
@@ -175,7 +184,12 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
       report(s, c);
       return false;
     }
-    __builtin_amdgcn_s_sleep(2);
+    // waiting workgroups poll gently so the claimer's stores are not queued
+    // behind their loads
+    if (t - tot < 64)
+      __builtin_amdgcn_s_sleep(4);
+    else
+      __builtin_amdgcn_s_sleep(32);
   }
   if (c.nt == 0 || t >= c.base + c.nt) {
     // Walk the publication words forward from the last package used; a
@@ -183,7 +197,7 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
     uint32_t p = c.nt ? c.p : 0;
     uint64_t base = c.nt ? c.base : 0;
     for (uint64_t spins2 = 0;;) {
-      const uint64_t w = dev_load(&s.pub[p]);
+      const uint64_t w = (p == 0 && s.pre_nt) ? pub_word(s.pre_g0, s.pre_g1 - s.pre_g0) : dev_load(&s.pub[p]);
       if (w == 0) {  // published by the claimer but not visible here yet
         if (++spins2 > s.spin_limit) {
           sys_store(&s.l1->gpu_flags, 1);
@@ -232,10 +246,25 @@ __device__ void leave(const SchedArgs& s) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   const uint32_t ex = dev_add(&q->exit_count, 1u);
   if (ex + 1 != gridDim.x) return;
-  const uint64_t tf = dev_load(&q->t_first);
+  uint64_t tf = dev_load(&q->t_first);
   const uint64_t tl = dev_load(&q->t_last);
-  const uint64_t gr = dev_load(&q->granules);
-  const uint32_t np = dev_load(&q->n_pkgs);
+  uint64_t gr = dev_load(&q->granules);
+  const uint32_t np = dev_load(&q->n_pkgs) + (s.pre_nt ? 1u : 0u);
+  if (s.pre_nt) {
+    // trace record of the pre-claimed package (read by the host after the run)
+    PkgSlot* ps = &s.pkgs[0];
+    const uint64_t tp = dev_load(&q->t_pre);
+    ps->g0 = s.pre_g0;
+    ps->g1 = s.pre_g1;
+    ps->base = 0;
+    ps->ntiles = s.pre_nt;
+    ps->t_claim = tp;
+    ps->t_end = dev_load(&q->t_end0);
+    tf = tp;
+    gr += s.pre_g1 - s.pre_g0;
+    dev_store(&q->t_pre, (uint64_t)0);
+    dev_store(&q->t_end0, (uint64_t)0);
+  }
   for (uint32_t i = 0; i < np && i < s.max_pkgs; ++i) {
     dev_store(&s.pub[i], (uint64_t)0);
     dev_store(&s.pkgs[i].tiles_done, 0u);
@@ -383,6 +412,8 @@ __global__ __launch_bounds__(kBlockThreads, 5) void k_persistent(T pay, SchedArg
       c = Cursor{};
       c.t_next = blockIdx.x - s.gather_wgs;  // the first ticket needs no atomic
       c.t_end = c.t_next + 1;
+      c.tot_seen = s.pre_nt;
+      if (s.pre_nt && c.t_next == 0) dev_store(&s.l2->t_pre, now_tick());
     }
   }
   uint32_t prev_p = 0xFFFFFFFFu, prev_nt = 0;

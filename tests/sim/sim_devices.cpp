@@ -151,11 +151,16 @@ hipError_t persistent_blocks_per_cu(const KernelArgs&, int* b) {
 hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, hipStream_t) {
   join_gpu();
   g_gpu = std::thread([a, s] {
-    uint64_t np = 0, gr = 0, stn = 0, t_first = 0, t_last = 0;
+    uint64_t np = 0, gr = 0, stn = s.st_first, t_first = 0, t_last = 0;
+    bool pre = s.pre_nt != 0;  // the package the host claimed for the GPU before the launch
     for (;;) {
       uint64_t g0 = 0, g1 = 0;
       spin_until(now_ns() + (int64_t)g_gpu_claim_ns);
-      if (s.kind == kStatic) {
+      if (pre) {
+        g0 = s.pre_g0;
+        g1 = s.pre_g1;
+        pre = false;
+      } else if (s.kind == kStatic) {
         if (s.st_nbands == 0) {
           if (stn || s.st_begin >= s.st_end) break;
           g0 = s.st_begin;
