@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["blur", "escape", "nbody", "batch", "serve", "copy"], default="blur")
     ap.add_argument("--serve-jobs", type=int, default=2000)
+    ap.add_argument("--trace-out", default=None, help="write the last co-executed run's package trace (JSON) here")
     ap.add_argument("--mode", choices=["device", "host"], default="device",
                     help="device: inputs and output resident in HBM; host: host buffers, PCIe inside the step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -271,6 +272,10 @@ def main():
     T_total = time.perf_counter() - t0
     eng.kernel_events(None, None)
     trace = eng.trace()
+    if args.trace_out:
+        with open(args.trace_out, "w") as f:
+            json.dump({"stats": {"t_device": list(stats[-1].t_device[:2]), "t_run": stats[-1].t_run},
+                       "packages": [list(r) for r in trace]}, f)
 
     kern_ms = [hev.elapsed_ms(ev_s[i], ev_e[i]) for i in range(K)]
     for ev in ev_s + ev_e:

@@ -102,7 +102,7 @@ typedef struct {
  *           floor(G_r * power[i] / (k * n * sum_j power[j]))), cut to the
  *           pending granules G_r. power[i] in [1, 2^20]; k >= 1;
  *           min_granules[i] == 0 selects the default (GPU: one tile per
- *           resident workgroup; host: 1 granule). */
+ *           resident workgroup; host: one host tile per worker thread). */
 typedef struct {
   int32_t kind;
   int32_t order;

@@ -45,6 +45,8 @@ struct alignas(64) L1State {
   // finished it publishes the number of ring entries of the run
   uint64_t host_final;  // host_final_word(run id, entries), written once per run
   uint64_t pad3[7];
+  uint64_t gathered;    // bytes of host output the GPU's gatherers have copied this run
+  uint64_t pad4[7];
 };
 
 // The host's final ring size and the run it belongs to, in one word so the

@@ -170,6 +170,7 @@ struct ce_engine {
   bool gather = false;          // this run's host tiles are copied into HBM by the GPU
   std::atomic<uint64_t> ring_count{0};
   std::atomic<uint64_t> ring_written{0};  // entries whose ring word is stored
+  std::atomic<uint64_t> ring_bytes{0};    // bytes of those entries
 
   // ---- host pool
   std::vector<std::thread> pool;
@@ -430,7 +431,20 @@ struct ce_engine {
     const uint64_t k = ring_count.fetch_add(1, std::memory_order_relaxed);
     uint64_t* ring = (uint64_t*)ring_buf.p;
     __atomic_store_n(&ring[k], ring_word(off, len), __ATOMIC_RELEASE);
+    ring_bytes.fetch_add(len, std::memory_order_relaxed);
     ring_written.fetch_add(1, std::memory_order_release);
+  }
+
+  // With the GPU gathering the host's output, the host is worth only as much
+  // output as PCIe can carry: its claimer waits while more than
+  // kGatherBacklog bytes are published but not yet copied.
+  static constexpr uint64_t kGatherBacklog = 2u << 20;
+  void gather_throttle() {
+    const int64_t limit = now_ns() + 1'000'000'000LL;  // never wait for a stalled GPU forever
+    while (ring_bytes.load(std::memory_order_relaxed) >
+               __atomic_load_n(&l1->gathered, __ATOMIC_ACQUIRE) + kGatherBacklog &&
+           now_ns() < limit)
+      cpu_relax();
   }
 
   // Host side of a run: every pool thread (and the caller) runs this loop.
@@ -448,6 +462,7 @@ struct ce_engine {
         if (hq.done.load(std::memory_order_acquire)) break;
         if (t == tot) {
           uint64_t g0 = 0, g1 = 0;
+          if (gather) gather_throttle();
           const int64_t tc = now_ns();
           if (hq.n_pkgs >= hq.cap || !host_claim(&g0, &g1)) {
             if (hq.n_pkgs >= hq.cap) host_error.store(1);
@@ -582,7 +597,9 @@ struct ce_engine {
         *gpu_max = G / std::max<uint64_t>(1, gpu_s->min_self) + 2;
       }
       if (hi >= 0) {
-        fill(host_s, hi, 1);
+        // default minimum: one host tile for every worker thread
+        const uint64_t tpg = std::max<uint32_t>(1, host_tiles(0, 1));
+        fill(host_s, hi, std::min<uint64_t>(G, ceil_div((uint64_t)std::max(1, host_threads), tpg)));
         *host_max = G / std::max<uint64_t>(1, host_s->min_self) + 2;
       }
       return CE_OK;
@@ -736,6 +753,8 @@ struct ce_engine {
     }
     ring_count.store(0, std::memory_order_relaxed);
     ring_written.store(0, std::memory_order_relaxed);
+    ring_bytes.store(0, std::memory_order_relaxed);
+    __atomic_store_n(&l1->gathered, 0, __ATOMIC_RELAXED);
     if (use_host()) {
       if (!hq.ensure(hmax)) return fail(CE_E_NOMEM, "run: host package table");
     }

@@ -434,7 +434,11 @@ __global__ __launch_bounds__(kBlockThreads, 5) void k_persistent(T pay, SchedArg
       if (__builtin_amdgcn_readfirstlane(sh_go) == 0) break;
       const uint64_t off = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sh_off >> 32)) << 32) |
                            __builtin_amdgcn_readfirstlane((uint32_t)sh_off);
-      gather_copy(s, off, __builtin_amdgcn_readfirstlane(sh_len));
+      const uint32_t len = __builtin_amdgcn_readfirstlane(sh_len);
+      gather_copy(s, off, len);
+      if (wave0) {
+        if (lane0) sys_fetch_add(&s.l1->gathered, (uint64_t)len);  // progress for the host's throttle
+      }
       __syncthreads();
     }
     if (wave0) {

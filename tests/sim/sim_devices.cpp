@@ -230,6 +230,7 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, 
         }
         if (!w) break;
         memcpy(s.gdst + ring_off(w), s.gsrc + ring_off(w), ring_len(w));
+        __atomic_fetch_add(&s.l1->gathered, ring_len(w), __ATOMIC_RELEASE);
       }
     }
     __atomic_store_n(&s.l1->gpu_t_first, t_first, __ATOMIC_RELEASE);
