@@ -275,7 +275,7 @@ typedef struct {
   uint64_t hbm_budget;      /* bytes of device memory for job buffers (> 0)  */
   uint32_t max_inflight;    /* admitted but unfinished jobs; 0 = 64           */
   uint32_t keep_outputs;    /* 0: a job's memory is freed when it finishes   */
-  uint32_t max_jobs;        /* jobs per session; 0 = 65536                    */
+  uint32_t max_jobs;        /* jobs per session; 0 = 65536, at most 2^23-1  */
   uint32_t workgroups_per_cu; /* serving workgroups per CU; 0 = the occupancy
                                * limit minus one, which leaves room for copies
                                * and the caller's own kernels during a session */

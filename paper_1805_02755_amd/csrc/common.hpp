@@ -67,10 +67,8 @@ CE_HD uint64_t ring_len(uint64_t w) { return w >> 40; }
 struct alignas(128) L2State {
   uint64_t ticket;      // next tile ticket
   uint64_t pad_ticket[15];
-  uint64_t total;       // tiles of all published packages
-  uint32_t done;        // no more packages for this device
-  uint32_t pad_done;
-  uint64_t pad_total[14];
+  uint64_t total;       // tiles of all published packages | kTotalDone once no more will come
+  uint64_t pad_total[15];
   uint32_t lock;        // held by the workgroup claiming the next package
   uint32_t pad_lock[31];
   uint32_t n_pkgs;      // packages published
@@ -85,6 +83,9 @@ struct alignas(128) L2State {
   uint64_t t_end0;      // latest end tick reported for that package
   uint64_t pad_misc[8];
 };
+
+constexpr uint64_t kTotalDone = 1ull << 63;
+constexpr uint64_t kTotalMask = kTotalDone - 1;
 
 // A published GPU package as one 64-bit word: granule count in the top 24
 // bits, first granule in the low 40 bits; 0 means "not published yet".

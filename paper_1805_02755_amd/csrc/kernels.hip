@@ -147,10 +147,14 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
   const uint64_t t = c.t_next++;
   uint64_t spins = 0;
   while (t + s.lookahead >= c.tot_seen) {
-    const uint64_t tot = max_u64(dev_load(&q->total), s.pre_nt);
+    // The published tile count and the "no more packages" flag share one
+    // word, so a workgroup never pairs a stale count with a fresh flag (which
+    // would make it leave with a ticket that did get published).
+    const uint64_t w = dev_load(&q->total);
+    const uint64_t tot = max_u64(w & kTotalMask, s.pre_nt);
     c.tot_seen = tot;
     if (t + s.lookahead < tot) break;
-    if (dev_load(&q->done)) {
+    if (w & kTotalDone) {
       if (t < tot) break;
       report(s, c);
       return false;
@@ -162,14 +166,15 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
     if ((t + s.lookahead == tot || t == tot) &&
         __hip_atomic_compare_exchange_strong(&q->lock, &unlocked, 1u, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT)) {
-      const uint64_t tot2 = max_u64(dev_load(&q->total), s.pre_nt);
-      if (!dev_load(&q->done) && t + s.lookahead >= tot2) {
+      const uint64_t w2 = dev_load(&q->total);
+      const uint64_t tot2 = max_u64(w2 & kTotalMask, s.pre_nt);
+      if (!(w2 & kTotalDone) && t + s.lookahead >= tot2) {
         uint64_t g0 = 0, g1 = 0;
         bool timed_out = false;
         const uint64_t tc = now_tick();
         if (dev_load(&q->n_pkgs) >= s.max_pkgs || !claim_package(s, &g0, &g1, &timed_out)) {
           if (timed_out || dev_load(&q->n_pkgs) >= s.max_pkgs) sys_store(&s.l1->gpu_flags, 1);
-          dev_store(&q->done, 1u);
+          dev_store(&q->total, tot2 | kTotalDone);
         } else {
           publish(pay, s, tot2, g0, g1, tc);
         }
@@ -180,7 +185,7 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
     if (t < tot) break;
     if (++spins > s.spin_limit) {
       sys_store(&s.l1->gpu_flags, 1);
-      dev_store(&q->done, 1u);
+      __hip_atomic_fetch_or(&q->total, kTotalDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       report(s, c);
       return false;
     }
@@ -276,7 +281,6 @@ __device__ void leave(const SchedArgs& s) {
   dev_store(&q->ticket, (uint64_t)0);
   dev_store(&q->total, (uint64_t)0);
   dev_store(&q->n_pkgs, 0u);
-  dev_store(&q->done, 0u);
   dev_store(&q->st_next, 0u);
   dev_store(&q->granules, (uint64_t)0);
   dev_store(&q->t_first, (uint64_t)0);

@@ -225,6 +225,7 @@ struct ce_server {
     cfg = *c;
     if (cfg.max_inflight == 0) cfg.max_inflight = 64;
     if (cfg.max_jobs == 0) cfg.max_jobs = 65536;
+    if (cfg.max_jobs > kServeMaxJobs) return fail(CE_E_INVALID, "config: max_jobs above %u", kServeMaxJobs);
     if (cfg.session_timeout_s <= 0.0) cfg.session_timeout_s = 300.0;
     if (cfg.hbm_budget == 0) return fail(CE_E_INVALID, "config: zero HBM budget");
     hipError_t he;

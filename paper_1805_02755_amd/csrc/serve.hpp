@@ -32,8 +32,8 @@ struct alignas(128) ServeDesc {
 // Serving kernel state in HBM (zero at the start of a session).
 struct alignas(64) ServeState {
   uint64_t ticket;      // next tile ticket
-  uint64_t ct;          // jobs copied from the host ring << 40 | tiles of those jobs
-  uint32_t done;        // no more jobs: workgroups leave
+  uint64_t ct;          // done << 63 | jobs copied from the host ring << 40 | tiles of those jobs
+  uint32_t pad_done;
   uint32_t exit_count;
   uint32_t flags;       // bit 0: deadline reached
   uint32_t pad0;
@@ -41,6 +41,8 @@ struct alignas(64) ServeState {
 };
 constexpr uint32_t kServeTotalBits = 40;  // tiles per session < 2^40
 constexpr uint64_t kServeTotalMask = (1ull << kServeTotalBits) - 1;
+constexpr uint64_t kServeDone = 1ull << 63;  // no more jobs: workgroups leave
+constexpr uint32_t kServeMaxJobs = (1u << 23) - 1;  // jobs per session (the count's field)
 
 // Host control block (host-coherent memory), read and written by both sides.
 struct alignas(64) ServeCtl {

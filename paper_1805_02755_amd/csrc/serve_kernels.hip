@@ -29,10 +29,11 @@ __device__ bool serve_next(const ServeArgs& a, uint64_t deadline, uint32_t* p_ca
   const uint64_t t = dev_add(&q->ticket, (uint64_t)1);
   for (;;) {
     // consumed jobs and their tiles are one word, so they are read together
+    // the flag, the job count and the tile count are one word, read together
     const uint64_t ct = dev_load(&q->ct);
-    const uint64_t tot = ct & kServeTotalMask, c = ct >> kServeTotalBits;
+    const uint64_t tot = ct & kServeTotalMask, c = (ct & ~kServeDone) >> kServeTotalBits;
     if (t < tot) break;
-    if (dev_load(&q->done)) return false;
+    if (ct & kServeDone) return false;
     if (t == tot) {
       // this workgroup appends the next admitted job, if there is one
       uint64_t h = sys_load(&a.ctl->head);
@@ -57,13 +58,13 @@ __device__ bool serve_next(const ServeArgs& a, uint64_t deadline, uint32_t* p_ca
         continue;
       }
       if (stop || c >= a.cap) {
-        dev_store(&q->done, 1u);
+        dev_store(&q->ct, ct | kServeDone);  // only this workgroup writes ct now
         return false;
       }
     }
     if (now_tick() > deadline) {
       dev_store(&q->flags, 1u);
-      dev_store(&q->done, 1u);
+      __hip_atomic_fetch_or(&q->ct, kServeDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
     if (t == tot)

@@ -202,3 +202,24 @@ def test_error_paths(eng):
     with pytest.raises(ce.CoexecError):
         e2.program_kernel(ce.CE_KERNEL_NBODY_ACC, ce.ce_nbody_params(10, 0.0, 1))
     e2.close()
+
+
+# ------------------------------------------------- repeated runs (races)
+def test_repeated_coexecution_runs_cover_every_item(eng):
+    """Many back-to-back runs of configurations whose GPU workgroups wait for
+    packages at the end of the run: every run must write every item (a
+    workgroup once paired a stale published-tile count with the end flag and
+    left with a ticket that had been published)."""
+    p = synth.escape_small()
+    ref_e = O.escape(p.w, p.h, *[float(v) for v in p.as_f32()], p.max_iter)
+    img = synth.blur_image(1024, 40, seed=1024 * 7919 + 40)
+    wt = ce.ce_gauss5_weights(1.0)
+    ref_b = O.blur5(img, O.gauss5_weights(1.0))
+    for rep in range(12):
+        for sched in ("static8", "hguided", "dynamic"):
+            out, st, tr = run_payload(eng, ce.CE_KERNEL_ESCAPE, escape_params(p), [p.w, p.h], None, [], (p.h, p.w),
+                                      np.uint32, BOTH, sched)
+            assert np.array_equal(out, ref_e), (rep, sched, diff_report(out, ref_e, tr))
+            out, st, tr = run_payload(eng, ce.CE_KERNEL_BLUR5, ce.ce_blur5_params(1024, 40), [1024, 40], None,
+                                      [img, wt], (40, 1024), np.float32, BOTH, sched)
+            assert np.array_equal(out.view(np.uint32), ref_b.view(np.uint32)), (rep, sched, diff_report(out, ref_b, tr))
