@@ -274,7 +274,8 @@ def main():
     trace = eng.trace()
     if args.trace_out:
         with open(args.trace_out, "w") as f:
-            json.dump({"stats": {"t_device": list(stats[-1].t_device[:2]), "t_run": stats[-1].t_run},
+            json.dump({"stats": {"t_device": list(stats[-1].t_device[:2]), "t_run": stats[-1].t_run,
+                                 "t_gather": stats[-1].t_gather, "gathered_bytes": stats[-1].gathered_bytes},
                        "packages": [list(r) for r in trace]}, f)
 
     kern_ms = [hev.elapsed_ms(ev_s[i], ev_e[i]) for i in range(K)]
@@ -381,6 +382,8 @@ def main():
             "packages_host": med([s.packages[1] for s in stats]),
             "scheduler": {k: (list(v) if isinstance(v, (list, tuple)) else v) for k, v in coexec.items()},
             "t_device_ms": [med([s.t_device[0] for s in stats]) * 1e3, med([s.t_device[1] for s in stats]) * 1e3],
+            "t_gather_ms": med([s.t_gather for s in stats]) * 1e3,
+            "gathered_MiB": med([s.gathered_bytes for s in stats]) / 2**20,
             "trace_packages": len(trace),
         },
     }

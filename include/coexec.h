@@ -131,6 +131,9 @@ typedef struct {
   uint64_t total_items;
   uint32_t gpu_workgroups;            /* persistent grid size of the last run */
   uint32_t host_threads;              /* host worker threads of the last run  */
+  double t_gather;                    /* end of the GPU's last copy of host output into
+                                       * the device output (0: no such copies)  */
+  uint64_t gathered_bytes;            /* bytes of host output the GPU copied     */
 } ce_run_stats;
 
 /* One package of the last run (section 5 "Introspector"): device, granule

@@ -35,7 +35,8 @@ struct alignas(64) L1State {
   uint64_t gpu_granules;
   uint64_t gpu_packages;
   uint64_t gpu_flags;   // bit 0: a wait on the dispenser timed out
-  uint64_t pad1[2];
+  uint64_t gpu_t_leave; // s_memrealtime just before gpu_run_id is written
+  uint64_t pad1[1];
   // clock calibration mailbox
   uint64_t ping;
   uint64_t pong;
@@ -46,7 +47,8 @@ struct alignas(64) L1State {
   uint64_t host_final;  // host_final_word(run id, entries), written once per run
   uint64_t pad3[7];
   uint64_t gathered;    // bytes of host output the GPU's gatherers have copied this run
-  uint64_t pad4[7];
+  uint64_t gpu_t_gather;// s_memrealtime at the end of the last gather copy (0: none)
+  uint64_t pad4[6];
 };
 
 // The host's final ring size and the run it belongs to, in one word so the
@@ -81,7 +83,8 @@ struct alignas(128) L2State {
   uint64_t gather_next; // next host completion-ring entry to copy
   uint64_t t_pre;       // start tick of the package claimed before the launch
   uint64_t t_end0;      // latest end tick reported for that package
-  uint64_t pad_misc[8];
+  uint64_t t_gather;    // latest end tick of a gather copy
+  uint64_t pad_misc[7];
 };
 
 constexpr uint64_t kTotalDone = 1ull << 63;

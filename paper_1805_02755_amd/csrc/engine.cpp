@@ -142,6 +142,7 @@ struct ce_engine {
   DevBuf pub_dev;  // publication words of the GPU's packages, zero between runs
   uint32_t pkgs_dev_cap = 0;
   double clock_offset_ns = 0.0;  // host_ns = tick * period + offset
+  double clock_latency_ns = 0.0; // one-way GPU -> host visibility latency (half the best round trip)
   bool clock_ok = false;
   const HostPayloadFns* hp = nullptr;
 
@@ -797,9 +798,20 @@ struct ce_engine {
     if (use_gpu()) {
       // the last workgroup out writes the run id; poll it, then sync
       const int64_t deadline = now_ns() + 120'000'000'000LL;
+      bool waited = false;
       while (__atomic_load_n(&l1->gpu_run_id, __ATOMIC_ACQUIRE) != run_id) {
+        waited = true;
         if (now_ns() > deadline) break;
         cpu_relax();
+      }
+      if (waited && clock_ok && __atomic_load_n(&l1->gpu_run_id, __ATOMIC_ACQUIRE) == run_id) {
+        // The host saw the GPU's last store as it happened (give or take the
+        // one-way latency measured at calibration): re-anchor the tick -> host
+        // mapping here, so the two clocks' drift since creation does not
+        // accumulate into the device times.
+        const double seen = (double)now_ns() - clock_latency_ns;
+        const uint64_t tl = __atomic_load_n(&l1->gpu_t_leave, __ATOMIC_ACQUIRE);
+        clock_offset_ns = seen - (double)tl * (1e9 / (double)wallclock_hz);
       }
       if ((he = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(he, "run: kernel");
       if (__atomic_load_n(&l1->gpu_run_id, __ATOMIC_ACQUIRE) != run_id)
@@ -907,6 +919,9 @@ struct ce_engine {
       s.granules[gi] = gr;
       s.t_device[gi] = np ? std::max(0.0, tick_to_host_s(tl)) : 0.0;
       s.t_gpu_kernel = np ? (double)(tl - tf) / (double)wallclock_hz : 0.0;
+      const uint64_t tg = __atomic_load_n(&l1->gpu_t_gather, __ATOMIC_ACQUIRE);
+      s.t_gather = (gather && tg) ? std::max(0.0, tick_to_host_s(tg)) : 0.0;
+      s.gathered_bytes = gather ? __atomic_load_n(&l1->gathered, __ATOMIC_ACQUIRE) : 0;
       gpu_pkgs_last = np;
     }
     if (hi >= 0) {
@@ -1019,7 +1034,10 @@ struct ce_engine {
     __atomic_store_n(&l1->ping, 0xFFFFFFFFull, __ATOMIC_RELEASE);
     (void)hipStreamSynchronize(stream);
     clock_ok = ok;
-    if (ok) clock_offset_ns = best_off;
+    if (ok) {
+      clock_offset_ns = best_off;
+      clock_latency_ns = 0.5 * best_rt;
+    }
     else errors.emplace_back("create: GPU clock calibration failed; GPU times are unmapped");
   }
 

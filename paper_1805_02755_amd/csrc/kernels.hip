@@ -288,6 +288,9 @@ __device__ void leave(const SchedArgs& s) {
   dev_store(&q->lock, 0u);
   dev_store(&q->gather_next, (uint64_t)0);
   dev_store(&q->exit_count, 0u);
+  sys_store(&s.l1->gpu_t_gather, dev_load(&q->t_gather));
+  dev_store(&q->t_gather, (uint64_t)0);
+  sys_store(&s.l1->gpu_t_leave, now_tick());  // lets the host re-anchor its clock mapping
   sys_store_release(&s.l1->gpu_run_id, s.run_id);
 }
 
@@ -441,7 +444,10 @@ __global__ __launch_bounds__(kBlockThreads, 5) void k_persistent(T pay, SchedArg
       const uint32_t len = __builtin_amdgcn_readfirstlane(sh_len);
       gather_copy(s, off, len);
       if (wave0) {
-        if (lane0) sys_fetch_add(&s.l1->gathered, (uint64_t)len);  // progress for the host's throttle
+        if (lane0) {
+          sys_fetch_add(&s.l1->gathered, (uint64_t)len);  // progress for the host's throttle
+          __hip_atomic_fetch_max(&s.l2->t_gather, now_tick(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
       }
       __syncthreads();
     }

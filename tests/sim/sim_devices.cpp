@@ -231,12 +231,14 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, 
         if (!w) break;
         memcpy(s.gdst + ring_off(w), s.gsrc + ring_off(w), ring_len(w));
         __atomic_fetch_add(&s.l1->gathered, ring_len(w), __ATOMIC_RELEASE);
+        __atomic_store_n(&s.l1->gpu_t_gather, (uint64_t)(now_ns() / 10), __ATOMIC_RELEASE);
       }
     }
     __atomic_store_n(&s.l1->gpu_t_first, t_first, __ATOMIC_RELEASE);
     __atomic_store_n(&s.l1->gpu_t_last, t_last, __ATOMIC_RELEASE);
     __atomic_store_n(&s.l1->gpu_granules, gr, __ATOMIC_RELEASE);
     __atomic_store_n(&s.l1->gpu_packages, np, __ATOMIC_RELEASE);
+    __atomic_store_n(&s.l1->gpu_t_leave, (uint64_t)(now_ns() / 10), __ATOMIC_RELEASE);
     __atomic_store_n(&s.l1->gpu_run_id, s.run_id, __ATOMIC_RELEASE);
   });
   return hipSuccess;
