@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--mode", choices=["device", "host"], default="device",
                     help="device: inputs and output resident in HBM; host: host buffers, PCIe inside the step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--merge", choices=["dma", "gpu"], default="dma",
+                    help="how the host's share reaches the device output: DMA copies or the GPU's gather")
     ap.add_argument("--host-threads", type=int, default=0)
     return ap.parse_args()
 
@@ -129,6 +131,7 @@ def main():
 
     eng = ce.Engine()
     eng.stream(stream.cuda_stream)
+    eng.output_merge(ce.CE_MERGE_DMA if args.merge == "dma" else ce.CE_MERGE_GPU_GATHER)
 
     # ---------------------------------------------------------------- payload
     wl = args.workload
@@ -151,7 +154,7 @@ def main():
         host_threads = args.host_threads
         coexec = dict(kind=ce.CE_SCHED_HGUIDED, k=2)
         config = {"workload": "blur5x5 8192x8192 fp32, sigma 1, clamp-to-edge", "scheduler": "hguided",
-                  "devices": "gpu+host", "residency": args.mode}
+                  "devices": "gpu+host", "residency": args.mode, "output_merge": args.merge}
         bound = "hbm"
     elif wl == "escape":
         p = synth.escape_small()

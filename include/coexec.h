@@ -186,6 +186,19 @@ ce_status ce_program_out(ce_engine* e, uint32_t slot, void* host_ptr, void* dev_
  * work-item, so only 1:1 is accepted (others: CE_E_UNSUPPORTED). */
 ce_status ce_program_out_pattern(ce_engine* e, uint32_t outs, uint32_t items);
 
+/* How the host's share of a device-resident output (output bound only as a
+ * device pointer, host in the device set) reaches HBM during the run
+ * (section 4.2 output pattern, 1:1):
+ *  CE_MERGE_DMA (default): as each host package finishes, its output range
+ *    is copied host -> device by the DMA engine, overlapping the GPU's work;
+ *  CE_MERGE_GPU_GATHER: a few GPU workgroups copy each finished host tile
+ *    over PCIe into HBM while the others compute.
+ * Either way the host claims new packages only while less than a few MiB of
+ * its output is still in flight. */
+#define CE_MERGE_DMA 0
+#define CE_MERGE_GPU_GATHER 1
+ce_status ce_engine_output_merge(ce_engine* e, int mode);
+
 /* Records the caller's HIP events (hipEvent_t handles) on the engine's
  * stream immediately before and after the GPU kernel of each following run,
  * so the caller can time the kernel with hipEventElapsedTime. NULL, NULL

@@ -43,9 +43,12 @@ CE_SCHED_HGUIDED = 2
 CE_ORDER_HOST_FIRST = 0
 CE_ORDER_GPU_FIRST = 1
 
+CE_MERGE_DMA = 0
+CE_MERGE_GPU_GATHER = 1
+
 EXPORTED_SYMBOLS = (
     "ce_engine_create", "ce_engine_destroy", "ce_engine_use", "ce_engine_work_items", "ce_engine_scheduler",
-    "ce_engine_stream", "ce_engine_kernel_events", "ce_program_kernel", "ce_program_in", "ce_program_out", "ce_program_out_pattern",
+    "ce_engine_stream", "ce_engine_output_merge", "ce_engine_kernel_events", "ce_program_kernel", "ce_program_in", "ce_program_out", "ce_program_out_pattern",
     "ce_engine_run", "ce_engine_stats", "ce_engine_trace", "ce_engine_has_errors", "ce_engine_error_count",
     "ce_engine_error", "ce_engine_clear_errors", "ce_bare_run", "ce_sched_static_plan", "ce_sched_hguided_size",
     "ce_gauss5_weights", "ce_version", "ce_batch_create", "ce_batch_destroy", "ce_batch_add_escape",
@@ -150,6 +153,7 @@ def load(path: str):
         "ce_engine_scheduler": (i32, [vp, C.POINTER(ce_sched_desc)]),
         "ce_engine_stream": (i32, [vp, vp]),
         "ce_engine_kernel_events": (i32, [vp, vp, vp]),
+        "ce_engine_output_merge": (i32, [vp, C.c_int]),
         "ce_program_kernel": (i32, [vp, C.c_int, vp, sz]),
         "ce_program_in": (i32, [vp, u32, vp, vp, sz]),
         "ce_program_out": (i32, [vp, u32, vp, vp, sz]),
@@ -348,6 +352,9 @@ class Engine:
 
     def stream(self, hip_stream):
         return self._check(self._L.ce_engine_stream(self._h, hip_stream), "ce_engine_stream")
+
+    def output_merge(self, mode: int):
+        return self._check(self._L.ce_engine_output_merge(self._h, mode), "ce_engine_output_merge")
 
     def kernel_events(self, start=None, stop=None):
         """Records torch.cuda.Event objects (or raw hipEvent_t) around the GPU kernel."""

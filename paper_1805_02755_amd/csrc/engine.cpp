@@ -18,6 +18,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <deque>
 #include <exception>
 #include <memory>
 #include <mutex>
@@ -168,7 +169,16 @@ struct ce_engine {
   DevBuf out_dev_scratch;
   PinnedBuf out_host_scratch;   // host output when only a device output is bound
   PinnedBuf ring_buf;           // host completion ring read by the GPU's gatherers
+  int merge_mode = CE_MERGE_DMA;
   bool gather = false;          // this run's host tiles are copied into HBM by the GPU
+  bool push = false;            // this run's host packages are copied into HBM by DMA
+  hipStream_t push_stream = nullptr;
+  std::mutex push_mu;
+  std::deque<std::pair<hipEvent_t, uint64_t>> push_pending;  // copies in flight (event, bytes)
+  std::vector<hipEvent_t> push_events;                       // free events
+  uint64_t push_inflight = 0, push_total = 0;
+  std::atomic<int> push_error{0};
+  int64_t push_end_ns = 0;
   std::atomic<uint64_t> ring_count{0};
   std::atomic<uint64_t> ring_written{0};  // entries whose ring word is stored
   std::atomic<uint64_t> ring_bytes{0};    // bytes of those entries
@@ -436,6 +446,57 @@ struct ce_engine {
     ring_written.fetch_add(1, std::memory_order_release);
   }
 
+  // Byte range of the output written by granules [g0, g1).
+  void out_range(uint64_t g0, uint64_t g1, size_t* off, size_t* len) const {
+    const size_t eb = out_elem_bytes();
+    *off = (size_t)item_offset(g0) * eb;
+    *len = (size_t)(item_offset(g1) - item_offset(g0)) * eb;
+  }
+
+  // DMA merge: a finished host package's output goes host -> HBM on the push
+  // stream while the GPU keeps computing.
+  void push_package(const HostPkg& p) {
+    size_t off, len;
+    out_range(p.g0, p.g1, &off, &len);
+    if (!len) return;
+    std::lock_guard<std::mutex> lk(push_mu);
+    hipEvent_t ev = nullptr;
+    if (!push_events.empty()) {
+      ev = push_events.back();
+      push_events.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      push_error.store(1);
+      return;
+    }
+    if (hipMemcpyAsync((char*)out[0].dev_out + off, (const char*)host_out + off, len, hipMemcpyHostToDevice,
+                       push_stream) != hipSuccess ||
+        hipEventRecord(ev, push_stream) != hipSuccess) {
+      push_error.store(1);
+      push_events.push_back(ev);
+      return;
+    }
+    push_pending.emplace_back(ev, (uint64_t)len);
+    push_inflight += len;
+    push_total += len;
+  }
+  // Retires finished copies; with `wait`, blocks until in-flight bytes fit
+  // the backlog (the host is worth only as much output as PCIe carries).
+  void push_drain(uint64_t backlog) {
+    std::unique_lock<std::mutex> lk(push_mu);
+    for (;;) {
+      while (!push_pending.empty() && hipEventQuery(push_pending.front().first) == hipSuccess) {
+        push_inflight -= push_pending.front().second;
+        push_events.push_back(push_pending.front().first);
+        push_pending.pop_front();
+      }
+      if (push_inflight <= backlog || push_pending.empty()) return;
+      const hipEvent_t ev = push_pending.front().first;
+      lk.unlock();
+      if (hipEventSynchronize(ev) != hipSuccess) push_error.store(1);
+      lk.lock();
+    }
+  }
+
   // With the GPU gathering the host's output, the host is worth only as much
   // output as PCIe can carry: its claimer waits while more than
   // kGatherBacklog bytes are published but not yet copied.
@@ -464,6 +525,7 @@ struct ce_engine {
         if (t == tot) {
           uint64_t g0 = 0, g1 = 0;
           if (gather) gather_throttle();
+          if (push) push_drain(kGatherBacklog);
           const int64_t tc = now_ns();
           if (hq.n_pkgs >= hq.cap || !host_claim(&g0, &g1)) {
             if (hq.n_pkgs >= hq.cap) host_error.store(1);
@@ -493,8 +555,10 @@ struct ce_engine {
       HostPkg& pk = hq.pkgs[p];
       host_tile(pk, (uint32_t)(t - pk.base));
       if (gather) publish_host_tile(pk, (uint32_t)(t - pk.base));
-      if (pk.tiles_done.fetch_add(1, std::memory_order_acq_rel) + 1 == pk.ntiles)
+      if (pk.tiles_done.fetch_add(1, std::memory_order_acq_rel) + 1 == pk.ntiles) {
         pk.t_end.store(now_ns(), std::memory_order_release);
+        if (push) push_package(pk);
+      }
     }
   }
 
@@ -695,7 +759,11 @@ struct ce_engine {
     }
 
     // the GPU copies the host's tiles into HBM when the output lives only there
-    gather = use_gpu() && use_host() && out[0].dev_out && !out[0].host_out;
+    const bool merge_dev = use_gpu() && use_host() && out[0].dev_out && !out[0].host_out;
+    gather = merge_dev && merge_mode == CE_MERGE_GPU_GATHER;
+    push = merge_dev && merge_mode == CE_MERGE_DMA;
+    push_total = 0;
+    push_error.store(0);
     // persistent grid: resident workgroups, plus gatherers (two per XCD)
     uint32_t grid = 0, gather_wgs = 0;
     if (use_gpu()) {
@@ -820,6 +888,13 @@ struct ce_engine {
       if (__atomic_load_n(&l1->gpu_flags, __ATOMIC_ACQUIRE))
         return fail(CE_E_TIMEOUT, "run: GPU dispenser wait exceeded its bound or package table overflow");
     }
+    if (push) {
+      // the last host packages' copies finish after the host's work
+      if ((he = hipStreamSynchronize(push_stream)) != hipSuccess) return hip_fail(he, "run: output copies");
+      push_drain(0);
+      push_end_ns = now_ns();
+      if (push_error.load()) return fail(CE_E_DEVICE, "run: host output copy to the device failed");
+    }
     if (host_error.load()) return fail(CE_E_DEVICE, "run: host package table overflow");
 
     // merge outputs so each bound pointer holds the whole result
@@ -856,7 +931,7 @@ struct ce_engine {
     const auto hiv = use_host() ? host_intervals() : std::vector<std::pair<uint64_t, uint64_t>>{};
     bool issued = false;
     // host-computed ranges into the device output (unless the GPU gathered them)
-    if (use_host() && out[0].dev_out && !gather) {
+    if (use_host() && out[0].dev_out && !gather && !push) {
       for (auto& iv : hiv) {
         size_t off, len;
         bytes_of(iv.first, iv.second, &off, &len);
@@ -922,6 +997,10 @@ struct ce_engine {
       const uint64_t tg = __atomic_load_n(&l1->gpu_t_gather, __ATOMIC_ACQUIRE);
       s.t_gather = (gather && tg) ? std::max(0.0, tick_to_host_s(tg)) : 0.0;
       s.gathered_bytes = gather ? __atomic_load_n(&l1->gathered, __ATOMIC_ACQUIRE) : 0;
+      if (push) {  // the copies were seen complete after the host's work, at push_end_ns at the latest
+        s.t_gather = push_total ? (double)(push_end_ns - t0_ns) * 1e-9 : 0.0;
+        s.gathered_bytes = push_total;
+      }
       gpu_pkgs_last = np;
     }
     if (hi >= 0) {
@@ -983,6 +1062,8 @@ struct ce_engine {
     int clk = 0;
     if (hipDeviceGetAttribute(&clk, hipDeviceAttributeWallClockRate, gpu) == hipSuccess && clk > 0)
       wallclock_hz = (uint32_t)clk * 1000u;
+    if ((he = hipStreamCreateWithFlags(&push_stream, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(he, "create: copy stream");
     if ((he = hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking)) != hipSuccess)
       return hip_fail(he, "create: stream");
     stream = own_stream;
@@ -1044,6 +1125,12 @@ struct ce_engine {
   ~ce_engine() {
     pool_stop();
     if (stream) (void)hipStreamSynchronize(stream);
+    if (push_stream) {
+      (void)hipStreamSynchronize(push_stream);
+      for (auto& pe : push_pending) (void)hipEventDestroy(pe.first);
+      for (hipEvent_t ev : push_events) (void)hipEventDestroy(ev);
+      (void)hipStreamDestroy(push_stream);
+    }
     if (own_stream) (void)hipStreamDestroy(own_stream);
     if (l2) (void)hipFree(l2);
     if (l1) (void)hipHostFree(l1);
@@ -1113,6 +1200,13 @@ ce_status ce_engine_scheduler(ce_engine* e, const ce_sched_desc* s) {
 ce_status ce_engine_stream(ce_engine* e, void* hip_stream) {
   if (!e) return CE_E_INVALID;
   e->stream = hip_stream ? (hipStream_t)hip_stream : e->own_stream;
+  return CE_OK;
+}
+
+ce_status ce_engine_output_merge(ce_engine* e, int mode) {
+  if (!e) return CE_E_INVALID;
+  if (mode != CE_MERGE_DMA && mode != CE_MERGE_GPU_GATHER) return e->fail(CE_E_INVALID, "output_merge: mode %d", mode);
+  e->merge_mode = mode;
   return CE_OK;
 }
 

@@ -32,4 +32,9 @@ hipError_t hipMemset(void*, int, size_t);
 hipError_t hipMemcpy(void*, const void*, size_t, hipMemcpyKind);
 hipError_t hipMemcpyAsync(void*, const void*, size_t, hipMemcpyKind, hipStream_t);
 hipError_t hipEventRecord(hipEvent_t, hipStream_t);
+#define hipEventDisableTiming 2
+hipError_t hipEventCreateWithFlags(hipEvent_t*, unsigned);
+hipError_t hipEventDestroy(hipEvent_t);
+hipError_t hipEventQuery(hipEvent_t);
+hipError_t hipEventSynchronize(hipEvent_t);
 const char* hipGetErrorString(hipError_t);

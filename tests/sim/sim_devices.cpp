@@ -70,9 +70,17 @@ hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int) {
   return hipSuccess;
 }
 hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t, int) { *v = 100000; return hipSuccess; }
-hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) { *s = (hipStream_t)0x1; return hipSuccess; }
+// Streams are distinct tokens; the simulated GPU thread belongs to the stream
+// its kernel was launched on, and only work on that stream waits for it.
+static std::atomic<uintptr_t> g_next_stream{1};
+static std::atomic<uintptr_t> g_gpu_stream{0};
+static bool on_gpu_stream(hipStream_t s) { return (uintptr_t)s == 0 || (uintptr_t)s == g_gpu_stream.load(); }
+hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) { *s = (hipStream_t)g_next_stream.fetch_add(1); return hipSuccess; }
 hipError_t hipStreamDestroy(hipStream_t) { return hipSuccess; }
-hipError_t hipStreamSynchronize(hipStream_t) { join_gpu(); return hipSuccess; }
+hipError_t hipStreamSynchronize(hipStream_t s) {
+  if (on_gpu_stream(s)) join_gpu();
+  return hipSuccess;
+}
 hipError_t hipMalloc(void** p, size_t n) { *p = calloc(1, n ? n : 1); return *p ? hipSuccess : 2; }
 hipError_t hipFree(void* p) { free(p); return hipSuccess; }
 hipError_t hipHostMalloc(void** p, size_t n, unsigned) { *p = calloc(1, n ? n : 1); return *p ? hipSuccess : 2; }
@@ -80,12 +88,23 @@ hipError_t hipHostFree(void* p) { free(p); return hipSuccess; }
 hipError_t hipHostGetDevicePointer(void** d, void* h, unsigned) { *d = h; return hipSuccess; }
 hipError_t hipMemset(void* p, int v, size_t n) { memset(p, v, n); return hipSuccess; }
 hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) { join_gpu(); memcpy(d, s, n); return hipSuccess; }
-hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) {
-  join_gpu();  // stream order: after the kernel
+hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t st) {
+  if (on_gpu_stream(st)) join_gpu();  // stream order: after the kernel
   memcpy(d, s, n);
   return hipSuccess;
 }
 hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
+// copies are synchronous here, so events are complete as soon as recorded
+hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) {
+  *e = reinterpret_cast<hipEvent_t>(new char[1]);
+  return hipSuccess;
+}
+hipError_t hipEventDestroy(hipEvent_t e) {
+  delete[] reinterpret_cast<char*>(e);
+  return hipSuccess;
+}
+hipError_t hipEventQuery(hipEvent_t) { return hipSuccess; }
+hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
 const char* hipGetErrorString(hipError_t) { return "sim"; }
 
 namespace ce {
@@ -148,8 +167,9 @@ hipError_t persistent_blocks_per_cu(const KernelArgs&, int* b) {
   return hipSuccess;
 }
 
-hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, hipStream_t) {
+hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, hipStream_t st) {
   join_gpu();
+  g_gpu_stream.store((uintptr_t)st);
   g_gpu = std::thread([a, s] {
     uint64_t np = 0, gr = 0, stn = s.st_first, t_first = 0, t_last = 0;
     bool pre = s.pre_nt != 0;  // the package the host claimed for the GPU before the launch
@@ -250,8 +270,9 @@ hipError_t launch_bare(const KernelArgs& a, hipStream_t) {
   return hipSuccess;
 }
 
-hipError_t launch_calibrate(L1State* l1, uint32_t rounds, uint64_t, hipStream_t) {
+hipError_t launch_calibrate(L1State* l1, uint32_t rounds, uint64_t, hipStream_t st) {
   join_gpu();
+  g_gpu_stream.store((uintptr_t)st);
   g_gpu = std::thread([l1, rounds] {
     for (uint32_t i = 1; i <= rounds; ++i) {
       const int64_t t0 = now_ns();

@@ -44,9 +44,10 @@ def _coverage(L, n):
     return cov
 
 
-def _run(L, kind, size, devs, sched, host_threads=4, rates=(0.0, 0.0, 0.0)):
+def _run(L, kind, size, devs, sched, host_threads=4, rates=(0.0, 0.0, 0.0), merge=ce.CE_MERGE_DMA):
     L.sim_set_rates(*rates)
     eng = ce.Engine(L)
+    eng.output_merge(merge)
     eng.use(devs, 0, host_threads)
     if kind == "escape":
         w, h = size
@@ -216,4 +217,24 @@ def test_error_list_and_states(simlib):
     assert eng.run_status() == ce.CE_E_INVALID  # power out of range
     eng.scheduler(kind=ce.CE_SCHED_DYNAMIC)
     assert eng.run_status() == ce.CE_E_INVALID  # neither size nor count
+    eng.close()
+
+
+@pytest.mark.parametrize("merge", [ce.CE_MERGE_DMA, ce.CE_MERGE_GPU_GATHER])
+@pytest.mark.parametrize("kind,size", [("escape", (77, 301)), ("blur", (1024, 64)), ("nbody", 2000)])
+def test_both_output_merges_move_every_host_range(simlib, merge, kind, size):
+    """Device-resident output with the host in the device set: the host's
+    ranges reach the device output by DMA copies or by the GPU's gather."""
+    for sched in ("hguided", "dynamic", "static"):
+        cnt, st, tr, G = _run(simlib, kind, size, BOTH, SCHEDS[sched], rates=(20.0, 20.0, 1000.0), merge=merge)
+        assert np.all(cnt == 1)
+        if st.packages[1]:
+            assert st.gathered_bytes > 0
+
+
+def test_output_merge_rejects_unknown_mode(simlib):
+    eng = ce.Engine(simlib)
+    with pytest.raises(ce.CoexecError) as ei:
+        eng.output_merge(7)
+    assert ei.value.status == ce.CE_E_INVALID
     eng.close()

@@ -216,10 +216,30 @@ def test_repeated_coexecution_runs_cover_every_item(eng):
     wt = ce.ce_gauss5_weights(1.0)
     ref_b = O.blur5(img, O.gauss5_weights(1.0))
     for rep in range(12):
+        merge = (ce.CE_MERGE_DMA, ce.CE_MERGE_GPU_GATHER)[rep % 2]
         for sched in ("static8", "hguided", "dynamic"):
             out, st, tr = run_payload(eng, ce.CE_KERNEL_ESCAPE, escape_params(p), [p.w, p.h], None, [], (p.h, p.w),
-                                      np.uint32, BOTH, sched)
+                                      np.uint32, BOTH, sched, merge=merge)
             assert np.array_equal(out, ref_e), (rep, sched, diff_report(out, ref_e, tr))
             out, st, tr = run_payload(eng, ce.CE_KERNEL_BLUR5, ce.ce_blur5_params(1024, 40), [1024, 40], None,
-                                      [img, wt], (40, 1024), np.float32, BOTH, sched)
+                                      [img, wt], (40, 1024), np.float32, BOTH, sched, merge=merge)
             assert np.array_equal(out.view(np.uint32), ref_b.view(np.uint32)), (rep, sched, diff_report(out, ref_b, tr))
+
+
+@pytest.mark.parametrize("merge", [ce.CE_MERGE_DMA, ce.CE_MERGE_GPU_GATHER])
+def test_output_merge_modes_ragged(eng, merge):
+    """Both ways of moving the host's share into a device-resident output, on
+    ragged shapes whose rows share cache lines across package boundaries."""
+    for (w, h) in [(203, 77), (1001, 37), (4099, 23)]:
+        img = synth.blur_image(w, h, seed=w + 3 * h)
+        ref = O.blur5(img, O.gauss5_weights(1.0))
+        for sched in ("hguided", "dynamic", "static_rev"):
+            out, st, tr = run_payload(eng, ce.CE_KERNEL_BLUR5, ce.ce_blur5_params(w, h), [w, h], None,
+                                      [img, ce.ce_gauss5_weights(1.0)], (h, w), np.float32, BOTH, sched, merge=merge)
+            assert np.array_equal(out.view(np.uint32), ref.view(np.uint32)), (w, h, sched, diff_report(out, ref, tr))
+    n = 3000
+    pos = synth.nbody_bodies(n, seed=31)
+    ref = O.nbody_acc(pos, 1e-6, True)
+    out, st, tr = run_payload(eng, ce.CE_KERNEL_NBODY_ACC, ce.ce_nbody_params(n, 1e-6, 1), [n], [256], [pos], (n, 4),
+                              np.float32, BOTH, "hguided", merge=merge)
+    assert np.array_equal(out.view(np.uint32), ref.view(np.uint32))
