@@ -86,12 +86,13 @@ __device__ void publish(const T& pay, const SchedArgs& s, uint64_t tot, uint64_t
   ps->base = tot;
   ps->ntiles = nt;
   ps->t_claim = tc;
-  dev_store(&ps->t_end, (uint64_t)0);  // raised by the workgroups' reports
+  // t_end is raised by the workgroups' reports with an atomic max; ticks only
+  // grow, so whatever an earlier run left there is below every tick of this
+  // one and needs no clearing.
   if (n == 0) dev_store(&q->t_first, tc);
   dev_store(&q->n_pkgs, nk + 1);
   dev_store(&q->granules, dev_load(&q->granules) + (g1 - g0));
-  // release: the cleared end tick is in place before anyone can report to it
-  __hip_atomic_store(&s.pub[n], pub_word(g0, g1 - g0), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  dev_store(&s.pub[n], pub_word(g0, g1 - g0));  // readers spin until it is visible
   dev_store(&q->total, tot + nt);
 }
 
@@ -164,8 +165,12 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
     // workgroup, so the lock is never stormed.
     uint32_t unlocked = 0;
     if ((t + s.lookahead == tot || t == tot) &&
-        __hip_atomic_compare_exchange_strong(&q->lock, &unlocked, 1u, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
+        __hip_atomic_compare_exchange_strong(&q->lock, &unlocked, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT)) {
+      // Everything the claimer reads or writes under the lock is an
+      // agent-scope atomic, performed where every XCD sees it, so the lock
+      // needs no cache maintenance: its loads start after the CAS returned,
+      // and the unlock waits until its stores are done.
       const uint64_t w2 = dev_load(&q->total);
       const uint64_t tot2 = max_u64(w2 & kTotalMask, s.pre_nt);
       if (!(w2 & kTotalDone) && t + s.lookahead >= tot2) {
@@ -179,7 +184,8 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
           publish(pay, s, tot2, g0, g1, tc);
         }
       }
-      __hip_atomic_store(&q->lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0);
+      dev_store(&q->lock, 0u);
       continue;
     }
     if (t < tot) break;
@@ -245,10 +251,10 @@ __device__ __forceinline__ void tile_done(const SchedArgs& s, uint32_t p, uint32
 // publication words and resets the level-2 state for the next run.
 __device__ void leave(const SchedArgs& s) {
   L2State* q = s.l2;
-  // This workgroup's dispenser atomics are performed before it counts itself
-  // out (a workgroup-scope release only waits for them; an agent-scope one
-  // would also write back this XCD's L2, once per workgroup).
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  // This workgroup's dispenser atomics are done before it counts itself out
+  // (waiting for them is enough; an agent-scope release would also write back
+  // this XCD's L2, once per workgroup).
+  __builtin_amdgcn_s_waitcnt(0);
   const uint32_t ex = dev_add(&q->exit_count, 1u);
   if (ex + 1 != gridDim.x) return;
   uint64_t tf = dev_load(&q->t_first);

@@ -166,7 +166,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_serve(ServeArgs a) {
   }
   if (wave0) {
     if (lane0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_s_waitcnt(0);  // this workgroup's atomics are done before it counts itself out
       const uint32_t ex = dev_add(&a.q->exit_count, 1u);
       if (ex + 1 == gridDim.x) {
         if (dev_load(&a.q->flags)) sys_store(&a.ctl->flags, 1);
