@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--mode", choices=["device", "host"], default="device",
                     help="device: inputs and output resident in HBM; host: host buffers, PCIe inside the step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--merge", choices=["dma", "gpu"], default="dma",
+    ap.add_argument("--merge", choices=["dma", "gpu"], default="gpu",
                     help="how the host's share reaches the device output: DMA copies or the GPU's gather")
     ap.add_argument("--host-threads", type=int, default=0)
     return ap.parse_args()

@@ -189,12 +189,14 @@ ce_status ce_program_out_pattern(ce_engine* e, uint32_t outs, uint32_t items);
 /* How the host's share of a device-resident output (output bound only as a
  * device pointer, host in the device set) reaches HBM during the run
  * (section 4.2 output pattern, 1:1):
- *  CE_MERGE_DMA (default): as each host package finishes, its output range
- *    is copied host -> device by the DMA engine, overlapping the GPU's work;
- *  CE_MERGE_GPU_GATHER: a few GPU workgroups copy each finished host tile
- *    over PCIe into HBM while the others compute.
- * Either way the host claims new packages only while less than a few MiB of
- * its output is still in flight. */
+ *  CE_MERGE_GPU_GATHER (default): a few workgroups of the GPU's kernel copy
+ *    each finished host tile over PCIe into HBM while the others compute;
+ *  CE_MERGE_DMA: as each host package finishes, its output range is queued
+ *    for a host -> device DMA copy (on this runtime such copies only make
+ *    progress once the GPU's kernel stops occupying every CU, so they land
+ *    after it).
+ * Either way the host claims new packages only while less than 512 KiB of
+ * its output is still waiting to be copied. */
 #define CE_MERGE_DMA 0
 #define CE_MERGE_GPU_GATHER 1
 ce_status ce_engine_output_merge(ce_engine* e, int mode);

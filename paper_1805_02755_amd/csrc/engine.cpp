@@ -169,7 +169,7 @@ struct ce_engine {
   DevBuf out_dev_scratch;
   PinnedBuf out_host_scratch;   // host output when only a device output is bound
   PinnedBuf ring_buf;           // host completion ring read by the GPU's gatherers
-  int merge_mode = CE_MERGE_DMA;
+  int merge_mode = CE_MERGE_GPU_GATHER;
   bool gather = false;          // this run's host tiles are copied into HBM by the GPU
   bool push = false;            // this run's host packages are copied into HBM by DMA
   hipStream_t push_stream = nullptr;
@@ -500,7 +500,7 @@ struct ce_engine {
   // With the GPU gathering the host's output, the host is worth only as much
   // output as PCIe can carry: its claimer waits while more than
   // kGatherBacklog bytes are published but not yet copied.
-  static constexpr uint64_t kGatherBacklog = 2u << 20;
+  static constexpr uint64_t kGatherBacklog = 512u << 10;
   void gather_throttle() {
     const int64_t limit = now_ns() + 1'000'000'000LL;  // never wait for a stalled GPU forever
     while (ring_bytes.load(std::memory_order_relaxed) >
@@ -800,7 +800,9 @@ struct ce_engine {
       gs.chunk = (uint32_t)std::min<uint64_t>(8, std::max<uint64_t>(1, per_wg / 8));
       // blur and n-body tiles all cost the same: a fixed round-robin needs no
       // atomics; escape-time tiles vary a lot, so they are dealt dynamically
-      gs.stride = kernel_id == CE_KERNEL_ESCAPE ? 0u : 1u;
+      // (with gatherers sharing some CUs the fixed round-robin would leave the
+      // workgroups on those CUs behind, so tiles are dealt dynamically then)
+      gs.stride = (kernel_id == CE_KERNEL_ESCAPE || gather) ? 0u : 1u;
       gs.wait_ticks = (uint64_t)wallclock_hz * 60;
       if (gather) {
         const uint64_t max_host_tiles =

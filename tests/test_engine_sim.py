@@ -44,7 +44,7 @@ def _coverage(L, n):
     return cov
 
 
-def _run(L, kind, size, devs, sched, host_threads=4, rates=(0.0, 0.0, 0.0), merge=ce.CE_MERGE_DMA):
+def _run(L, kind, size, devs, sched, host_threads=4, rates=(0.0, 0.0, 0.0), merge=ce.CE_MERGE_GPU_GATHER):
     L.sim_set_rates(*rates)
     eng = ce.Engine(L)
     eng.output_merge(merge)
