@@ -34,6 +34,29 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
+DEVICE_SOURCES = ("paper_1805_02755_amd/csrc/kernels.hip", "paper_1805_02755_amd/csrc/device_tiles.hpp",
+                  "paper_1805_02755_amd/csrc/device_atomics.hpp", "paper_1805_02755_amd/csrc/device_payloads.hpp",
+                  "paper_1805_02755_amd/csrc/common.hpp")
+
+
+def measured_traffic(name):
+    """HBM bytes per dispatch from the committed counter summary, or None if
+    the device sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in rec.get("device_sources", DEVICE_SOURCES):
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec.get("device_source_sha256"):
+        return None
+    return rec.get("traffic_bytes_per_dispatch")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -295,8 +318,9 @@ def main():
     # --------------------------------------------------------- roofline
     if wl == "blur":
         achieved = sum(bytes_per_item * g for g in gpu_items) / (sum(kern_ms) * 1e-3) / 1e9
+        traffic = measured_traffic("blur5_8192_hbm_traffic.json") if args.mode == "device" else None
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes per launch",
                 "kernel": "k_persistent<Blur5Tile>", "kernel_ms": med(kern_ms),
                 "algorithmic_bytes_per_item": bytes_per_item}
     elif wl == "escape":
