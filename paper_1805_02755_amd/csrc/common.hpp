@@ -76,10 +76,10 @@ struct alignas(128) L2State {
   uint32_t n_pkgs;      // packages published
   uint32_t exit_count;  // workgroups that left
   uint32_t st_next;     // static: next band of this device
-  uint32_t pad0;
+  uint32_t exit_compute;// computing (non-gather) workgroups that left
   uint64_t granules;    // granules published
   uint64_t t_first;     // first claim tick
-  uint64_t t_last;      // latest package end tick
+  uint64_t t_last;      // tick at which the last computing workgroup left
   uint64_t gather_next; // next host completion-ring entry to copy
   uint64_t t_pre;       // start tick of the package claimed before the launch
   uint64_t t_end0;      // latest end tick reported for that package

@@ -86,9 +86,7 @@ __device__ void publish(const T& pay, const SchedArgs& s, uint64_t tot, uint64_t
   ps->base = tot;
   ps->ntiles = nt;
   ps->t_claim = tc;
-  // t_end is raised by the workgroups' reports with an atomic max; ticks only
-  // grow, so whatever an earlier run left there is below every tick of this
-  // one and needs no clearing.
+  // t_end is written by the workgroup that runs the package's last ticket.
   if (n == 0) dev_store(&q->t_first, tc);
   dev_store(&q->n_pkgs, nk + 1);
   dev_store(&q->granules, dev_load(&q->granules) + (g1 - g0));
@@ -99,27 +97,23 @@ __device__ void publish(const T& pay, const SchedArgs& s, uint64_t tot, uint64_t
 // What one workgroup knows of the ticket chain, held by the lane that talks
 // to the dispenser: tickets taken but not yet run, the published total it
 // last read (it only grows, so it is a safe lower bound), the package of its
-// last ticket, and the tiles of that package it finished but has not
-// reported yet. Reporting once per package instead of once per tile keeps
-// the contended atomics to about one per tile ticket.
+// current ticket and that ticket. Completion needs no per-tile atomics: the
+// workgroup that runs a package's last ticket stamps the package's end, and
+// the GPU's end is the moment the last workgroup leaves (a report from every
+// workgroup at the end of a run would queue ~1000 atomics on one line).
 struct Cursor {  // zero-initialised at the start of a run
   uint64_t t_next, t_end;
   uint64_t tot_seen;
   uint64_t base, g0, g1;
+  uint64_t cur_t;  // ticket of the tile being run
   uint32_t p, nt;  // nt == 0: no package yet
-  uint32_t done_cnt;
-  uint32_t pad;
-  uint64_t last_end;
 };
 
-__device__ __forceinline__ void report(const SchedArgs& s, Cursor& c) {
-  if (c.done_cnt == 0) return;
-  PkgSlot* ps = &s.pkgs[c.p];
-  dev_add(&ps->tiles_done, c.done_cnt);
-  uint64_t* te = (c.p == 0 && s.pre_nt) ? &s.l2->t_end0 : &ps->t_end;
-  __hip_atomic_fetch_max(te, c.last_end, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_fetch_max(&s.l2->t_last, c.last_end, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  c.done_cnt = 0;
+// After a tile: if it held its package's last ticket, stamp the package end.
+__device__ __forceinline__ void tile_finished(const SchedArgs& s, const Cursor& c) {
+  if (c.nt == 0 || c.cur_t + 1 != c.base + c.nt) return;
+  uint64_t* te = (c.p == 0 && s.pre_nt) ? &s.l2->t_end0 : &s.pkgs[c.p].t_end;
+  dev_store(te, now_tick());
 }
 
 // Ticket chain with lookahead. Every workgroup's first ticket is its own
@@ -131,7 +125,7 @@ __device__ __forceinline__ void report(const SchedArgs& s, Cursor& c) {
 // level-1 package, so the PCIe round trip of the claim overlaps the last
 // round of tiles. The GPU thus acts as one device towards the scheduler while
 // its workgroups share each package. Returns false when this workgroup
-// should leave (its finished tiles are reported by then).
+// should leave.
 template <class T>
 __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t* ti_out) {
   L2State* q = s.l2;
@@ -157,7 +151,6 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
     if (t + s.lookahead < tot) break;
     if (w & kTotalDone) {
       if (t < tot) break;
-      report(s, c);
       return false;
     }
     // Only two tickets may claim: the one `lookahead` before the end of the
@@ -192,7 +185,6 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
     if (++spins > s.spin_limit) {
       sys_store(&s.l1->gpu_flags, 1);
       __hip_atomic_fetch_or(&q->total, kTotalDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      report(s, c);
       return false;
     }
     // waiting workgroups poll gently so the claimer's stores are not queued
@@ -212,7 +204,6 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
       if (w == 0) {  // published by the claimer but not visible here yet
         if (++spins2 > s.spin_limit) {
           sys_store(&s.l1->gpu_flags, 1);
-          report(s, c);
           return false;
         }
         continue;
@@ -220,7 +211,6 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
       const uint64_t g0 = pub_g0(w), g1 = g0 + pub_size(w);
       const uint32_t nt = pay.ntiles(g0, g1);
       if (t < base + nt) {
-        if (p != c.p || c.nt == 0) report(s, c);
         c.p = p;
         c.base = base;
         c.g0 = g0;
@@ -232,20 +222,13 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
       ++p;
     }
   }
+  c.cur_t = t;
   *ti_out = (uint32_t)(t - c.base);
   return true;
 }
 
-// Direct mode: a package is one tile run by the workgroup that claimed it.
-__device__ __forceinline__ void tile_done(const SchedArgs& s, uint32_t p, uint32_t nt) {
-  PkgSlot* ps = &s.pkgs[p];
-  const uint32_t d = dev_add(&ps->tiles_done, 1u);
-  if (d + 1 == nt) {
-    const uint64_t te = now_tick();
-    ps->t_end = te;
-    __hip_atomic_fetch_max(&s.l2->t_last, te, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
+// Direct mode: a package is one tile, run by the workgroup that claimed it.
+__device__ __forceinline__ void tile_done(const SchedArgs& s, uint32_t p) { s.pkgs[p].t_end = now_tick(); }
 
 // The last workgroup out publishes the GPU's summary to the host, clears the
 // publication words and resets the level-2 state for the next run.
@@ -278,7 +261,6 @@ __device__ void leave(const SchedArgs& s) {
   }
   for (uint32_t i = 0; i < np && i < s.max_pkgs; ++i) {
     dev_store(&s.pub[i], (uint64_t)0);
-    dev_store(&s.pkgs[i].tiles_done, 0u);
   }
   sys_store(&s.l1->gpu_t_first, tf);
   sys_store(&s.l1->gpu_t_last, tl);
@@ -291,6 +273,7 @@ __device__ void leave(const SchedArgs& s) {
   dev_store(&q->granules, (uint64_t)0);
   dev_store(&q->t_first, (uint64_t)0);
   dev_store(&q->t_last, (uint64_t)0);
+  dev_store(&q->exit_compute, 0u);
   dev_store(&q->lock, 0u);
   dev_store(&q->gather_next, (uint64_t)0);
   dev_store(&q->exit_count, 0u);
@@ -411,7 +394,7 @@ __device__ void gather_copy(const SchedArgs& s, uint64_t off, uint32_t len) {
 // update while the other lanes keep passing the barriers, which never ends.
 template <class T>
 __global__ __launch_bounds__(kBlockThreads, 5) void k_persistent(T pay, SchedArgs s) {
-  __shared__ uint32_t sh_go, sh_p, sh_ti, sh_nt;
+  __shared__ uint32_t sh_go, sh_p, sh_ti;
   __shared__ uint64_t sh_g0, sh_g1;
   const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) == 0;
   const bool lane0 = threadIdx.x == 0;
@@ -429,7 +412,7 @@ __global__ __launch_bounds__(kBlockThreads, 5) void k_persistent(T pay, SchedArg
       if (s.pre_nt && c.t_next == 0) dev_store(&s.l2->t_pre, now_tick());
     }
   }
-  uint32_t prev_p = 0xFFFFFFFFu, prev_nt = 0;
+  uint32_t prev_p = 0xFFFFFFFFu;
   if (blockIdx.x < s.gather_wgs) {
     __shared__ uint64_t sh_off;
     __shared__ uint32_t sh_len;
@@ -465,27 +448,22 @@ __global__ __launch_bounds__(kBlockThreads, 5) void k_persistent(T pay, SchedArg
   for (;;) {
     if (wave0) {
       if (lane0) {
-        uint32_t p = 0, ti = 0, nt = 1;
+        uint32_t p = 0, ti = 0;
         uint64_t g0 = 0, g1 = 0;
         bool go;
         if (s.direct) {
-          if (prev_p != 0xFFFFFFFFu) tile_done(s, prev_p, prev_nt);
+          if (prev_p != 0xFFFFFFFFu) tile_done(s, prev_p);
           go = direct_claim(s, &p, &g0, &g1);
         } else {
-          if (prev_p != 0xFFFFFFFFu) {
-            ++c.done_cnt;
-            c.last_end = now_tick();
-          }
+          if (prev_p != 0xFFFFFFFFu) tile_finished(s, c);
           go = next_tile(pay, s, c, &ti);
           p = c.p;
           g0 = c.g0;
           g1 = c.g1;
-          nt = c.nt;
         }
         sh_go = go ? 1u : 0u;
         sh_p = p;
         sh_ti = ti;
-        sh_nt = nt;
         sh_g0 = g0;
         sh_g1 = g1;
       }
@@ -495,18 +473,21 @@ __global__ __launch_bounds__(kBlockThreads, 5) void k_persistent(T pay, SchedArg
     if (go == 0) break;
     const uint32_t p = __builtin_amdgcn_readfirstlane(sh_p);
     const uint32_t ti = __builtin_amdgcn_readfirstlane(sh_ti);
-    const uint32_t nt = __builtin_amdgcn_readfirstlane(sh_nt);
     const uint64_t g0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sh_g0 >> 32)) << 32) |
                         __builtin_amdgcn_readfirstlane((uint32_t)sh_g0);
     const uint64_t g1 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sh_g1 >> 32)) << 32) |
                         __builtin_amdgcn_readfirstlane((uint32_t)sh_g1);
     pay.run(g0, g1, ti);
     prev_p = p;
-    prev_nt = nt;
     __syncthreads();  // the tile is complete and the shared slots may be reused
   }
   if (wave0) {
-    if (lane0) leave(s);
+    if (lane0) {
+      // the last computing workgroup out marks the end of the GPU's work
+      // (gather workgroups may still be copying the host's output)
+      if (dev_add(&s.l2->exit_compute, 1u) + 1 == gridDim.x - s.gather_wgs) dev_store(&s.l2->t_last, now_tick());
+      leave(s);
+    }
   }
 }
 
