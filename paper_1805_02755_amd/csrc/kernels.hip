@@ -343,21 +343,23 @@ __device__ bool gather_entry(const SchedArgs& s, uint64_t* off, uint32_t* len) {
 
 // Host memory is reached over PCIe with a latency of microseconds, so each
 // thread issues a batch of independent loads before it stores any of them.
+// The loads are system-scope atomics: a plain load could be served from a
+// line this XCD cached while copying a neighbouring tile that shares it,
+// before the host had written this tile's part (ragged rows share lines).
 __device__ void gather_copy(const SchedArgs& s, uint64_t off, uint32_t len) {
   constexpr uint32_t kBatch = 8;
   const char* src = s.gsrc + off;
   char* dst = s.gdst + off;
-  if (((off | len) & 15u) == 0) {
-    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));  // a native vector stays in registers
-    const u32x4* a = reinterpret_cast<const u32x4*>(src);
-    u32x4* b = reinterpret_cast<u32x4*>(dst);
-    const uint32_t n = len / 16;
+  if (((off | len) & 7u) == 0) {
+    uint64_t* a = reinterpret_cast<uint64_t*>(const_cast<char*>(src));
+    uint64_t* b = reinterpret_cast<uint64_t*>(dst);
+    const uint32_t n = len / 8;
     for (uint32_t i0 = 0; i0 < n; i0 += kBlockThreads * kBatch) {
-      u32x4 v[kBatch];
+      uint64_t v[kBatch];
 #pragma unroll
       for (uint32_t k = 0; k < kBatch; ++k) {
         const uint32_t i = i0 + k * kBlockThreads + threadIdx.x;
-        if (i < n) v[k] = a[i];
+        if (i < n) v[k] = __hip_atomic_load(a + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       }
 #pragma unroll
       for (uint32_t k = 0; k < kBatch; ++k) {
@@ -366,7 +368,7 @@ __device__ void gather_copy(const SchedArgs& s, uint64_t off, uint32_t len) {
       }
     }
   } else {
-    const uint32_t* a = reinterpret_cast<const uint32_t*>(src);
+    uint32_t* a = reinterpret_cast<uint32_t*>(const_cast<char*>(src));
     uint32_t* b = reinterpret_cast<uint32_t*>(dst);
     const uint32_t n = len / 4;
     for (uint32_t i0 = 0; i0 < n; i0 += kBlockThreads * kBatch) {
@@ -374,7 +376,7 @@ __device__ void gather_copy(const SchedArgs& s, uint64_t off, uint32_t len) {
 #pragma unroll
       for (uint32_t k = 0; k < kBatch; ++k) {
         const uint32_t i = i0 + k * kBlockThreads + threadIdx.x;
-        if (i < n) v[k] = a[i];
+        if (i < n) v[k] = __hip_atomic_load(a + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       }
 #pragma unroll
       for (uint32_t k = 0; k < kBatch; ++k) {

@@ -215,8 +215,14 @@ def test_repeated_coexecution_runs_cover_every_item(eng):
     img = synth.blur_image(1024, 40, seed=1024 * 7919 + 40)
     wt = ce.ce_gauss5_weights(1.0)
     ref_b = O.blur5(img, O.gauss5_weights(1.0))
+    pr = synth.escape_region(333, 77, -1.9, 0.7, -1.1, 1.3, 700)  # ragged rows share cache lines
+    ref_r = O.escape(pr.w, pr.h, *[float(v) for v in pr.as_f32()], pr.max_iter)
     for rep in range(12):
         merge = (ce.CE_MERGE_DMA, ce.CE_MERGE_GPU_GATHER)[rep % 2]
+        for sched in ("dynamic", "hguided"):
+            out, st, tr = run_payload(eng, ce.CE_KERNEL_ESCAPE, escape_params(pr), [pr.w, pr.h], None, [],
+                                      (pr.h, pr.w), np.uint32, BOTH, sched, merge=merge)
+            assert np.array_equal(out, ref_r), (rep, sched, merge, diff_report(out, ref_r, tr))
         for sched in ("static8", "hguided", "dynamic"):
             out, st, tr = run_payload(eng, ce.CE_KERNEL_ESCAPE, escape_params(p), [p.w, p.h], None, [], (p.h, p.w),
                                       np.uint32, BOTH, sched, merge=merge)
