@@ -58,6 +58,8 @@ __device__ __forceinline__ float dpp_from_right(float edge, float v) {
                                                     false));
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // kFresh: the input may have been written after the launch began (the
 // serving kernel reuses memory while it runs), so wave-uniform reads, which
 // the compiler would serve from the scalar cache, use coherent vector loads.
@@ -155,7 +157,10 @@ struct Blur5TileT {
         if (y + 1 < r1) load_raw((int64_t)y + 3, x, xw, pend);
         float o[4];
         out4(v[k % 6], v[(k + 1) % 6], v[(k + 2) % 6], v[(k + 3) % 6], v[(k + 4) % 6], o);
-        *reinterpret_cast<float4*>(out + (size_t)y * p.w + x) = make_float4(o[0], o[1], o[2], o[3]);
+        // Streaming store: the output is not read again by this kernel, so
+        // it should not push the input rows (reused as halo) out of L2.
+        const f32x4 ov = {o[0], o[1], o[2], o[3]};
+        __builtin_nontemporal_store(ov, reinterpret_cast<f32x4*>(out + (size_t)y * p.w + x));
       }
     }
   }
@@ -187,7 +192,7 @@ struct Blur5TileT {
       float* orow = out + (size_t)y * p.w;
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        if (x + q < p.w) orow[x + q] = o[q];
+        if (x + q < p.w) __builtin_nontemporal_store(o[q], orow + x + q);
     }
   }
 
