@@ -170,11 +170,20 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
         uint64_t g0 = 0, g1 = 0;
         bool timed_out = false;
         const uint64_t tc = now_tick();
-        if (dev_load(&q->n_pkgs) >= s.max_pkgs || !claim_package(s, &g0, &g1, &timed_out)) {
-          if (timed_out || dev_load(&q->n_pkgs) >= s.max_pkgs) sys_store(&s.l1->gpu_flags, 1);
+        // slots in use: the kernel's packages plus the one claimed before the launch
+        const uint32_t pre = s.pre_nt ? 1u : 0u;
+        if (dev_load(&q->n_pkgs) + pre >= s.max_pkgs || !claim_package(s, &g0, &g1, &timed_out)) {
+          if (timed_out || dev_load(&q->n_pkgs) + pre >= s.max_pkgs) sys_store(&s.l1->gpu_flags, 1);
           dev_store(&q->total, tot2 | kTotalDone);
         } else {
           publish(pay, s, tot2, g0, g1, tc);
+          // A static plan fixes all of this device's bands in advance: publish
+          // the rest of them now rather than one claim round trip per band.
+          uint64_t tot3 = tot2 + pay.ntiles(g0, g1);
+          while (s.kind == kStatic && dev_load(&q->n_pkgs) + pre < s.max_pkgs && claim_package(s, &g0, &g1, &timed_out)) {
+            publish(pay, s, tot3, g0, g1, tc);
+            tot3 += pay.ntiles(g0, g1);
+          }
         }
       }
       __builtin_amdgcn_s_waitcnt(0);
