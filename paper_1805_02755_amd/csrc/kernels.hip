@@ -410,8 +410,14 @@ __global__ __launch_bounds__(kBlockThreads, 5) void k_persistent(T pay, SchedArg
   const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) == 0;
   const bool lane0 = threadIdx.x == 0;
   pay.load_constants();
-  // The cursor lives in LDS: only lane 0 of wave 0 uses it, and keeping it
-  // in registers across the tile loop would cost the payload occupancy.
+  // The scheduler arguments are read from LDS inside the tile loop: kept in
+  // scalar registers across the payload they would crowd out its own.
+  __shared__ SchedArgs sh_args;
+  if (threadIdx.x == 0) sh_args = s;
+  __syncthreads();
+  const SchedArgs& sa = sh_args;
+  // The cursor lives in LDS too: only lane 0 of wave 0 uses it, and keeping
+  // it in registers across the tile loop would cost the payload occupancy.
   __shared__ Cursor sh_cursor;
   Cursor& c = sh_cursor;
   if (wave0) {
@@ -462,12 +468,12 @@ __global__ __launch_bounds__(kBlockThreads, 5) void k_persistent(T pay, SchedArg
         uint32_t p = 0, ti = 0;
         uint64_t g0 = 0, g1 = 0;
         bool go;
-        if (s.direct) {
-          if (prev_p != 0xFFFFFFFFu) tile_done(s, prev_p);
-          go = direct_claim(s, &p, &g0, &g1);
+        if (sa.direct) {
+          if (prev_p != 0xFFFFFFFFu) tile_done(sa, prev_p);
+          go = direct_claim(sa, &p, &g0, &g1);
         } else {
-          if (prev_p != 0xFFFFFFFFu) tile_finished(s, c);
-          go = next_tile(pay, s, c, &ti);
+          if (prev_p != 0xFFFFFFFFu) tile_finished(sa, c);
+          go = next_tile(pay, sa, c, &ti);
           p = c.p;
           g0 = c.g0;
           g1 = c.g1;
@@ -496,8 +502,8 @@ __global__ __launch_bounds__(kBlockThreads, 5) void k_persistent(T pay, SchedArg
     if (lane0) {
       // the last computing workgroup out marks the end of the GPU's work
       // (gather workgroups may still be copying the host's output)
-      if (dev_add(&s.l2->exit_compute, 1u) + 1 == gridDim.x - s.gather_wgs) dev_store(&s.l2->t_last, now_tick());
-      leave(s);
+      if (dev_add(&sa.l2->exit_compute, 1u) + 1 == gridDim.x - sa.gather_wgs) dev_store(&sa.l2->t_last, now_tick());
+      leave(sa);
     }
   }
 }
