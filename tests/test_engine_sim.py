@@ -238,3 +238,14 @@ def test_output_merge_rejects_unknown_mode(simlib):
         eng.output_merge(7)
     assert ei.value.status == ce.CE_E_INVALID
     eng.close()
+
+
+def test_empty_index_spaces_are_refused(simlib):
+    eng = ce.Engine(simlib)
+    for kid, prm in ((ce.CE_KERNEL_ESCAPE, ce.ce_escape_params(0, 4, -2, -1, 0.01, 0.01, 8)),
+                     (ce.CE_KERNEL_BLUR5, ce.ce_blur5_params(7, 0)),
+                     (ce.CE_KERNEL_NBODY_ACC, ce.ce_nbody_params(0, 1e-6, 1))):
+        with pytest.raises(ce.CoexecError) as ei:
+            eng.program_kernel(kid, prm)
+        assert ei.value.status == ce.CE_E_INVALID
+    eng.close()

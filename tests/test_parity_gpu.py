@@ -201,6 +201,14 @@ def test_error_paths(eng):
     assert e2.run_status() == ce.CE_E_INVALID  # space does not match the image
     with pytest.raises(ce.CoexecError):
         e2.program_kernel(ce.CE_KERNEL_NBODY_ACC, ce.ce_nbody_params(10, 0.0, 1))
+    # empty index spaces are refused, not run
+    for kid, prm in ((ce.CE_KERNEL_ESCAPE, ce.ce_escape_params(0, 4, -2, -1, 0.01, 0.01, 8)),
+                     (ce.CE_KERNEL_ESCAPE, ce.ce_escape_params(4, 0, -2, -1, 0.01, 0.01, 8)),
+                     (ce.CE_KERNEL_BLUR5, ce.ce_blur5_params(0, 0)),
+                     (ce.CE_KERNEL_NBODY_ACC, ce.ce_nbody_params(0, 1e-6, 1))):
+        with pytest.raises(ce.CoexecError) as ei:
+            e2.program_kernel(kid, prm)
+        assert ei.value.status == ce.CE_E_INVALID
     e2.close()
 
 
