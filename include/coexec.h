@@ -189,12 +189,15 @@ ce_status ce_program_out_pattern(ce_engine* e, uint32_t outs, uint32_t items);
 /* How the host's share of a device-resident output (output bound only as a
  * device pointer, host in the device set) reaches HBM during the run
  * (section 4.2 output pattern, 1:1):
- *  CE_MERGE_GPU_GATHER (default): a few workgroups of the GPU's kernel copy
- *    each finished host tile over PCIe into HBM while the others compute;
- *  CE_MERGE_DMA: as each host package finishes, its output range is queued
- *    for a host -> device DMA copy (on this runtime such copies only make
- *    progress once the GPU's kernel stops occupying every CU, so they land
- *    after it).
+ *  CE_MERGE_DMA (default): as each host package finishes, its output range
+ *    is copied host -> device by the GPU's system DMA engines (split over up
+ *    to four of them), which need no compute unit and so run beside the
+ *    GPU's kernel; the run returns once every copy has landed. Refused with
+ *    CE_E_UNSUPPORTED if the GPU exposes no host-to-device copy engine; an
+ *    engine is then created with CE_MERGE_GPU_GATHER.
+ *  CE_MERGE_GPU_GATHER: a few workgroups of the GPU's kernel copy each
+ *    finished host tile over PCIe into HBM while the others compute (their
+ *    long PCIe loads slow the workgroups that share their compute units).
  * Either way the host claims new packages only while less than 512 KiB of
  * its output is still waiting to be copied. */
 #define CE_MERGE_DMA 0

@@ -41,12 +41,12 @@ def build(verbose: bool = False) -> str:
         o = os.path.join(BUILD, src + ".o")
         _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], verbose)
         objs.append(o)
-    for src in ("host_payloads.cpp", "engine.cpp", "batch.cpp", "serve.cpp"):
+    for src in ("host_payloads.cpp", "dma.cpp", "engine.cpp", "batch.cpp", "serve.cpp"):
         o = os.path.join(BUILD, src + ".o")
         _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], verbose)
         objs.append(o)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-pthread",
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-pthread", "-L" + os.path.join(ROCM, "lib"), "-lhsa-runtime64",
           "-Wl,-soname,libcoexec.so", "-Wl,--no-undefined"], verbose)
     os.replace(tmp, LIB)
     return LIB

@@ -18,7 +18,7 @@ enum SchedKind : uint32_t { kStatic = 0, kDynamic = 1, kHGuided = 2 };
 // 2-D payloads: a tile is kTileRows rows by one column block.
 constexpr uint32_t kEscapeTileRows = 16;
 constexpr uint32_t kEscapeTileCols = 64;
-constexpr uint32_t kBlurTileRows = 16;
+constexpr uint32_t kBlurTileRows = 32;
 constexpr uint32_t kBlurTileCols = 1024;  // 256 threads x 4 columns
 constexpr uint32_t kNbodyGranule = 256;   // bodies per granule (1-D lws)
 constexpr uint32_t kBlockThreads = 256;

@@ -28,6 +28,7 @@
 
 #include "../../include/coexec.h"
 #include "common.hpp"
+#include "dma.hpp"
 #include "host_payloads.hpp"
 #include "kernels.hpp"
 
@@ -169,13 +170,13 @@ struct ce_engine {
   DevBuf out_dev_scratch;
   PinnedBuf out_host_scratch;   // host output when only a device output is bound
   PinnedBuf ring_buf;           // host completion ring read by the GPU's gatherers
-  int merge_mode = CE_MERGE_GPU_GATHER;
+  int merge_mode = CE_MERGE_DMA;  // CE_MERGE_GPU_GATHER where the GPU has no copy engine
   bool gather = false;          // this run's host tiles are copied into HBM by the GPU
   bool push = false;            // this run's host packages are copied into HBM by DMA
-  hipStream_t push_stream = nullptr;
+  SdmaCopier sdma;              // the GPU's copy engines (none: CE_MERGE_DMA is unavailable)
+  char sdma_why[128] = "";
   std::mutex push_mu;
-  std::deque<std::pair<hipEvent_t, uint64_t>> push_pending;  // copies in flight (event, bytes)
-  std::vector<hipEvent_t> push_events;                       // free events
+  std::deque<std::pair<int, uint64_t>> push_pending;  // copies in flight (copier handle, bytes)
   uint64_t push_inflight = 0, push_total = 0;
   std::atomic<int> push_error{0};
   int64_t push_end_ns = 0;
@@ -453,47 +454,43 @@ struct ce_engine {
     *len = (size_t)(item_offset(g1) - item_offset(g0)) * eb;
   }
 
-  // DMA merge: a finished host package's output goes host -> HBM on the push
-  // stream while the GPU keeps computing.
+  // DMA merge: a finished host package's output goes host -> HBM on the
+  // GPU's copy engines while its kernel keeps every CU busy.
   void push_package(const HostPkg& p) {
     size_t off, len;
     out_range(p.g0, p.g1, &off, &len);
     if (!len) return;
     std::lock_guard<std::mutex> lk(push_mu);
-    hipEvent_t ev = nullptr;
-    if (!push_events.empty()) {
-      ev = push_events.back();
-      push_events.pop_back();
-    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    const int h = sdma.start((char*)out[0].dev_out + off, (const char*)host_out + off, len);
+    if (h < 0) {
       push_error.store(1);
       return;
     }
-    if (hipMemcpyAsync((char*)out[0].dev_out + off, (const char*)host_out + off, len, hipMemcpyHostToDevice,
-                       push_stream) != hipSuccess ||
-        hipEventRecord(ev, push_stream) != hipSuccess) {
-      push_error.store(1);
-      push_events.push_back(ev);
-      return;
-    }
-    push_pending.emplace_back(ev, (uint64_t)len);
+    push_pending.emplace_back(h, (uint64_t)len);
     push_inflight += len;
     push_total += len;
   }
-  // Retires finished copies; with `wait`, blocks until in-flight bytes fit
-  // the backlog (the host is worth only as much output as PCIe carries).
+  // Retires finished copies and blocks until the bytes in flight fit the
+  // backlog (the host is worth only as much output as PCIe carries). Only
+  // one thread drains at a time: the host claimer during a run, the caller
+  // after it, so a handle waited on outside the lock stays valid.
   void push_drain(uint64_t backlog) {
     std::unique_lock<std::mutex> lk(push_mu);
     for (;;) {
-      while (!push_pending.empty() && hipEventQuery(push_pending.front().first) == hipSuccess) {
+      while (!push_pending.empty() && sdma.poll(push_pending.front().first)) {
         push_inflight -= push_pending.front().second;
-        push_events.push_back(push_pending.front().first);
+        sdma.release(push_pending.front().first);
         push_pending.pop_front();
       }
       if (push_inflight <= backlog || push_pending.empty()) return;
-      const hipEvent_t ev = push_pending.front().first;
+      const int h = push_pending.front().first;
       lk.unlock();
-      if (hipEventSynchronize(ev) != hipSuccess) push_error.store(1);
+      const bool ok = sdma.wait(h, 10'000'000'000ull);
       lk.lock();
+      if (!ok) {  // a copy that does not finish in 10 s: fail the run, keep the handle
+        push_error.store(1);
+        return;
+      }
     }
   }
 
@@ -521,7 +518,16 @@ struct ce_engine {
           have = true;
           break;
         }
-        if (hq.done.load(std::memory_order_acquire)) break;
+        if (hq.done.load(std::memory_order_acquire)) {
+          // The count read above may predate the last package: the flag is
+          // set only after the final count was stored, so read it again
+          // before giving up a ticket.
+          if (t < hq.total.load(std::memory_order_acquire)) {
+            have = true;
+            break;
+          }
+          break;
+        }
         if (t == tot) {
           uint64_t g0 = 0, g1 = 0;
           if (gather) gather_throttle();
@@ -653,7 +659,10 @@ struct ce_engine {
         s->min_self = sched.min_granules[d] ? sched.min_granules[d] : def_min;
       };
       if (gi >= 0) {
-        // default minimum: one tile for every resident workgroup
+        // Default minimum: one tile for every resident workgroup. Each GPU
+        // claim is a chain of PCIe atomics that the host's output copies slow
+        // down, and each package boundary leaves partial tiles, so the GPU
+        // takes few, large packages (the host then stops claiming early).
         const uint32_t tiles_per_g = std::max<uint32_t>(1, gpu_tiles(kargs, 0, 1));
         uint64_t rows_per_tile = 1;
         while (rows_per_tile < G && gpu_tiles(kargs, 0, rows_per_tile + 1) == tiles_per_g) ++rows_per_tile;
@@ -793,8 +802,10 @@ struct ce_engine {
       gs.pkgs = (PkgSlot*)pkgs_dev.p;
       gs.pub = (uint64_t*)pub_dev.p;
       gs.max_pkgs = pkgs_dev_cap;
-      // claim the next package while a quarter round of tiles is still to be handed out
-      gs.lookahead = std::max<uint32_t>(1, (grid - gather_wgs) / 4);
+      // Claim the next package while half a round of tiles is still to be
+      // handed out: with the host in the set its output copies share PCIe
+      // with the claim's atomics, which can then take tens of microseconds.
+      gs.lookahead = std::max<uint32_t>(1, (grid - gather_wgs) / 2);
       // several tickets per atomic once there are many tiles per workgroup
       const uint64_t per_wg = gpu_tiles(kargs, 0, G) / std::max<uint32_t>(1, grid - gather_wgs);
       gs.chunk = (uint32_t)std::min<uint64_t>(8, std::max<uint64_t>(1, per_wg / 8));
@@ -892,7 +903,6 @@ struct ce_engine {
     }
     if (push) {
       // the last host packages' copies finish after the host's work
-      if ((he = hipStreamSynchronize(push_stream)) != hipSuccess) return hip_fail(he, "run: output copies");
       push_drain(0);
       push_end_ns = now_ns();
       if (push_error.load()) return fail(CE_E_DEVICE, "run: host output copy to the device failed");
@@ -1064,8 +1074,7 @@ struct ce_engine {
     int clk = 0;
     if (hipDeviceGetAttribute(&clk, hipDeviceAttributeWallClockRate, gpu) == hipSuccess && clk > 0)
       wallclock_hz = (uint32_t)clk * 1000u;
-    if ((he = hipStreamCreateWithFlags(&push_stream, hipStreamNonBlocking)) != hipSuccess)
-      return hip_fail(he, "create: copy stream");
+    if (!sdma.init(gpu, sdma_why, sizeof(sdma_why))) merge_mode = CE_MERGE_GPU_GATHER;
     if ((he = hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking)) != hipSuccess)
       return hip_fail(he, "create: stream");
     stream = own_stream;
@@ -1127,12 +1136,7 @@ struct ce_engine {
   ~ce_engine() {
     pool_stop();
     if (stream) (void)hipStreamSynchronize(stream);
-    if (push_stream) {
-      (void)hipStreamSynchronize(push_stream);
-      for (auto& pe : push_pending) (void)hipEventDestroy(pe.first);
-      for (hipEvent_t ev : push_events) (void)hipEventDestroy(ev);
-      (void)hipStreamDestroy(push_stream);
-    }
+    // SdmaCopier's destructor waits for copies still queued
     if (own_stream) (void)hipStreamDestroy(own_stream);
     if (l2) (void)hipFree(l2);
     if (l1) (void)hipHostFree(l1);
@@ -1208,6 +1212,8 @@ ce_status ce_engine_stream(ce_engine* e, void* hip_stream) {
 ce_status ce_engine_output_merge(ce_engine* e, int mode) {
   if (!e) return CE_E_INVALID;
   if (mode != CE_MERGE_DMA && mode != CE_MERGE_GPU_GATHER) return e->fail(CE_E_INVALID, "output_merge: mode %d", mode);
+  if (mode == CE_MERGE_DMA && !e->sdma.ready())
+    return e->fail(CE_E_UNSUPPORTED, "output_merge: no DMA engine (%s)", e->sdma_why);
   e->merge_mode = mode;
   return CE_OK;
 }

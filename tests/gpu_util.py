@@ -32,7 +32,7 @@ def _sched_for(name, devs):
 
 
 def run_payload(eng, kernel_id, params, gws, lws, inputs, out_shape, out_dtype, devs, sched, mode="dev",
-                host_threads=0, merge=ce.CE_MERGE_GPU_GATHER):
+                host_threads=0, merge=ce.CE_MERGE_DMA):
     """inputs: list of numpy arrays. mode: 'dev' (device-resident in and out,
     host mirror of inputs), 'host' (host pointers only), 'both' (everything
     bound on both sides). Returns (output ndarray, stats, trace)."""

@@ -257,3 +257,33 @@ def test_output_merge_modes_ragged(eng, merge):
     out, st, tr = run_payload(eng, ce.CE_KERNEL_NBODY_ACC, ce.ce_nbody_params(n, 1e-6, 1), [n], [256], [pos], (n, 4),
                               np.float32, BOTH, "hguided", merge=merge)
     assert np.array_equal(out.view(np.uint32), ref.view(np.uint32))
+
+
+def test_dma_output_seen_by_later_kernels(eng):
+    """Host rows copied into HBM by the copy engines are read correctly by the
+    next kernel on the caller's stream, also where the same buffer's lines
+    were just written by a GPU kernel (a fill) and may sit in the GPU's caches."""
+    w, h = 1001, 37
+    img = synth.blur_image(w, h, seed=w + 3 * h)
+    wt = ce.ce_gauss5_weights(1.0)
+    ref = torch.from_numpy(O.blur5(img, O.gauss5_weights(1.0)).view(np.int32)).to(DEV)
+    img_d, wt_d = torch.from_numpy(img).to(DEV), torch.from_numpy(wt).to(DEV)
+    out = torch.empty((h, w), dtype=torch.int32, device=DEV)
+    eng.use(BOTH, 0, 4)
+    eng.output_merge(ce.CE_MERGE_DMA)
+    eng.work_items([w, h])
+    eng.program_kernel(ce.CE_KERNEL_BLUR5, ce.ce_blur5_params(w, h))
+    eng.program_in(0, host=img, dev=img_d, nbytes=img.nbytes)
+    eng.program_in(1, host=wt, dev=wt_d, nbytes=wt.nbytes)
+    eng.program_out(0, dev=out, nbytes=out.numel() * 4)
+    copied = 0
+    for rep in range(16):
+        sched = ("hguided", "dynamic", "static", "static_rev")[rep % 4]
+        eng.scheduler(**SCHEDULES[sched])
+        out.fill_(-1 - rep)  # a kernel writes every line of the buffer
+        torch.cuda.synchronize()
+        eng.run()
+        copied += eng.stats().gathered_bytes
+        same = torch.eq(out, ref).all().item()  # read by a kernel on the caller's stream
+        assert same, (rep, sched, int((out != ref).sum().item()))
+    assert copied > 0  # the host did take rows
