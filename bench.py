@@ -5,12 +5,16 @@ Default workload: 5x5 Gaussian blur of an 8192 x 8192 FP32 image (pixels
 uniform in [0, 1), seed 0xB1), HGuided scheduler, GPU + every host core. A
 step is one ce_engine_run over the whole image. Inputs are resident before
 the timed region: in HBM for the GPU and mirrored in host memory for the host
-workers; the output is gathered into HBM.
+workers; the output ends in HBM (the host's rows copied by the SDMA engines
+during the run).
 
-The JSON line reports work-items/s of the co-executed run (value), the plain
-single-GPU launch of the same kernel, the engine's overhead over it, the
-balance and efficiency of section 7.3, the roofline of the persistent GPU
-kernel (timed with HIP events on its stream) and the oracle timed on the host.
+The JSON line reports work-items/s of the co-executed run (value: K runs timed
+back to back, nothing else in the loop), the plain single-GPU launch of the
+same kernel, the engine's overhead over it, the balance and efficiency of
+section 7.3 (from per-run medians, measured alike for the plain launch, the
+engine alone and the co-execution), the roofline of the persistent GPU kernel
+(timed with HIP events on its stream, in a second, untimed pass of K runs) and
+the oracle timed on the host.
 
 Other workloads: --workload escape (1024^2, max_iter 256, Static with 8
 packages, GPU + 1 host thread) and --workload nbody (65,536 bodies, Dynamic
@@ -277,8 +281,11 @@ def main():
     # ------------------------------------------------- co-execution
     T_bare, T_gpu, T_host = med(t_bare), med(t_gpu), med(t_host)
     if coexec["kind"] == ce.CE_SCHED_HGUIDED:
-        ratio = T_host / T_gpu  # computing powers from the standalone throughputs
-        coexec["power"] = [max(1, min(1 << 20, int(round(ratio)))), 1]
+        # computing powers from the standalone throughputs, the slower device at 1
+        if T_host >= T_gpu:
+            coexec["power"] = [max(1, min(1 << 20, int(round(T_host / T_gpu)))), 1]
+        else:
+            coexec["power"] = [1, max(1, min(1 << 20, int(round(T_gpu / T_host))))]
     elif coexec["kind"] == ce.CE_SCHED_STATIC:
         coexec["props"] = [max(0.0, 1.0 - T_gpu / (T_gpu + T_host))]
     eng.use(ce.CE_DEV_GPU | ce.CE_DEV_HOST, 0, host_threads)
