@@ -13,6 +13,9 @@
 namespace ce {
 
 struct EscapeTile {
+  // workgroups per CU the persistent kernel is compiled for (1: no bound; a
+  // bound of 5 made this latency-bound loop measurably slower)
+  static constexpr int kMinBlocksPerCu = 1;
   ce_escape_params p;
   uint32_t* out;
   __device__ void load_constants() {}
@@ -65,6 +68,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // the compiler would serve from the scalar cache, use coherent vector loads.
 template <bool kFresh>
 struct Blur5TileT {
+  // five resident workgroups per CU keep enough loads in flight for HBM
+  static constexpr int kMinBlocksPerCu = 5;
   ce_blur5_params p;
   const float* in;
   const float* wt;
@@ -236,6 +241,7 @@ __device__ __forceinline__ float rsqrt_lomont(float x) {
 // bodies are staged through LDS 256 at a time.
 template <bool STRICT>
 struct NbodyTile {
+  static constexpr int kMinBlocksPerCu = 1;  // one granule per workgroup: no bound
   ce_nbody_params p;
   const float4* pos;
   float4* out;

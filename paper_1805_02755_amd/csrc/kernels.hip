@@ -404,7 +404,7 @@ __device__ void gather_copy(const SchedArgs& s, uint64_t off, uint32_t len) {
 // rotate the loop so that lane 0 leaves an inner loop through an exec-mask
 // update while the other lanes keep passing the barriers, which never ends.
 template <class T>
-__global__ __launch_bounds__(kBlockThreads, 5) void k_persistent(T pay, SchedArgs s) {
+__global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persistent(T pay, SchedArgs s) {
   __shared__ uint32_t sh_go, sh_p, sh_ti;
   __shared__ uint64_t sh_g0, sh_g1;
   const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) == 0;
