@@ -494,6 +494,11 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
                         __builtin_amdgcn_readfirstlane((uint32_t)sh_g0);
     const uint64_t g1 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sh_g1 >> 32)) << 32) |
                         __builtin_amdgcn_readfirstlane((uint32_t)sh_g1);
+    // Nothing of the scheduler's may still be in flight when the payload
+    // starts: its pointers come from LDS, so its accesses are flat ones,
+    // which count against the LDS counter too; with one pending, every LDS
+    // wait inside the payload would have to drain all of them.
+    __builtin_amdgcn_s_waitcnt(0);
     pay.run(g0, g1, ti);
     prev_p = p;
     __syncthreads();  // the tile is complete and the shared slots may be reused
