@@ -114,7 +114,7 @@ struct SchedArgs {
   uint32_t kind;
   uint32_t n_dev;       // devices in the set (HGuided n)
   uint32_t k;           // HGuided k
-  uint32_t direct;      // Dynamic with one tile per package: claim per workgroup
+  uint32_t batch;       // Dynamic: packages taken by one claim (>= 1)
   uint64_t G;           // granules in the index space
   uint64_t pkg;         // Dynamic package size (granules)
   uint64_t P_self;      // HGuided power of this device
@@ -137,6 +137,10 @@ struct SchedArgs {
   uint64_t pre_g0, pre_g1;
   uint32_t pre_nt;      // its tiles
   uint32_t st_first;    // static: bands taken by that claim
+  // Dynamic: tiles of every GPU package but the one that ends the index
+  // space, so ticket t lies in package t / dyn_tiles (0: walk the packages)
+  uint32_t dyn_tiles;
+  uint32_t pad_dyn;
   // gather of host-computed output into HBM (gather_wgs == 0: off)
   const uint64_t* ring; // device view of the host completion ring
   const char* gsrc;     // device view of the host output buffer

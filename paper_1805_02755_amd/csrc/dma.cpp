@@ -65,6 +65,39 @@ bool SdmaCopier::init(int hip_device, char* why, size_t why_len) {
     if (mask & (1u << b)) engine_ids_[n_engines_++] = 1u << b;
   for (uint32_t i = 0; i < kSlots; ++i) free_[i] = kSlots - 1 - i;
   n_free_ = kSlots;
+  // The first copy on an engine sets up its queue and takes milliseconds:
+  // pay that here, outside any run.
+  void* hbuf = nullptr;
+  void* dbuf = nullptr;
+  bool pending = false;  // a test copy that did not finish keeps its buffers
+  if (hipHostMalloc(&hbuf, 4096, hipHostMallocDefault) == hipSuccess && hipMalloc(&dbuf, 4096) == hipSuccess) {
+    hsa_signal_t sg;
+    if (hsa_signal_create(1, 0, nullptr, &sg) == HSA_STATUS_SUCCESS) {
+      uint32_t usable = 0;
+      for (uint32_t e = 0; e < n_engines_; ++e) {
+        hsa_signal_store_screlease(sg, 1);
+        if (hsa_amd_memory_async_copy_on_engine(dbuf, s.gpu, hbuf, s.cpu, 4096, 0, nullptr, sg,
+                                                (hsa_amd_sdma_engine_id_t)engine_ids_[e], true) != HSA_STATUS_SUCCESS)
+          continue;
+        // bounded wait: the hint is in system-timestamp ticks, so re-check the value
+        for (int i = 0; i < 20 && hsa_signal_load_scacquire(sg) > 0; ++i)
+          hsa_signal_wait_scacquire(sg, HSA_SIGNAL_CONDITION_LT, 1, 100'000'000ull, HSA_WAIT_STATE_BLOCKED);
+        if (hsa_signal_load_scacquire(sg) > 0) break;  // an engine that does not finish: leave the signal
+        engine_ids_[usable++] = engine_ids_[e];
+      }
+      pending = hsa_signal_load_scacquire(sg) > 0;
+      n_engines_ = usable;
+      if (!pending) hsa_signal_destroy(sg);
+    }
+  }
+  if (!pending) {
+    if (dbuf) (void)hipFree(dbuf);
+    if (hbuf) (void)hipHostFree(hbuf);
+  }
+  if (n_engines_ == 0) {
+    snprintf(why, why_len, "no host-to-device copy engine completed a test copy");
+    return false;
+  }
   return true;
 }
 

@@ -333,7 +333,6 @@ struct ce_engine {
   void gpu_preclaim(SchedArgs& gs) {
     gs.pre_nt = 0;
     gs.st_first = 0;
-    if (gs.direct) return;
     uint64_t g0 = 0, g1 = 0;
     if (gs.kind == kStatic) {
       if (gs.st_begin >= gs.st_end) return;
@@ -641,7 +640,6 @@ struct ce_engine {
       if (pkg > kPubMaxSize) return fail(CE_E_INVALID, "dynamic: package larger than 2^24-1 granules");
       gpu_s->pkg = host_s->pkg = pkg;
       *gpu_max = *host_max = ceil_div(G, pkg) + 1;
-      if (gi >= 0 && gpu_tiles(kargs, 0, std::min(pkg, G)) == 1) gpu_s->direct = 1;
       return CE_OK;
     }
     if (sched.kind == CE_SCHED_HGUIDED) {
@@ -806,6 +804,15 @@ struct ce_engine {
       // handed out: with the host in the set its output copies share PCIe
       // with the claim's atomics, which can then take tens of microseconds.
       gs.lookahead = std::max<uint32_t>(1, (grid - gather_wgs) / 2);
+      // A Dynamic claim takes as many packages as half a round of tiles holds:
+      // the GPU's workgroups are that many requesters, and one PCIe atomic
+      // per package would serialise them (about 1 us each).
+      gs.batch = 1;
+      gs.dyn_tiles = 0;
+      if (gs.kind == kDynamic) {
+        gs.dyn_tiles = std::max<uint32_t>(1, gpu_tiles(kargs, 0, std::min(gs.pkg, G)));
+        gs.batch = std::max<uint32_t>(1, gs.lookahead / gs.dyn_tiles);
+      }
       // several tickets per atomic once there are many tiles per workgroup
       const uint64_t per_wg = gpu_tiles(kargs, 0, G) / std::max<uint32_t>(1, grid - gather_wgs);
       gs.chunk = (uint32_t)std::min<uint64_t>(8, std::max<uint64_t>(1, per_wg / 8));

@@ -49,10 +49,12 @@ __device__ bool claim_package(const SchedArgs& s, uint64_t* g0, uint64_t* g1, bo
     return true;
   }
   if (s.kind == kDynamic) {
-    const uint64_t a = sys_fetch_add(&s.l1->next, s.pkg);
+    // `batch` consecutive packages with one atomic (split up by the caller)
+    const uint64_t span = s.pkg * s.batch;
+    const uint64_t a = sys_fetch_add(&s.l1->next, span);
     if (a >= s.G) return false;
     *g0 = a;
-    *g1 = (a + s.pkg < s.G) ? a + s.pkg : s.G;
+    *g1 = (a + span < s.G) ? a + span : s.G;
     return true;
   }
   // HGuided: the size follows the pending granules at the moment of the claim.
@@ -92,6 +94,60 @@ __device__ void publish(const T& pay, const SchedArgs& s, uint64_t tot, uint64_t
   dev_store(&q->granules, dev_load(&q->granules) + (g1 - g0));
   dev_store(&s.pub[n], pub_word(g0, g1 - g0));  // readers spin until it is visible
   dev_store(&q->total, tot + nt);
+}
+
+// Publishes the packages of one Dynamic claim ([g0, g1) holds `batch`
+// packages of `pkg` granules, the last one possibly short). The publication
+// words and the published count go out first, so workgroups start on the
+// packages at once; the trace records, which only the host reads after the
+// run, follow.
+template <class T>
+__device__ void publish_dynamic(const T& pay, const SchedArgs& s, uint64_t tot, uint64_t g0, uint64_t g1,
+                                uint64_t tc) {
+  // The arguments live in LDS and the stores below are flat ones, which may
+  // alias LDS and count against its counter: with the fields re-read from
+  // LDS after every store, each package would wait for all stores before it.
+  L2State* const q = s.l2;
+  PkgSlot* const pkgs = s.pkgs;
+  uint64_t* const pub = s.pub;
+  const uint64_t pkg = s.pkg;
+  const uint32_t max_pkgs = s.max_pkgs;
+  const uint32_t pre = s.pre_nt ? 1u : 0u;
+  const uint32_t nk0 = dev_load(&q->n_pkgs);
+  // packages that fit the table (the host sizes it so that all do)
+  uint64_t end = g1;
+  const uint64_t room = max_pkgs > nk0 + pre ? (uint64_t)(max_pkgs - nk0 - pre) : 0;
+  if (ceil_div(g1 - g0, pkg) > room) end = g0 + room * pkg;
+  const uint64_t tot0 = tot;  // first ticket of the claim
+  uint32_t nk = nk0;
+  for (uint64_t x = g0; x < end; x += pkg) {
+    const uint64_t y = (x + pkg < end) ? x + pkg : end;
+    dev_store(&pub[nk + pre], pub_word(x, y - x));
+    tot += pay.ntiles(x, y);
+    ++nk;
+    // the published count is the line every waiting workgroup polls: move
+    // it in steps of 32 packages rather than once per package
+    if (((nk - nk0) & 31u) == 0) dev_store(&q->total, tot);
+  }
+  dev_store(&q->total, tot);
+  uint64_t base = tot0;
+  if (nk0 + pre == 0) dev_store(&q->t_first, tc);
+  nk = nk0;
+  for (uint64_t x = g0; x < end; x += pkg) {
+    const uint64_t y = (x + pkg < end) ? x + pkg : end;
+    const uint32_t nt = pay.ntiles(x, y);
+    PkgSlot* ps = &pkgs[nk + pre];
+    ps->g0 = x;
+    ps->g1 = y;
+    ps->base = base;
+    ps->ntiles = nt;
+    ps->t_claim = tc;
+    base += nt;
+    ++nk;
+  }
+  dev_store(&q->n_pkgs, nk);
+  dev_store(&q->granules, dev_load(&q->granules) + (end - g0));
+  if (end < g1) sys_store(&s.l1->gpu_flags, 1);
 }
 
 // What one workgroup knows of the ticket chain, held by the lane that talks
@@ -175,6 +231,8 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
         if (dev_load(&q->n_pkgs) + pre >= s.max_pkgs || !claim_package(s, &g0, &g1, &timed_out)) {
           if (timed_out || dev_load(&q->n_pkgs) + pre >= s.max_pkgs) sys_store(&s.l1->gpu_flags, 1);
           dev_store(&q->total, tot2 | kTotalDone);
+        } else if (s.kind == kDynamic) {
+          publish_dynamic(pay, s, tot2, g0, g1, tc);
         } else {
           publish(pay, s, tot2, g0, g1, tc);
           // A static plan fixes all of this device's bands in advance: publish
@@ -197,17 +255,25 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
       return false;
     }
     // waiting workgroups poll gently so the claimer's stores are not queued
-    // behind their loads
+    // behind their loads; those far from the published end poll least
     if (t - tot < 64)
       __builtin_amdgcn_s_sleep(4);
-    else
+    else if (t - tot < 512)
       __builtin_amdgcn_s_sleep(32);
+    else
+      __builtin_amdgcn_s_sleep(127);
   }
   if (c.nt == 0 || t >= c.base + c.nt) {
     // Walk the publication words forward from the last package used; a
-    // workgroup's tickets only grow, so it never walks back.
+    // workgroup's tickets only grow, so it never walks back. Dynamic
+    // packages all have the same tile count, so the walk starts at the
+    // ticket's own package (one load instead of one per package before it).
     uint32_t p = c.nt ? c.p : 0;
     uint64_t base = c.nt ? c.base : 0;
+    if (s.dyn_tiles) {
+      p = (uint32_t)(t / s.dyn_tiles);
+      base = (uint64_t)p * s.dyn_tiles;
+    }
     for (uint64_t spins2 = 0;;) {
       const uint64_t w = (p == 0 && s.pre_nt) ? pub_word(s.pre_g0, s.pre_g1 - s.pre_g0) : dev_load(&s.pub[p]);
       if (w == 0) {  // published by the claimer but not visible here yet
@@ -236,8 +302,6 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
   return true;
 }
 
-// Direct mode: a package is one tile, run by the workgroup that claimed it.
-__device__ __forceinline__ void tile_done(const SchedArgs& s, uint32_t p) { s.pkgs[p].t_end = now_tick(); }
 
 // The last workgroup out publishes the GPU's summary to the host, clears the
 // publication words and resets the level-2 state for the next run.
@@ -290,35 +354,6 @@ __device__ void leave(const SchedArgs& s) {
   dev_store(&q->t_gather, (uint64_t)0);
   sys_store(&s.l1->gpu_t_leave, now_tick());  // lets the host re-anchor its clock mapping
   sys_store_release(&s.l1->gpu_run_id, s.run_id);
-}
-
-// Direct claim (Dynamic with single-tile packages): the workgroup takes its
-// own package from level 1. Returns false when the dispenser is exhausted.
-__device__ bool direct_claim(const SchedArgs& s, uint32_t* slot_out, uint64_t* g0, uint64_t* g1) {
-  const uint64_t tc = now_tick();
-  const uint64_t a = sys_fetch_add(&s.l1->next, s.pkg);
-  if (a >= s.G) return false;
-  const uint64_t b = (a + s.pkg < s.G) ? a + s.pkg : s.G;
-  const uint32_t slot = dev_add(&s.l2->n_pkgs, 1u);
-  if (slot >= s.max_pkgs) {  // the host sizes the table so this cannot happen
-    sys_store(&s.l1->gpu_flags, 1);
-    return false;
-  }
-  PkgSlot* ps = &s.pkgs[slot];
-  ps->g0 = a;
-  ps->g1 = b;
-  ps->base = 0;
-  ps->ntiles = 1;
-  ps->t_claim = tc;
-  ps->t_end = 0;
-  uint64_t zero = 0;
-  __hip_atomic_compare_exchange_strong(&s.l2->t_first, &zero, tc, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-  dev_add(&s.l2->granules, b - a);
-  *slot_out = slot;
-  *g0 = a;
-  *g1 = b;
-  return true;
 }
 
 // Gather (device-resident output with the host in the device set): the host
@@ -468,16 +503,11 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
         uint32_t p = 0, ti = 0;
         uint64_t g0 = 0, g1 = 0;
         bool go;
-        if (sa.direct) {
-          if (prev_p != 0xFFFFFFFFu) tile_done(sa, prev_p);
-          go = direct_claim(sa, &p, &g0, &g1);
-        } else {
-          if (prev_p != 0xFFFFFFFFu) tile_finished(sa, c);
-          go = next_tile(pay, sa, c, &ti);
-          p = c.p;
-          g0 = c.g0;
-          g1 = c.g1;
-        }
+        if (prev_p != 0xFFFFFFFFu) tile_finished(sa, c);
+        go = next_tile(pay, sa, c, &ti);
+        p = c.p;
+        g0 = c.g0;
+        g1 = c.g1;
         sh_go = go ? 1u : 0u;
         sh_p = p;
         sh_ti = ti;
