@@ -664,7 +664,10 @@ struct ce_engine {
         const uint32_t tiles_per_g = std::max<uint32_t>(1, gpu_tiles(kargs, 0, 1));
         uint64_t rows_per_tile = 1;
         while (rows_per_tile < G && gpu_tiles(kargs, 0, rows_per_tile + 1) == tiles_per_g) ++rows_per_tile;
-        const uint64_t def = std::max<uint64_t>(1, ceil_div((uint64_t)grid, tiles_per_g) * rows_per_tile);
+        uint64_t def = std::max<uint64_t>(1, ceil_div((uint64_t)grid, tiles_per_g) * rows_per_tile);
+        // ... but never more than the GPU's proportional share of the space
+        // (where the host is the faster device the GPU must leave it work)
+        def = std::min<uint64_t>(def, std::max<uint64_t>(1, G * P[gi] / sumP));
         fill(gpu_s, gi, std::min<uint64_t>(def, G));
         *gpu_max = G / std::max<uint64_t>(1, gpu_s->min_self) + 2;
       }
