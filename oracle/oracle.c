@@ -145,6 +145,38 @@ void orc_nbody_acc(const float* pos4, uint32_t n, float eps2, int strict, float*
   for (uint32_t i = 0; i < n; ++i) orc_nbody_acc_body(pos4, n, eps2, strict, i, out4 + 4 * (size_t)i);
 }
 
+/* N-body integration step (the NBody program of section 6.2: positions and
+ * velocities in, positions and velocities out, a time step and a squared
+ * softening). The paper shows the program's buffers and arguments, not its
+ * update; the update here is the constant-acceleration step of elementary
+ * kinematics over dt, with a_i the acceleration of orc_nbody_acc_body:
+ *   v' = v + a dt,   x' = x + v dt + a dt^2 / 2,
+ * evaluated per component in FP32 as h = (dt * dt) * 0.5, x' = (x + v*dt) + a*h,
+ * v' = v + a*dt. The mass (w of the position) and w of the velocity are copied. */
+void orc_nbody_step_body(const float* pos4, const float* vel4, uint32_t n, float eps2, float dt, int strict,
+                         uint32_t i, float pos_out[4], float vel_out[4]) {
+  float a[4];
+  orc_nbody_acc_body(pos4, n, eps2, strict, i, a);
+  const float h = (dt * dt) * 0.5f;
+  for (int c = 0; c < 3; ++c) {
+    const float x = pos4[4 * (size_t)i + c];
+    const float v = vel4[4 * (size_t)i + c];
+    const float vdt = v * dt;
+    const float ah = a[c] * h;
+    pos_out[c] = (x + vdt) + ah;
+    const float adt = a[c] * dt;
+    vel_out[c] = v + adt;
+  }
+  pos_out[3] = pos4[4 * (size_t)i + 3];
+  vel_out[3] = vel4[4 * (size_t)i + 3];
+}
+
+void orc_nbody_step(const float* pos4, const float* vel4, uint32_t n, float eps2, float dt, int strict,
+                    float* pos_out4, float* vel_out4) {
+  for (uint32_t i = 0; i < n; ++i)
+    orc_nbody_step_body(pos4, vel4, n, eps2, dt, strict, i, pos_out4 + 4 * (size_t)i, vel_out4 + 4 * (size_t)i);
+}
+
 /* The same sum in double for bodies [i0, i1): error reference for FP32. */
 void orc_nbody_acc_f64(const float* pos4, uint32_t n, double eps2, uint32_t i0, uint32_t i1,
                        double* out3) {

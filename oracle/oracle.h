@@ -45,6 +45,13 @@ void orc_nbody_acc_body(const float* pos4, uint32_t n, float eps2, int strict, u
 void orc_nbody_acc(const float* pos4, uint32_t n, float eps2, int strict, float* out4);
 void orc_nbody_acc_f64(const float* pos4, uint32_t n, double eps2, uint32_t i0, uint32_t i1,
                        double* out3);
+/* ---- N-body integration step (NBody program of section 6.2: pos and vel
+ * in, pos and vel out, dt, eps2): v' = v + a dt, x' = x + v dt + a dt^2/2 with
+ * a from orc_nbody_acc_body; mass and vel w copied. */
+void orc_nbody_step_body(const float* pos4, const float* vel4, uint32_t n, float eps2, float dt, int strict,
+                         uint32_t i, float pos_out[4], float vel_out[4]);
+void orc_nbody_step(const float* pos4, const float* vel4, uint32_t n, float eps2, float dt, int strict,
+                    float* pos_out4, float* vel_out4);
 
 /* ---- schedulers (section 5.3) */
 /* Static: n devices, props[0..n-2] fractions in device order, last gets the

@@ -52,6 +52,11 @@ def lib():
         L.orc_nbody_acc.argtypes = [_f32p, C.c_uint32, C.c_float, C.c_int, _f32p]
         L.orc_nbody_acc_f64.restype = None
         L.orc_nbody_acc_f64.argtypes = [_f32p, C.c_uint32, C.c_double, C.c_uint32, C.c_uint32, _f64p]
+        L.orc_nbody_step_body.restype = None
+        L.orc_nbody_step_body.argtypes = [_f32p, _f32p, C.c_uint32, C.c_float, C.c_float, C.c_int, C.c_uint32,
+                                          _f32p, _f32p]
+        L.orc_nbody_step.restype = None
+        L.orc_nbody_step.argtypes = [_f32p, _f32p, C.c_uint32, C.c_float, C.c_float, C.c_int, _f32p, _f32p]
         L.orc_static_plan.restype = C.c_int
         L.orc_static_plan.argtypes = [C.c_uint64, C.c_uint32, _f64p, _u32p, C.c_uint32, _u64p, _u64p]
         L.orc_hguided_size.restype = C.c_uint64
@@ -109,6 +114,24 @@ def nbody_acc_body(pos4: np.ndarray, eps2: float, i: int, strict: bool = True) -
     out = np.empty(4, dtype=np.float32)
     lib().orc_nbody_acc_body(pos4, pos4.shape[0], eps2, int(strict), i, out)
     return out
+
+
+def nbody_step(pos4: np.ndarray, vel4: np.ndarray, eps2: float, dt: float, strict: bool = True):
+    """One integration step of every body: returns (positions, velocities)."""
+    pos4 = np.ascontiguousarray(pos4, dtype=np.float32)
+    vel4 = np.ascontiguousarray(vel4, dtype=np.float32)
+    assert pos4.shape == vel4.shape and pos4.shape[1] == 4
+    po, vo = np.empty_like(pos4), np.empty_like(vel4)
+    lib().orc_nbody_step(pos4, vel4, pos4.shape[0], eps2, dt, int(strict), po, vo)
+    return po, vo
+
+
+def nbody_step_body(pos4: np.ndarray, vel4: np.ndarray, eps2: float, dt: float, i: int, strict: bool = True):
+    pos4 = np.ascontiguousarray(pos4, dtype=np.float32)
+    vel4 = np.ascontiguousarray(vel4, dtype=np.float32)
+    po, vo = np.empty(4, np.float32), np.empty(4, np.float32)
+    lib().orc_nbody_step_body(pos4, vel4, pos4.shape[0], eps2, dt, int(strict), i, po, vo)
+    return po, vo
 
 
 def nbody_acc_f64(pos4: np.ndarray, eps2: float, i0: int = 0, i1: int | None = None) -> np.ndarray:

@@ -118,6 +118,15 @@ def nbody_bodies(n: int = 65536, seed: int = SEED_NBODY) -> np.ndarray:
     return out
 
 
+def nbody_velocities(n: int = 65536, seed: int = SEED_NBODY) -> np.ndarray:
+    """(n, 4) FP32 array of (vx, vy, vz, 0): components uniform in [-0.5, 0.5)."""
+    out = np.zeros((n, 4), dtype=np.float32)
+    out[:, 0] = uniform_f32(seed, 5, n, -0.5, 0.5)
+    out[:, 1] = uniform_f32(seed, 6, n, -0.5, 0.5)
+    out[:, 2] = uniform_f32(seed, 7, n, -0.5, 0.5)
+    return out
+
+
 # --------------------------------------------------------------------------
 # Batched escape-time jobs
 # --------------------------------------------------------------------------

@@ -230,6 +230,90 @@ def test_nbody_self_term_is_zero():
     assert np.array_equal(O.nbody_acc(pos, 1e-6, True), np.zeros((1, 4), np.float32))
 
 
+# ------------------------------------------- n-body integration step
+def _bodies_and_velocities(n, seed):
+    from paper_1805_02755_amd.synth import nbody_bodies, nbody_velocities
+    return nbody_bodies(n, seed=seed), nbody_velocities(n, seed=seed)
+
+
+def test_nbody_step_zero_dt_is_identity():
+    pos, vel = _bodies_and_velocities(40, 3)
+    for strict in (True, False):
+        po, vo = O.nbody_step(pos, vel, 1e-6, 0.0, strict)
+        assert np.array_equal(po, pos) and np.array_equal(vo, vel)
+
+
+def test_nbody_step_single_body_exact():
+    """One body feels no force: it moves in a straight line. With values
+    whose products and sums are exact in FP32 the result is exact."""
+    pos = np.array([[1.0, 2.0, 3.0, 5.0]], np.float32)
+    vel = np.array([[2.0, -4.0, 0.5, 7.0]], np.float32)
+    po, vo = O.nbody_step(pos, vel, 1e-6, 0.25, True)
+    assert np.array_equal(po, np.array([[1.5, 1.0, 3.125, 5.0]], np.float32))
+    assert np.array_equal(vo, vel)
+
+
+def test_nbody_step_massless_bodies_drift():
+    """Massless bodies exert no force: velocities are unchanged bit for bit and
+    positions advance by v dt (two roundings from the FP64 value)."""
+    pos, vel = _bodies_and_velocities(64, 8)
+    pos[:, 3] = 0.0
+    dt = 0.01
+    po, vo = O.nbody_step(pos, vel, 1e-6, dt, True)
+    assert np.array_equal(vo, vel)
+    exact = pos[:, :3].astype(np.float64) + vel[:, :3].astype(np.float64) * dt
+    assert np.all(np.abs(po[:, :3] - exact) <= 2 * np.spacing(np.abs(exact).astype(np.float32)))
+
+
+def test_nbody_step_follows_the_acceleration():
+    """v' - v = a dt and x' - x = v dt + a dt^2/2 against the (separately
+    pinned) acceleration, in FP64 within the few roundings of each update."""
+    pos, vel = _bodies_and_velocities(128, 12)
+    dt, eps2 = 0.003, 1e-6
+    a = O.nbody_acc(pos, eps2, True)[:, :3].astype(np.float64)
+    po, vo = O.nbody_step(pos, vel, eps2, dt, True)
+    v = vel[:, :3].astype(np.float64)
+    x = pos[:, :3].astype(np.float64)
+    v_ref = v + a * dt
+    x_ref = x + v * dt + a * (dt * dt / 2)
+    tol_v = 2 * np.spacing(np.abs(v_ref).astype(np.float32)) + 1e-7 * np.abs(a * dt)
+    tol_x = 3 * np.spacing(np.abs(x_ref).astype(np.float32)) + 1e-7 * np.abs(a * dt * dt)
+    assert np.all(np.abs(vo[:, :3] - v_ref) <= tol_v)
+    assert np.all(np.abs(po[:, :3] - x_ref) <= tol_x)
+    assert np.array_equal(po[:, 3], pos[:, 3]) and np.array_equal(vo[:, 3], vel[:, 3])
+
+
+def test_nbody_step_conserves_momentum():
+    pos, vel = _bodies_and_velocities(200, 5)
+    m = pos[:, 3].astype(np.float64)
+    dt = 0.01
+    po, vo = O.nbody_step(pos, vel, 1e-6, dt, True)
+    before = (m[:, None] * vel[:, :3]).sum(0)
+    after = (m[:, None] * vo[:, :3].astype(np.float64)).sum(0)
+    a = O.nbody_acc(pos, 1e-6, True)[:, :3].astype(np.float64)
+    scale = (m[:, None] * np.abs(a)).sum(0) * dt + (m[:, None] * np.abs(vel[:, :3])).sum(0) * 1e-6
+    assert np.all(np.abs(after - before) <= 1e-4 * scale)
+
+
+def test_nbody_step_two_body_circular_orbit():
+    """Two unit masses at distance 1 on a circular orbit about their centre
+    (speed sqrt(1/2) each): a quarter period of small steps keeps them at
+    distance 1 and turns the line between them by 90 degrees."""
+    r = 0.5
+    vc = np.sqrt(1.0 / (4.0 * r))
+    pos = np.array([[-r, 0, 0, 1], [r, 0, 0, 1]], np.float32)
+    vel = np.array([[0, -vc, 0, 0], [0, vc, 0, 0]], np.float32)
+    period = 2 * np.pi * r / vc
+    steps = 1000
+    dt = np.float32(period / 4 / steps)
+    for _ in range(steps):
+        pos, vel = O.nbody_step(pos, vel, 1e-12, float(dt), True)
+    d = pos[1, :3].astype(np.float64) - pos[0, :3].astype(np.float64)
+    assert abs(np.linalg.norm(d) - 1.0) < 0.01
+    angle = np.degrees(np.arctan2(d[1], d[0]))
+    assert abs(angle - 90.0) < 2.0
+
+
 # -------------------------------------------------------------- schedulers
 def test_static_listing_example():
     g = _gold("static_listing_example.json")
