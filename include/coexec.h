@@ -53,6 +53,7 @@ typedef int32_t ce_status;
 #define CE_KERNEL_ESCAPE 1    /* escape-time fractal (Mandelbrot), 2-D, 0 in : 1 out  */
 #define CE_KERNEL_BLUR5 2     /* 5x5 Gaussian blur, 2-D, 2 in (image, weights) : 1 out */
 #define CE_KERNEL_NBODY_ACC 3 /* all-pairs N-body acceleration, 1-D, 1 in : 1 out      */
+#define CE_KERNEL_NBODY_STEP 4 /* N-body integration step, 1-D, 2 in (pos, vel) : 2 out (pos, vel) */
 
 /* Schedulers (section 5.3). */
 #define CE_SCHED_STATIC 0
@@ -88,6 +89,22 @@ typedef struct {
   float eps2;
   uint32_t strict;
 } ce_nbody_params;
+
+/* N-body integration step (the NBody program of section 6.2: positions and
+ * velocities in, positions and velocities out, a time step and a squared
+ * softening). Slot 0 in: n float4 (x, y, z, m); slot 1 in: n float4
+ * (vx, vy, vz, w). With a_i the acceleration of CE_KERNEL_NBODY_ACC, each body
+ * moves by the constant-acceleration step over dt, per component in FP32 as
+ * h = (dt*dt)*0.5, x' = (x + v*dt) + a*h, v' = v + a*dt. Slot 0 out: n float4
+ * (x', y', z', m); slot 1 out: n float4 (vx', vy', vz', w). Outputs must not
+ * alias inputs (every body reads every position); time stepping swaps two
+ * pairs of buffers. eps2 and strict as for CE_KERNEL_NBODY_ACC; dt finite. */
+typedef struct {
+  uint32_t n;
+  float eps2;
+  float dt;
+  uint32_t strict;
+} ce_nbody_step_params;
 
 /* Scheduler description (section 5.3). Arrays are indexed by engine device
  * index (GPU = 0 when used, then host).
@@ -178,8 +195,9 @@ ce_status ce_program_kernel(ce_engine* e, int kernel_id, const void* params, siz
  * host workers read host_ptr (or a host copy the engine makes of dev_ptr).
  * bytes must equal the slot's size for the bound kernel. */
 ce_status ce_program_in(ce_engine* e, uint32_t slot, const void* host_ptr, const void* dev_ptr, size_t bytes);
-/* Binds output slot `slot`. After a successful run the whole output is in
- * every pointer given (host_ptr and/or dev_ptr). */
+/* Binds output slot `slot` (0, or 0 and 1 for CE_KERNEL_NBODY_STEP). After a
+ * successful run the whole output is in every pointer given (host_ptr and/or
+ * dev_ptr). Every output slot of the kernel must be bound before a run. */
 ce_status ce_program_out(ce_engine* e, uint32_t slot, void* host_ptr, void* dev_ptr, size_t bytes);
 /* Output pattern outs:items (section 4.2): each package of `items` work-items
  * writes `outs` output elements. The payloads here write one element per
@@ -198,6 +216,8 @@ ce_status ce_program_out_pattern(ce_engine* e, uint32_t outs, uint32_t items);
  *  CE_MERGE_GPU_GATHER: a few workgroups of the GPU's kernel copy each
  *    finished host tile over PCIe into HBM while the others compute (their
  *    long PCIe loads slow the workgroups that share their compute units).
+ *    Single-output kernels only: a run of a kernel with two outputs that
+ *    needs this merge fails with CE_E_UNSUPPORTED.
  * Either way the host claims new packages only while less than 512 KiB of
  * its output is still waiting to be copied. */
 #define CE_MERGE_DMA 0
@@ -344,6 +364,10 @@ const char* ce_server_error(const ce_server* s);
  * space with no dispenser, on `hip_stream` (NULL = default stream). Device
  * pointers only; ins[] follows the kernel's input slots. sync != 0 waits for
  * completion. Returns CE_E_DEVICE without a GPU. */
+/* As ce_bare_run for payloads with several outputs (outs[] follows the
+ * kernel's output slots; n_outs must match their count). */
+ce_status ce_bare_run_outs(int kernel_id, const void* params, size_t params_size, const void* const* ins,
+                           void* const* outs, uint32_t n_outs, void* hip_stream, int sync);
 ce_status ce_bare_run(int kernel_id, const void* params, size_t params_size, const void* const* ins,
                       void* out, void* hip_stream, int sync);
 

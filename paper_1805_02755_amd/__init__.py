@@ -36,6 +36,7 @@ CE_MAX_DEVICES = 2
 CE_KERNEL_ESCAPE = 1
 CE_KERNEL_BLUR5 = 2
 CE_KERNEL_NBODY_ACC = 3
+CE_KERNEL_NBODY_STEP = 4
 
 CE_SCHED_STATIC = 0
 CE_SCHED_DYNAMIC = 1
@@ -50,7 +51,7 @@ EXPORTED_SYMBOLS = (
     "ce_engine_create", "ce_engine_destroy", "ce_engine_use", "ce_engine_work_items", "ce_engine_scheduler",
     "ce_engine_stream", "ce_engine_output_merge", "ce_engine_kernel_events", "ce_program_kernel", "ce_program_in", "ce_program_out", "ce_program_out_pattern",
     "ce_engine_run", "ce_engine_stats", "ce_engine_trace", "ce_engine_has_errors", "ce_engine_error_count",
-    "ce_engine_error", "ce_engine_clear_errors", "ce_bare_run", "ce_sched_static_plan", "ce_sched_hguided_size",
+    "ce_engine_error", "ce_engine_clear_errors", "ce_bare_run", "ce_bare_run_outs", "ce_sched_static_plan", "ce_sched_hguided_size",
     "ce_gauss5_weights", "ce_version", "ce_batch_create", "ce_batch_destroy", "ce_batch_add_escape",
     "ce_batch_clear", "ce_batch_set_config", "ce_batch_get_config", "ce_batch_tune", "ce_batch_run",
     "ce_batch_run_separate", "ce_batch_stats", "ce_batch_error", "ce_server_create", "ce_server_destroy",
@@ -75,6 +76,10 @@ class ce_blur5_params(C.Structure):
 
 class ce_nbody_params(C.Structure):
     _fields_ = [("n", C.c_uint32), ("eps2", C.c_float), ("strict", C.c_uint32)]
+
+
+class ce_nbody_step_params(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("eps2", C.c_float), ("dt", C.c_float), ("strict", C.c_uint32)]
 
 
 class ce_sched_desc(C.Structure):
@@ -166,6 +171,7 @@ def load(path: str):
         "ce_engine_error": (C.c_char_p, [vp, C.c_int]),
         "ce_engine_clear_errors": (None, [vp]),
         "ce_bare_run": (i32, [C.c_int, vp, sz, C.POINTER(vp), vp, vp, C.c_int]),
+        "ce_bare_run_outs": (i32, [C.c_int, vp, sz, C.POINTER(vp), C.POINTER(vp), C.c_uint32, vp, C.c_int]),
         "ce_sched_static_plan": (i32, [u64, u32, C.POINTER(C.c_double), C.POINTER(u32), u32, C.POINTER(u64),
                                        C.POINTER(u64)]),
         "ce_sched_hguided_size": (u64, [u64, C.POINTER(u64), u32, u32, u32, u64]),
@@ -279,6 +285,16 @@ def ce_bare_run(kernel_id: int, params, ins, out, stream=None, sync: bool = True
                            _ptr(stream) if stream is not None else None, int(sync))
     if st != CE_OK:
         raise CoexecError(st, "ce_bare_run")
+
+
+def ce_bare_run_outs(kernel_id: int, params, ins, outs, stream=None, sync: bool = True) -> None:
+    """As ce_bare_run for payloads with several outputs (device pointers)."""
+    arr = (C.c_void_p * max(1, len(ins)))(*[_ptr(x) for x in ins]) if ins else None
+    oarr = (C.c_void_p * len(outs))(*[_ptr(x) for x in outs])
+    st = lib().ce_bare_run_outs(kernel_id, C.byref(params), C.sizeof(params), arr, oarr, len(outs),
+                                _ptr(stream) if stream is not None else None, int(sync))
+    if st != CE_OK:
+        raise CoexecError(st, "ce_bare_run_outs")
 
 
 def stream_handle(stream) -> Optional[int]:

@@ -235,10 +235,39 @@ __device__ __forceinline__ float rsqrt_lomont(float x) {
   return y;
 }
 
-// All-pairs acceleration (NBody program, force part): body i accumulates
-// m_j d_ij / (|d_ij|^2 + eps2)^(3/2) over j ascending in one FP32 sum per
-// component. A granule is 256 bodies, one per thread; positions of the j
-// bodies are staged through LDS 256 at a time.
+// All-pairs acceleration of body i (NBody program, force part): the sum of
+// m_j d_ij / (|d_ij|^2 + eps2)^(3/2) over j ascending, one FP32 sum per
+// component. Positions of the j bodies are staged through LDS 256 at a time;
+// every thread of the workgroup takes part in the staging.
+template <bool STRICT>
+__device__ __forceinline__ void nbody_accumulate(const float4* pos, uint32_t n, float eps2, const float4 pi,
+                                                 float4* sh, float& ax, float& ay, float& az) {
+  ax = 0.0f;
+  ay = 0.0f;
+  az = 0.0f;
+  for (uint32_t j0 = 0; j0 < n; j0 += kNbodyGranule) {
+    __syncthreads();
+    if (j0 + threadIdx.x < n) sh[threadIdx.x] = pos[j0 + threadIdx.x];
+    __syncthreads();
+    const uint32_t m = (n - j0 < kNbodyGranule) ? n - j0 : kNbodyGranule;
+#pragma unroll 8
+    for (uint32_t jj = 0; jj < m; ++jj) {
+      const float4 pj = sh[jj];
+      const float dx = pj.x - pi.x;
+      const float dy = pj.y - pi.y;
+      const float dz = pj.z - pi.z;
+      const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+      const float rinv = STRICT ? rsqrt_lomont(r2) : __builtin_amdgcn_rsqf(r2);
+      const float s = (rinv * rinv) * rinv;
+      const float f = pj.w * s;
+      ax = __builtin_fmaf(f, dx, ax);
+      ay = __builtin_fmaf(f, dy, ay);
+      az = __builtin_fmaf(f, dz, az);
+    }
+  }
+}
+
+// Accelerations: a granule is 256 bodies, one per thread.
 template <bool STRICT>
 struct NbodyTile {
   static constexpr int kMinBlocksPerCu = 1;  // one granule per workgroup: no bound
@@ -253,29 +282,49 @@ struct NbodyTile {
     const uint64_t i = (g0 + t) * kNbodyGranule + threadIdx.x;
     const bool active = i < p.n;
     const float4 pi = active ? pos[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-    const float eps2 = p.eps2;
-    float ax = 0.0f, ay = 0.0f, az = 0.0f;
-    for (uint32_t j0 = 0; j0 < p.n; j0 += kNbodyGranule) {
-      __syncthreads();
-      if (j0 + threadIdx.x < p.n) sh[threadIdx.x] = pos[j0 + threadIdx.x];
-      __syncthreads();
-      const uint32_t m = (p.n - j0 < kNbodyGranule) ? p.n - j0 : kNbodyGranule;
-#pragma unroll 8
-      for (uint32_t jj = 0; jj < m; ++jj) {
-        const float4 pj = sh[jj];
-        const float dx = pj.x - pi.x;
-        const float dy = pj.y - pi.y;
-        const float dz = pj.z - pi.z;
-        const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
-        const float rinv = STRICT ? rsqrt_lomont(r2) : __builtin_amdgcn_rsqf(r2);
-        const float s = (rinv * rinv) * rinv;
-        const float f = pj.w * s;
-        ax = __builtin_fmaf(f, dx, ax);
-        ay = __builtin_fmaf(f, dy, ay);
-        az = __builtin_fmaf(f, dz, az);
-      }
-    }
+    float ax, ay, az;
+    nbody_accumulate<STRICT>(pos, p.n, p.eps2, pi, sh, ax, ay, az);
     if (active) out[i] = make_float4(ax, ay, az, 0.0f);
+  }
+};
+
+// Integration step (NBody program: positions and velocities in and out):
+// with the acceleration above, v' = v + a dt and x' = x + v dt + a dt^2/2,
+// per component as h = (dt dt) 0.5, x' = (x + v dt) + a h, v' = v + a dt;
+// the mass and the velocity's w are copied.
+template <bool STRICT>
+struct NbodyStepTile {
+  static constexpr int kMinBlocksPerCu = 1;
+  ce_nbody_step_params p;
+  const float4* pos;
+  const float4* vel;
+  float4* pos_out;
+  float4* vel_out;
+  __device__ void load_constants() {}
+  __host__ __device__ uint64_t granules() const { return ceil_div(p.n, kNbodyGranule); }
+  __host__ __device__ uint32_t ntiles(uint64_t g0, uint64_t g1) const { return (uint32_t)(g1 - g0); }
+  __device__ void run(uint64_t g0, uint64_t, uint32_t t) const {
+    __shared__ float4 sh[kNbodyGranule];
+    const uint64_t i = (g0 + t) * kNbodyGranule + threadIdx.x;
+    const bool active = i < p.n;
+    const float4 pi = active ? pos[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float ax, ay, az;
+    nbody_accumulate<STRICT>(pos, p.n, p.eps2, pi, sh, ax, ay, az);
+    if (!active) return;
+    const float4 vi = vel[i];
+    const float dt = p.dt;
+    const float h = (dt * dt) * 0.5f;
+    float4 xo, vo;
+    xo.x = (pi.x + vi.x * dt) + ax * h;
+    xo.y = (pi.y + vi.y * dt) + ay * h;
+    xo.z = (pi.z + vi.z * dt) + az * h;
+    xo.w = pi.w;
+    vo.x = vi.x + ax * dt;
+    vo.y = vi.y + ay * dt;
+    vo.z = vi.z + az * dt;
+    vo.w = vi.w;
+    pos_out[i] = xo;
+    vel_out[i] = vo;
   }
 };
 

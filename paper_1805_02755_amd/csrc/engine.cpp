@@ -160,15 +160,16 @@ struct ce_engine {
   ce_escape_params esc{};
   ce_blur5_params blur{};
   ce_nbody_params nb{};
+  ce_nbody_step_params nbs{};
   Binding in[kMaxSlots];
-  Binding out[1];
+  Binding out[kMaxSlots];
   uint32_t pat_outs = 1, pat_items = 1;
 
   // ---- scratch
   DevBuf in_dev[kMaxSlots];
   PinnedBuf in_host[kMaxSlots];
-  DevBuf out_dev_scratch;
-  PinnedBuf out_host_scratch;   // host output when only a device output is bound
+  DevBuf out_dev_scratch[kMaxSlots];
+  PinnedBuf out_host_scratch[kMaxSlots];  // host output when only a device output is bound
   PinnedBuf ring_buf;           // host completion ring read by the GPU's gatherers
   int merge_mode = CE_MERGE_DMA;  // CE_MERGE_GPU_GATHER where the GPU has no copy engine
   bool gather = false;          // this run's host tiles are copied into HBM by the GPU
@@ -201,7 +202,8 @@ struct ce_engine {
   int64_t t0_ns = 0;
   const void* host_in0 = nullptr;
   const void* host_in1 = nullptr;
-  void* host_out = nullptr;
+  void* host_out = nullptr;    // output slot 0 as the host workers write it
+  void* host_out1 = nullptr;   // output slot 1 (n-body step velocities)
   std::atomic<int> host_error{0};
 
   // ---- results
@@ -243,29 +245,34 @@ struct ce_engine {
       case CE_KERNEL_ESCAPE: return esc.h;
       case CE_KERNEL_BLUR5: return blur.h;
       case CE_KERNEL_NBODY_ACC: return ceil_div(nb.n, kNbodyGranule);
+      case CE_KERNEL_NBODY_STEP: return ceil_div(nbs.n, kNbodyGranule);
     }
     return 0;
   }
+  uint32_t n_bodies() const { return kernel_id == CE_KERNEL_NBODY_STEP ? nbs.n : nb.n; }
+  bool is_nbody() const { return kernel_id == CE_KERNEL_NBODY_ACC || kernel_id == CE_KERNEL_NBODY_STEP; }
   uint64_t items_in(uint64_t g0, uint64_t g1) const {
     switch (kernel_id) {
       case CE_KERNEL_ESCAPE: return (g1 - g0) * esc.w;
       case CE_KERNEL_BLUR5: return (g1 - g0) * blur.w;
-      case CE_KERNEL_NBODY_ACC: {
-        const uint64_t a = g0 * kNbodyGranule, b = std::min<uint64_t>(g1 * kNbodyGranule, nb.n);
+      case CE_KERNEL_NBODY_ACC:
+      case CE_KERNEL_NBODY_STEP: {
+        const uint64_t a = g0 * kNbodyGranule, b = std::min<uint64_t>(g1 * kNbodyGranule, n_bodies());
         return b > a ? b - a : 0;
       }
     }
     return 0;
   }
-  size_t out_elem_bytes() const { return kernel_id == CE_KERNEL_NBODY_ACC ? 16 : 4; }
+  size_t out_elem_bytes() const { return is_nbody() ? 16 : 4; }
   uint64_t item_offset(uint64_t g) const {
-    return kernel_id == CE_KERNEL_NBODY_ACC ? std::min<uint64_t>(g * kNbodyGranule, nb.n) : g * gws[0];
+    return is_nbody() ? std::min<uint64_t>(g * kNbodyGranule, n_bodies()) : g * gws[0];
   }
   size_t in_bytes(int slot) const {
     switch (kernel_id) {
       case CE_KERNEL_BLUR5:
         return slot == 0 ? (size_t)blur.w * blur.h * 4 : (slot == 1 ? 25 * 4 : 0);
       case CE_KERNEL_NBODY_ACC: return slot == 0 ? (size_t)nb.n * 16 : 0;
+      case CE_KERNEL_NBODY_STEP: return slot < 2 ? (size_t)nbs.n * 16 : 0;
     }
     return 0;
   }
@@ -273,19 +280,22 @@ struct ce_engine {
     switch (kernel_id) {
       case CE_KERNEL_BLUR5: return 2;
       case CE_KERNEL_NBODY_ACC: return 1;
+      case CE_KERNEL_NBODY_STEP: return 2;
     }
     return 0;
   }
+  int n_out_slots() const { return kernel_id == CE_KERNEL_NBODY_STEP ? 2 : 1; }
   size_t out_bytes() const {
     switch (kernel_id) {
       case CE_KERNEL_ESCAPE: return (size_t)esc.w * esc.h * 4;
       case CE_KERNEL_BLUR5: return (size_t)blur.w * blur.h * 4;
       case CE_KERNEL_NBODY_ACC: return (size_t)nb.n * 16;
+      case CE_KERNEL_NBODY_STEP: return (size_t)nbs.n * 16;
     }
     return 0;
   }
   uint32_t host_tiles(uint64_t g0, uint64_t g1) const {
-    if (kernel_id == CE_KERNEL_NBODY_ACC) return (uint32_t)ceil_div(items_in(g0, g1), kHostNbodyTile);
+    if (is_nbody()) return (uint32_t)ceil_div(items_in(g0, g1), kHostNbodyTile);
     return (uint32_t)(g1 - g0);
   }
 
@@ -418,14 +428,25 @@ struct ce_engine {
         hp->nbody_bodies((const float*)host_in0, nb.n, nb.eps2, (int)nb.strict, i0, i1, (float*)host_out);
         break;
       }
+      case CE_KERNEL_NBODY_STEP: {
+        const uint64_t i0 = p.g0 * kNbodyGranule + (uint64_t)ti * kHostNbodyTile;
+        const uint64_t end = std::min<uint64_t>(p.g1 * kNbodyGranule, nbs.n);
+        const uint64_t i1 = std::min<uint64_t>(i0 + kHostNbodyTile, end);
+        // the accelerations land in the velocity output first, then the step
+        // turns them into the new velocities
+        hp->nbody_bodies((const float*)host_in0, nbs.n, nbs.eps2, (int)nbs.strict, i0, i1, (float*)host_out1);
+        nbody_step_update((const float*)host_in0, (const float*)host_in1, nbs.dt, i0, i1, (float*)host_out,
+                          (float*)host_out1);
+        break;
+      }
     }
   }
 
   // Byte range of the output written by host tile ti of package p.
   void host_tile_bytes(const HostPkg& p, uint32_t ti, uint64_t* off, uint64_t* len) const {
-    if (kernel_id == CE_KERNEL_NBODY_ACC) {
+    if (is_nbody()) {
       const uint64_t i0 = p.g0 * kNbodyGranule + (uint64_t)ti * kHostNbodyTile;
-      const uint64_t end = std::min<uint64_t>(p.g1 * kNbodyGranule, nb.n);
+      const uint64_t end = std::min<uint64_t>(p.g1 * kNbodyGranule, n_bodies());
       const uint64_t i1 = std::min<uint64_t>(i0 + kHostNbodyTile, end);
       *off = i0 * 16;
       *len = (i1 - i0) * 16;
@@ -460,14 +481,17 @@ struct ce_engine {
     out_range(p.g0, p.g1, &off, &len);
     if (!len) return;
     std::lock_guard<std::mutex> lk(push_mu);
-    const int h = sdma.start((char*)out[0].dev_out + off, (const char*)host_out + off, len);
-    if (h < 0) {
-      push_error.store(1);
-      return;
+    void* const src[2] = {host_out, host_out1};
+    for (int s = 0; s < n_out_slots(); ++s) {
+      const int h = sdma.start((char*)out[s].dev_out + off, (const char*)src[s] + off, len);
+      if (h < 0) {
+        push_error.store(1);
+        return;
+      }
+      push_pending.emplace_back(h, (uint64_t)len);
+      push_inflight += len;
+      push_total += len;
     }
-    push_pending.emplace_back(h, (uint64_t)len);
-    push_inflight += len;
-    push_total += len;
   }
   // Retires finished copies and blocks until the bytes in flight fit the
   // backlog (the host is worth only as much output as PCIe carries). Only
@@ -690,8 +714,8 @@ struct ce_engine {
     if (n_devices() == 0) return fail(CE_E_STATE, "run: empty device set");
     if (use_host() && !hp) return fail(CE_E_UNSUPPORTED, "run: host CPU lacks AVX2/FMA");
     // index space must match the kernel
-    if (kernel_id == CE_KERNEL_NBODY_ACC) {
-      if (ndim != 1 || gws[0] != nb.n || lws0 != kNbodyGranule)
+    if (is_nbody()) {
+      if (ndim != 1 || gws[0] != n_bodies() || lws0 != kNbodyGranule)
         return fail(CE_E_INVALID, "run: n-body needs a 1-D space of n items with lws 256");
     } else {
       const uint64_t w = kernel_id == CE_KERNEL_ESCAPE ? esc.w : blur.w;
@@ -700,7 +724,12 @@ struct ce_engine {
     }
     for (int s = 0; s < n_in_slots(); ++s)
       if (!in[s].bound) return fail(CE_E_STATE, "run: input slot %d not bound", s);
-    if (!out[0].bound) return fail(CE_E_STATE, "run: output slot 0 not bound");
+    for (int s = 0; s < n_out_slots(); ++s)
+      if (!out[s].bound) return fail(CE_E_STATE, "run: output slot %d not bound", s);
+    for (int s = 1; s < n_out_slots(); ++s)
+      if ((out[s].host_out == nullptr) != (out[0].host_out == nullptr) ||
+          (out[s].dev_out == nullptr) != (out[0].dev_out == nullptr))
+        return fail(CE_E_UNSUPPORTED, "run: output slots must be bound alike (host, device or both)");
 
     const uint64_t G = granules();
     ++run_id;
@@ -711,10 +740,11 @@ struct ce_engine {
     // GPU-side pointers
     kargs = KernelArgs{};
     kargs.kernel_id = kernel_id;
-    kargs.strict = nb.strict;
+    kargs.strict = kernel_id == CE_KERNEL_NBODY_STEP ? nbs.strict : nb.strict;
     kargs.esc = esc;
     kargs.blur = blur;
     kargs.nb = nb;
+    kargs.nbs = nbs;
     const void* gin[kMaxSlots] = {nullptr, nullptr};
     if (use_gpu()) {
       for (int s = 0; s < n_in_slots(); ++s) {
@@ -730,16 +760,20 @@ struct ce_engine {
     }
     kargs.in0 = gin[0];
     kargs.in1 = gin[1];
-    void* gpu_out = out[0].dev_out;
-    if (use_gpu() && !gpu_out) {
-      if (!out_dev_scratch.ensure(out[0].bytes)) return fail(CE_E_NOMEM, "run: device output scratch");
-      gpu_out = out_dev_scratch.p;
+    void* gpu_out[kMaxSlots] = {nullptr, nullptr};
+    for (int s = 0; s < n_out_slots(); ++s) {
+      gpu_out[s] = out[s].dev_out;
+      if (use_gpu() && !gpu_out[s]) {
+        if (!out_dev_scratch[s].ensure(out[s].bytes)) return fail(CE_E_NOMEM, "run: device output scratch");
+        gpu_out[s] = out_dev_scratch[s].p;
+      }
     }
-    kargs.out = gpu_out;
+    kargs.out = gpu_out[0];
+    kargs.out1 = gpu_out[1];
 
     // host-side pointers
     host_in0 = host_in1 = nullptr;
-    host_out = nullptr;
+    host_out = host_out1 = nullptr;
     if (use_host()) {
       const void* hin[kMaxSlots] = {nullptr, nullptr};
       for (int s = 0; s < n_in_slots(); ++s) {
@@ -754,13 +788,18 @@ struct ce_engine {
       }
       host_in0 = hin[0];
       host_in1 = hin[1];
-      host_out = out[0].host_out;
-      if (!host_out) {
-        // host-coherent so the GPU's gatherers can read it over PCIe
-        out_host_scratch.flags = hipHostMallocCoherent | hipHostMallocMapped;
-        if (!out_host_scratch.ensure(out[0].bytes)) return fail(CE_E_NOMEM, "run: host output scratch");
-        host_out = out_host_scratch.p;
+      void* hout[kMaxSlots] = {nullptr, nullptr};
+      for (int s = 0; s < n_out_slots(); ++s) {
+        hout[s] = out[s].host_out;
+        if (!hout[s]) {
+          // host-coherent so the GPU's gatherers can read it over PCIe
+          out_host_scratch[s].flags = hipHostMallocCoherent | hipHostMallocMapped;
+          if (!out_host_scratch[s].ensure(out[s].bytes)) return fail(CE_E_NOMEM, "run: host output scratch");
+          hout[s] = out_host_scratch[s].p;
+        }
       }
+      host_out = hout[0];
+      host_out1 = hout[1];
       bool downloaded = false;
       for (int s = 0; s < n_in_slots(); ++s) downloaded |= (in[s].host == nullptr);
       if (downloaded) {
@@ -770,6 +809,8 @@ struct ce_engine {
 
     // the GPU copies the host's tiles into HBM when the output lives only there
     const bool merge_dev = use_gpu() && use_host() && out[0].dev_out && !out[0].host_out;
+    if (merge_dev && merge_mode == CE_MERGE_GPU_GATHER && n_out_slots() > 1)
+      return fail(CE_E_UNSUPPORTED, "run: the gather merge handles one output slot; use CE_MERGE_DMA");
     gather = merge_dev && merge_mode == CE_MERGE_GPU_GATHER;
     push = merge_dev && merge_mode == CE_MERGE_DMA;
     push_total = 0;
@@ -827,7 +868,7 @@ struct ce_engine {
       gs.wait_ticks = (uint64_t)wallclock_hz * 60;
       if (gather) {
         const uint64_t max_host_tiles =
-            kernel_id == CE_KERNEL_NBODY_ACC ? ceil_div(nb.n, kHostNbodyTile) : G;
+            is_nbody() ? ceil_div(n_bodies(), kHostNbodyTile) : G;
         const size_t cap = (size_t)max_host_tiles + gather_wgs + 1;
         ring_buf.flags = hipHostMallocCoherent | hipHostMallocMapped;
         if (!ring_buf.ensure(cap * sizeof(uint64_t), true)) return fail(CE_E_NOMEM, "run: completion ring");
@@ -942,7 +983,7 @@ struct ce_engine {
     return m;
   }
 
-  ce_status merge_outputs(void* gpu_out) {
+  ce_status merge_outputs(void* const* gpu_out) {
     hipError_t he;
     const size_t eb = out_elem_bytes();
     const uint64_t G = granules();
@@ -953,25 +994,28 @@ struct ce_engine {
     const auto hiv = use_host() ? host_intervals() : std::vector<std::pair<uint64_t, uint64_t>>{};
     bool issued = false;
     // host-computed ranges into the device output (unless the GPU gathered them)
+    void* const hsrc[kMaxSlots] = {host_out, host_out1};
     if (use_host() && out[0].dev_out && !gather && !push) {
-      for (auto& iv : hiv) {
-        size_t off, len;
-        bytes_of(iv.first, iv.second, &off, &len);
-        if (!len) continue;
-        if ((he = hipMemcpyAsync((char*)out[0].dev_out + off, (const char*)host_out + off, len,
-                                 hipMemcpyHostToDevice, stream)) != hipSuccess)
-          return hip_fail(he, "merge: host ranges to device");
-        issued = true;
+      for (int s = 0; s < n_out_slots(); ++s) {
+        for (auto& iv : hiv) {
+          size_t off, len;
+          bytes_of(iv.first, iv.second, &off, &len);
+          if (!len) continue;
+          if ((he = hipMemcpyAsync((char*)out[s].dev_out + off, (const char*)hsrc[s] + off, len,
+                                   hipMemcpyHostToDevice, stream)) != hipSuccess)
+            return hip_fail(he, "merge: host ranges to device");
+          issued = true;
+        }
       }
     }
     // GPU-computed ranges (the complement of the host's) into the host output
-    if (use_gpu() && out[0].host_out) {
+    for (int slot = 0; slot < n_out_slots() && use_gpu() && out[slot].host_out; ++slot) {
       uint64_t cur = 0;
       auto copy = [&](uint64_t a, uint64_t b) -> ce_status {
         size_t off, len;
         bytes_of(a, b, &off, &len);
         if (!len) return CE_OK;
-        hipError_t e2 = hipMemcpyAsync((char*)out[0].host_out + off, (const char*)gpu_out + off, len,
+        hipError_t e2 = hipMemcpyAsync((char*)out[slot].host_out + off, (const char*)gpu_out[slot] + off, len,
                                        hipMemcpyDeviceToHost, stream);
         if (e2 != hipSuccess) return hip_fail(e2, "merge: device ranges to host");
         issued = true;
@@ -1267,11 +1311,22 @@ ce_status ce_program_kernel(ce_engine* e, int kernel_id, const void* params, siz
       e->nb = p;
       break;
     }
+    case CE_KERNEL_NBODY_STEP: {
+      if (params_size != sizeof(ce_nbody_step_params)) return e->fail(CE_E_INVALID, "kernel: n-body step params size");
+      ce_nbody_step_params p;
+      memcpy(&p, params, sizeof p);
+      if (p.n == 0) return e->fail(CE_E_INVALID, "kernel: no bodies");
+      if (!(p.eps2 >= 1.17549435e-38f) || !std::isfinite(p.eps2))
+        return e->fail(CE_E_INVALID, "kernel: eps2 must be a positive normal float");
+      if (!std::isfinite(p.dt)) return e->fail(CE_E_INVALID, "kernel: dt must be finite");
+      e->nbs = p;
+      break;
+    }
     default: return e->fail(CE_E_INVALID, "kernel: unknown kernel id %d", kernel_id);
   }
   e->kernel_id = kernel_id;
   for (auto& b : e->in) b = Binding{};
-  e->out[0] = Binding{};
+  for (auto& b : e->out) b = Binding{};
   return CE_OK;
 }
 
@@ -1289,10 +1344,10 @@ ce_status ce_program_in(ce_engine* e, uint32_t slot, const void* host_ptr, const
 ce_status ce_program_out(ce_engine* e, uint32_t slot, void* host_ptr, void* dev_ptr, size_t bytes) {
   if (!e) return CE_E_INVALID;
   if (e->kernel_id == 0) return e->fail(CE_E_STATE, "out: bind a kernel first");
-  if (slot != 0) return e->fail(CE_E_INVALID, "out: kernel has one output slot");
+  if ((int)slot >= e->n_out_slots()) return e->fail(CE_E_INVALID, "out: kernel has no output slot %u", slot);
   if (!host_ptr && !dev_ptr) return e->fail(CE_E_INVALID, "out: needs a host or device pointer");
   if (bytes != e->out_bytes()) return e->fail(CE_E_INVALID, "out: expects %zu bytes, got %zu", e->out_bytes(), bytes);
-  e->out[0] = Binding{nullptr, nullptr, host_ptr, dev_ptr, bytes, true};
+  e->out[slot] = Binding{nullptr, nullptr, host_ptr, dev_ptr, bytes, true};
   return CE_OK;
 }
 
@@ -1350,7 +1405,15 @@ void ce_engine_clear_errors(ce_engine* e) {
 
 ce_status ce_bare_run(int kernel_id, const void* params, size_t params_size, const void* const* ins, void* out,
                       void* hip_stream, int sync) {
-  if (!params || !out) return CE_E_INVALID;
+  void* const outs[1] = {out};
+  return ce_bare_run_outs(kernel_id, params, params_size, ins, outs, 1, hip_stream, sync);
+}
+
+ce_status ce_bare_run_outs(int kernel_id, const void* params, size_t params_size, const void* const* ins,
+                           void* const* outs, uint32_t n_outs, void* hip_stream, int sync) {
+  if (!params || !outs || !outs[0]) return CE_E_INVALID;
+  if (n_outs != (kernel_id == CE_KERNEL_NBODY_STEP ? 2u : 1u)) return CE_E_INVALID;
+  void* const out = outs[0];
   KernelArgs a{};
   a.kernel_id = kernel_id;
   switch (kernel_id) {
@@ -1372,6 +1435,15 @@ ce_status ce_bare_run(int kernel_id, const void* params, size_t params_size, con
       if (a.nb.n == 0 || !(a.nb.eps2 >= 1.17549435e-38f)) return CE_E_INVALID;
       a.strict = a.nb.strict;
       a.in0 = ins[0];
+      break;
+    case CE_KERNEL_NBODY_STEP:
+      if (params_size != sizeof(ce_nbody_step_params) || !ins || !ins[0] || !ins[1] || !outs[1]) return CE_E_INVALID;
+      memcpy(&a.nbs, params, sizeof a.nbs);
+      if (a.nbs.n == 0 || !(a.nbs.eps2 >= 1.17549435e-38f) || !std::isfinite(a.nbs.dt)) return CE_E_INVALID;
+      a.strict = a.nbs.strict;
+      a.in0 = ins[0];
+      a.in1 = ins[1];
+      a.out1 = outs[1];
       break;
     default: return CE_E_INVALID;
   }

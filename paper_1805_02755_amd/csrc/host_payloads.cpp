@@ -228,6 +228,24 @@ const HostPayloadFns k512 = {escape_rows_512, blur5_rows_512, nbody_bodies_512, 
 
 }  // namespace
 
+void nbody_step_update(const float* pos4, const float* vel4, float dt, uint64_t i0, uint64_t i1, float* pos_out4,
+                       float* vel_out4) {
+  const float h = (dt * dt) * 0.5f;
+  for (uint64_t i = i0; i < i1; ++i) {
+    const float* x = pos4 + 4 * i;
+    const float* v = vel4 + 4 * i;
+    float* xo = pos_out4 + 4 * i;
+    float* vo = vel_out4 + 4 * i;
+    const float a[3] = {vo[0], vo[1], vo[2]};
+    for (int c = 0; c < 3; ++c) {
+      xo[c] = (x[c] + v[c] * dt) + a[c] * h;
+      vo[c] = v[c] + a[c] * dt;
+    }
+    xo[3] = x[3];
+    vo[3] = v[3];
+  }
+}
+
 const HostPayloadFns* host_payloads() {
   __builtin_cpu_init();
   if (__builtin_cpu_supports("avx512f") && __builtin_cpu_supports("avx512dq") &&

@@ -25,4 +25,12 @@ struct HostPayloadFns {
 // AVX2+FMA); returns nullptr if the CPU lacks FMA.
 const HostPayloadFns* host_payloads();
 
+// N-body integration step of bodies [i0, i1), after the accelerations: on
+// entry vel_out4 holds them (as nbody_bodies writes them); on return
+// pos_out4 and vel_out4 hold the stepped positions and velocities, with the
+// same FP32 operations as the GPU: h = (dt*dt)*0.5, x' = (x + v*dt) + a*h,
+// v' = v + a*dt, mass and velocity w copied.
+void nbody_step_update(const float* pos4, const float* vel4, float dt, uint64_t i0, uint64_t i1, float* pos_out4,
+                       float* vel_out4);
+
 }  // namespace ce

@@ -573,6 +573,10 @@ template <bool S>
 NbodyTile<S> make_nbody(const KernelArgs& a) {
   return NbodyTile<S>{a.nb, (const float4*)a.in0, (float4*)a.out};
 }
+template <bool S>
+NbodyStepTile<S> make_nbody_step(const KernelArgs& a) {
+  return NbodyStepTile<S>{a.nbs, (const float4*)a.in0, (const float4*)a.in1, (float4*)a.out, (float4*)a.out1};
+}
 }  // namespace
 
 uint64_t gpu_granules(const KernelArgs& a) {
@@ -580,6 +584,7 @@ uint64_t gpu_granules(const KernelArgs& a) {
     case CE_KERNEL_ESCAPE: return make_escape(a).granules();
     case CE_KERNEL_BLUR5: return make_blur(a).granules();
     case CE_KERNEL_NBODY_ACC: return make_nbody<true>(a).granules();
+    case CE_KERNEL_NBODY_STEP: return make_nbody_step<true>(a).granules();
   }
   return 0;
 }
@@ -589,6 +594,7 @@ uint32_t gpu_tiles(const KernelArgs& a, uint64_t g0, uint64_t g1) {
     case CE_KERNEL_ESCAPE: return make_escape(a).ntiles(g0, g1);
     case CE_KERNEL_BLUR5: return make_blur(a).ntiles(g0, g1);
     case CE_KERNEL_NBODY_ACC: return make_nbody<true>(a).ntiles(g0, g1);
+    case CE_KERNEL_NBODY_STEP: return make_nbody_step<true>(a).ntiles(g0, g1);
   }
   return 0;
 }
@@ -604,6 +610,11 @@ hipError_t persistent_blocks_per_cu(const KernelArgs& a, int* blocks) {
                                                                      kBlockThreads, 0)
                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_persistent<NbodyTile<false>>,
                                                                      kBlockThreads, 0);
+    case CE_KERNEL_NBODY_STEP:
+      return a.strict ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_persistent<NbodyStepTile<true>>,
+                                                                     kBlockThreads, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_persistent<NbodyStepTile<false>>,
+                                                                     kBlockThreads, 0);
   }
   return hipErrorInvalidValue;
 }
@@ -618,6 +629,12 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t g
         hipLaunchKernelGGL(k_persistent<NbodyTile<true>>, g, b, 0, st, make_nbody<true>(a), s);
       else
         hipLaunchKernelGGL(k_persistent<NbodyTile<false>>, g, b, 0, st, make_nbody<false>(a), s);
+      break;
+    case CE_KERNEL_NBODY_STEP:
+      if (a.strict)
+        hipLaunchKernelGGL(k_persistent<NbodyStepTile<true>>, g, b, 0, st, make_nbody_step<true>(a), s);
+      else
+        hipLaunchKernelGGL(k_persistent<NbodyStepTile<false>>, g, b, 0, st, make_nbody_step<false>(a), s);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -637,6 +654,12 @@ hipError_t launch_bare(const KernelArgs& a, hipStream_t st) {
         hipLaunchKernelGGL(k_bare<NbodyTile<true>>, g, b, 0, st, make_nbody<true>(a), G);
       else
         hipLaunchKernelGGL(k_bare<NbodyTile<false>>, g, b, 0, st, make_nbody<false>(a), G);
+      break;
+    case CE_KERNEL_NBODY_STEP:
+      if (a.strict)
+        hipLaunchKernelGGL(k_bare<NbodyStepTile<true>>, g, b, 0, st, make_nbody_step<true>(a), G);
+      else
+        hipLaunchKernelGGL(k_bare<NbodyStepTile<false>>, g, b, 0, st, make_nbody_step<false>(a), G);
       break;
     default: return hipErrorInvalidValue;
   }

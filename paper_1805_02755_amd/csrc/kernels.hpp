@@ -16,9 +16,11 @@ struct KernelArgs {
   ce_escape_params esc;
   ce_blur5_params blur;
   ce_nbody_params nb;
+  ce_nbody_step_params nbs;
   const void* in0;          // device pointers
   const void* in1;
   void* out;
+  void* out1;               // second output (n-body step: velocities)
 };
 
 // Granules of the index space and tiles of a package, as the GPU cuts them.

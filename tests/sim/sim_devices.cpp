@@ -111,7 +111,15 @@ namespace ce {
 
 // ------------------------------------------------ coverage-marking payloads
 namespace {
-size_t item_words(int kernel_id) { return kernel_id == CE_KERNEL_NBODY_ACC ? 4 : 1; }
+size_t item_words(int kernel_id) {
+  return (kernel_id == CE_KERNEL_NBODY_ACC || kernel_id == CE_KERNEL_NBODY_STEP) ? 4 : 1;
+}
+uint32_t bodies_of(const KernelArgs& a) { return a.kernel_id == CE_KERNEL_NBODY_STEP ? a.nbs.n : a.nb.n; }
+// the second output of the step payload gets the same item indices, uncounted
+void mark_second(uint32_t* out1, uint64_t i0, uint64_t i1) {
+  if (!out1) return;
+  for (uint64_t i = i0; i < i1; ++i) out1[i * 4] = (uint32_t)i;
+}
 void mark(uint32_t* out, uint64_t i0, uint64_t i1, size_t words) {
   for (uint64_t i = i0; i < i1; ++i) {
     out[i * words] = (uint32_t)i;
@@ -139,23 +147,31 @@ const HostPayloadFns kSim = {h_escape, h_blur, h_nbody, "sim"};
 uint64_t items_of(const KernelArgs& a, uint64_t g0, uint64_t g1) {
   if (a.kernel_id == CE_KERNEL_ESCAPE) return (g1 - g0) * a.esc.w;
   if (a.kernel_id == CE_KERNEL_BLUR5) return (g1 - g0) * a.blur.w;
-  const uint64_t lo = g0 * 256, hi = std::min<uint64_t>(g1 * 256, a.nb.n);
+  const uint64_t lo = g0 * 256, hi = std::min<uint64_t>(g1 * 256, bodies_of(a));
   return hi > lo ? hi - lo : 0;
 }
 uint64_t first_item(const KernelArgs& a, uint64_t g) {
   if (a.kernel_id == CE_KERNEL_ESCAPE) return g * a.esc.w;
   if (a.kernel_id == CE_KERNEL_BLUR5) return g * a.blur.w;
-  return std::min<uint64_t>(g * 256, a.nb.n);
+  return std::min<uint64_t>(g * 256, bodies_of(a));
 }
 }  // namespace
 
 const HostPayloadFns* host_payloads() { return &kSim; }
 
+// The step's update after the (coverage-counting) force payload: the
+// position output gets the same item indices.
+void nbody_step_update(const float*, const float*, float, uint64_t i0, uint64_t i1, float* pos_out4, float* vel_out4) {
+  uint32_t* po = (uint32_t*)pos_out4;
+  const uint32_t* vo = (const uint32_t*)vel_out4;
+  for (uint64_t i = i0; i < i1; ++i) po[i * 4] = vo[i * 4];
+}
+
 // ------------------------------------------------------ fake GPU kernels
 uint64_t gpu_granules(const KernelArgs& a) {
   if (a.kernel_id == CE_KERNEL_ESCAPE) return a.esc.h;
   if (a.kernel_id == CE_KERNEL_BLUR5) return a.blur.h;
-  return (a.nb.n + 255) / 256;
+  return (bodies_of(a) + 255) / 256;
 }
 uint32_t gpu_tiles(const KernelArgs& a, uint64_t g0, uint64_t g1) {
   if (a.kernel_id == CE_KERNEL_ESCAPE) return (uint32_t)(ceil_div(g1 - g0, kEscapeTileRows) * ceil_div(a.esc.w, kEscapeTileCols));
@@ -220,6 +236,7 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, 
       const uint64_t n = items_of(a, g0, g1);
       const int64_t until = now_ns() + (int64_t)(g_gpu_ns_per_item * (double)n);
       mark((uint32_t*)a.out, first_item(a, g0), first_item(a, g0) + n, item_words(a.kernel_id));
+      mark_second((uint32_t*)a.out1, first_item(a, g0), first_item(a, g0) + n);
       spin_until(until);
       PkgSlot& ps = s.pkgs[np];
       ps.g0 = g0;
@@ -267,6 +284,7 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, 
 hipError_t launch_bare(const KernelArgs& a, hipStream_t) {
   const uint64_t G = gpu_granules(a);
   mark((uint32_t*)a.out, 0, items_of(a, 0, G), item_words(a.kernel_id));
+  mark_second((uint32_t*)a.out1, 0, items_of(a, 0, G));
   return hipSuccess;
 }
 

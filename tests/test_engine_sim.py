@@ -253,3 +253,91 @@ def test_empty_index_spaces_are_refused(simlib):
             eng.program_kernel(kid, prm)
         assert ei.value.status == ce.CE_E_INVALID
     eng.close()
+
+
+def _run_step(L, n, devs, sched, residency, merge=ce.CE_MERGE_DMA, host_threads=4, rates=(20.0, 20.0, 1000.0)):
+    """The two-output n-body step: both outputs hold every body's index."""
+    L.sim_set_rates(*rates)
+    eng = ce.Engine(L)
+    eng.output_merge(merge)
+    eng.use(devs, 0, host_threads)
+    eng.work_items([n], [256])
+    eng.program_kernel(ce.CE_KERNEL_NBODY_STEP, ce.ce_nbody_step_params(n, 1e-6, 0.01, 1))
+    pos = np.zeros((n, 4), np.float32)
+    vel = np.zeros((n, 4), np.float32)
+    eng.program_in(0, host=pos, dev=pos)
+    eng.program_in(1, host=vel, dev=vel)
+    outs = [np.zeros((n, 4), np.uint32), np.zeros((n, 4), np.uint32)]
+    mirrors = [np.zeros((n, 4), np.uint32), np.zeros((n, 4), np.uint32)]
+    for s in range(2):
+        if residency == "dev":
+            eng.program_out(s, dev=outs[s])
+        elif residency == "host":
+            eng.program_out(s, host=outs[s])
+        else:
+            eng.program_out(s, host=outs[s], dev=mirrors[s])
+    eng.scheduler(**sched)
+    L.sim_reset(n)
+    eng.run()
+    st = eng.stats()
+    eng.close()
+    cnt = _coverage(L, n)
+    for s in range(2):
+        assert np.array_equal(outs[s][:, 0], np.arange(n, dtype=np.uint32)), (s, residency)
+        if residency == "both":
+            assert np.array_equal(mirrors[s][:, 0], np.arange(n, dtype=np.uint32)), (s, residency)
+    return cnt, st
+
+
+@pytest.mark.parametrize("residency", ["dev", "host", "both"])
+@pytest.mark.parametrize("sched", ["hguided", "dynamic", "static"])
+@pytest.mark.parametrize("devs", [ce.CE_DEV_GPU, ce.CE_DEV_HOST, BOTH])
+def test_nbody_step_two_outputs_every_body_once(simlib, residency, sched, devs):
+    s = SCHEDS[sched] if devs == BOTH else _one_dev(SCHEDS[sched])
+    cnt, st = _run_step(simlib, 3000, devs, s, residency)
+    assert np.all(cnt == 1)
+    if devs == BOTH and residency == "dev" and st.packages[1]:
+        assert st.gathered_bytes > 0  # both outputs' host ranges were copied
+
+
+def test_nbody_step_refusals(simlib):
+    L = simlib
+    eng = ce.Engine(L)
+    n = 600
+    eng.use(BOTH, 0, 2)
+    eng.work_items([n], [256])
+    # a one-output kernel has no slot 1
+    eng.program_kernel(ce.CE_KERNEL_NBODY_ACC, ce.ce_nbody_params(n, 1e-6, 1))
+    with pytest.raises(ce.CoexecError) as ei:
+        eng.program_out(1, host=np.zeros((n, 4), np.float32))
+    assert ei.value.status == ce.CE_E_INVALID
+    # dt must be finite
+    with pytest.raises(ce.CoexecError) as ei:
+        eng.program_kernel(ce.CE_KERNEL_NBODY_STEP, ce.ce_nbody_step_params(n, 1e-6, float("inf"), 1))
+    assert ei.value.status == ce.CE_E_INVALID
+    eng.program_kernel(ce.CE_KERNEL_NBODY_STEP, ce.ce_nbody_step_params(n, 1e-6, 0.01, 1))
+    pos = np.zeros((n, 4), np.float32)
+    eng.program_in(0, host=pos, dev=pos)
+    eng.program_in(1, host=pos, dev=pos)
+    a, b = np.zeros((n, 4), np.float32), np.zeros((n, 4), np.float32)
+    eng.program_out(0, dev=a)
+    # the second output unbound
+    with pytest.raises(ce.CoexecError) as ei:
+        eng.scheduler(ce.CE_SCHED_DYNAMIC, package_granules=1)
+        eng.run()
+    assert ei.value.status == ce.CE_E_STATE
+    # outputs bound differently
+    eng.program_out(1, host=b)
+    with pytest.raises(ce.CoexecError) as ei:
+        eng.run()
+    assert ei.value.status == ce.CE_E_UNSUPPORTED
+    # the gather merge takes one output slot
+    eng.program_out(1, dev=b)
+    eng.output_merge(ce.CE_MERGE_GPU_GATHER)
+    with pytest.raises(ce.CoexecError) as ei:
+        eng.run()
+    assert ei.value.status == ce.CE_E_UNSUPPORTED
+    eng.output_merge(ce.CE_MERGE_DMA)
+    L.sim_reset(n)
+    eng.run()
+    eng.close()
