@@ -70,7 +70,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["blur", "escape", "nbody", "batch", "serve", "copy"], default="blur")
+    ap.add_argument("--workload", choices=["blur", "escape", "nbody", "nbody-step", "batch", "serve", "copy"],
+                    default="blur")
     ap.add_argument("--serve-jobs", type=int, default=2000)
     ap.add_argument("--trace-out", default=None, help="write the last co-executed run's package trace (JSON) here")
     ap.add_argument("--mode", choices=["device", "host"], default="device",
@@ -156,6 +157,8 @@ def main():
         return bench_serve(args, ce, synth, torch, np, stream)
     if args.workload == "copy":
         return bench_copy(args, torch, stream)
+    if args.workload == "nbody-step":
+        return bench_nbody_step(args, ce, synth, torch, np, stream)
 
     eng = ce.Engine()
     eng.stream(stream.cuda_stream)
@@ -427,6 +430,131 @@ def main():
             "t_gather_ms": med([s.t_gather for s in stats]) * 1e3,
             "gathered_MiB": med([s.gathered_bytes for s in stats]) / 2**20,
             "trace_packages": len(trace),
+        },
+    }
+    print(json.dumps(res), flush=True)
+    eng.close()
+
+
+def bench_nbody_step(args, ce, synth, torch, np, stream):
+    """Time stepping of 65,536 bodies (positions and velocities in HBM,
+    alternating between two pairs of buffers), one co-executed integration
+    step per bench step: Dynamic 256-body packages, GPU + every host core.
+    With device-only buffers the engine downloads the two inputs for the
+    host workers at the start of each step and copies the host's rows of
+    both outputs into HBM."""
+    K, W = args.steps, args.warmup
+    n, eps2, dt = 65536, 1e-6, 1e-3
+    dev = torch.device("cuda:0")
+    pos, vel = synth.nbody_bodies(n), synth.nbody_velocities(n)
+    bufs = [[torch.from_numpy(pos).to(dev), torch.from_numpy(vel).to(dev)],
+            [torch.empty((n, 4), device=dev), torch.empty((n, 4), device=dev)]]
+    sync = torch.cuda.synchronize
+    sync()
+    params = ce.ce_nbody_step_params(n, eps2, dt, 1)
+    kid = ce.CE_KERNEL_NBODY_STEP
+    nbytes = n * 16
+
+    def bind(eng, k):
+        a, b = k % 2, 1 - k % 2
+        for s_ in range(2):
+            eng.program_in(s_, dev=bufs[a][s_], nbytes=nbytes)
+            eng.program_out(s_, dev=bufs[b][s_], nbytes=nbytes)
+
+    hev = HipEvents()
+    ev_s = [hev.create() for _ in range(K)]
+    ev_e = [hev.create() for _ in range(K)]
+    # plain launch: one grid over all bodies, two outputs
+    log("bare launch")
+    def bare():
+        ce.ce_bare_run_outs(kid, params, bufs[0], bufs[1], stream=stream.cuda_stream, sync=True)
+    t_bare = timed_runs(bare, W, K, sync)
+    for i in range(K):
+        hev.record(ev_s[i], stream.cuda_stream)
+        ce.ce_bare_run_outs(kid, params, bufs[0], bufs[1], stream=stream.cuda_stream, sync=False)
+        hev.record(ev_e[i], stream.cuda_stream)
+    sync()
+    k_bare_ms = med([hev.elapsed_ms(ev_s[i], ev_e[i]) for i in range(K)])
+
+    eng = ce.Engine()
+    eng.stream(stream.cuda_stream)
+    eng.work_items([n], [256])
+    eng.program_kernel(kid, params)
+    bind(eng, 0)
+    log("engine GPU only")
+    eng.use(ce.CE_DEV_GPU, 0, 0)
+    eng.scheduler(ce.CE_SCHED_STATIC)
+    t_gpu = timed_runs(eng.run, W, K, sync)
+    log("engine host only")
+    eng.use(ce.CE_DEV_HOST, 0, args.host_threads)
+    t_host = timed_runs(eng.run, 1, min(K, 3), sync)
+    host_threads_used = eng.stats().host_threads
+
+    log("co-execution")
+    eng.use(ce.CE_DEV_GPU | ce.CE_DEV_HOST, 0, args.host_threads)
+    eng.scheduler(ce.CE_SCHED_DYNAMIC, package_granules=1)
+    for k in range(W):
+        bind(eng, k)
+        eng.run()
+    per_run = []
+    sync()
+    t0 = time.perf_counter()
+    for k in range(K):
+        a = time.perf_counter()
+        bind(eng, W + k)
+        eng.run()
+        per_run.append(time.perf_counter() - a)
+    sync()
+    T_total = time.perf_counter() - t0
+    stats = []
+    for k in range(K):
+        bind(eng, W + K + k)
+        eng.kernel_events(ev_s[k], ev_e[k])
+        eng.run()
+        stats.append(eng.stats())
+    eng.kernel_events(None, None)
+    kern_ms = [hev.elapsed_ms(ev_s[i], ev_e[i]) for i in range(K)]
+    for ev in ev_s + ev_e:
+        hev.destroy(ev)
+    T_bare, T_gpu, T_host = med(t_bare), med(t_gpu), med(t_host)
+    s_real = T_bare / med(per_run)
+    s_max = min(T_bare, T_host) * (1.0 / T_bare + 1.0 / T_host)
+    gpu_share = sum(s_.items[0] for s_ in stats) / (K * n)
+    ops = 24.0 * n * n * gpu_share
+    achieved = ops / (med(kern_ms) * 1e-3) / 1e12
+    cpu_base = None
+    if not args.no_cpu_baseline:
+        log("oracle CPU baseline")
+        from oracle import oracle as O
+        t0c = time.perf_counter()
+        i = 0
+        while time.perf_counter() - t0c < 10.0:
+            O.nbody_step_body(pos, vel, eps2, dt, i, True)
+            i += 1
+        dtc = time.perf_counter() - t0c
+        cpu_base = {"value": i / dtc, "unit": "work-items/s", "cores": 1, "kind": "oracle",
+                    "sample": f"{i} bodies stepped (each against all {n})", "seconds": dtc}
+    res = {
+        "metric": METRIC, "value": n * K / T_total, "unit": "work-items/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": T_total / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded SplitMix64 inputs; see DESIGN.md)",
+        "config": {"workload": "nbody integration step, 65536 bodies fp32, eps2 1e-6, dt 1e-3, strict rsqrt, "
+                               "resident ping-pong buffers", "scheduler": "dynamic 256-body packages",
+                   "devices": "gpu+host", "residency": "device"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "TOP/s (FP32 VALU lane-ops)", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "k_persistent<NbodyStepTile<true>>", "kernel_ms": med(kern_ms),
+                     "ops_per_interaction": 24},
+        "cpu_baseline": cpu_base,
+        "coexec": {
+            "plain_gpu_items_per_s": n / T_bare, "vs_plain_gpu": s_real, "s_real": s_real, "s_max": s_max,
+            "efficiency": s_real / s_max, "balance": med([s_.balance for s_ in stats]),
+            "overhead_pct_gpu_only": (T_gpu - T_bare) / T_bare * 100.0,
+            "t_bare_ms": T_bare * 1e3, "t_bare_kernel_ms": k_bare_ms, "t_engine_gpu_ms": T_gpu * 1e3,
+            "t_engine_host_ms": T_host * 1e3, "t_coexec_ms_median": med(per_run) * 1e3,
+            "host_threads": host_threads_used, "gpu_share": gpu_share,
+            "packages_gpu": med([s_.packages[0] for s_ in stats]), "packages_host": med([s_.packages[1] for s_ in stats]),
+            "t_device_ms": [med([s_.t_device[0] for s_ in stats]) * 1e3, med([s_.t_device[1] for s_ in stats]) * 1e3],
         },
     }
     print(json.dumps(res), flush=True)
