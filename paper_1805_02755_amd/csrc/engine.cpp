@@ -161,6 +161,8 @@ struct ce_engine {
   ce_blur5_params blur{};
   ce_nbody_params nb{};
   ce_nbody_step_params nbs{};
+  static constexpr int kOccSlots = 16;
+  int occ_cache[kOccSlots] = {};  // persistent workgroups per CU by (kernel id, strict)
   Binding in[kMaxSlots];
   Binding out[kMaxSlots];
   uint32_t pat_outs = 1, pat_items = 1;
@@ -818,8 +820,13 @@ struct ce_engine {
     // persistent grid: resident workgroups, plus gatherers (two per XCD)
     uint32_t grid = 0, gather_wgs = 0;
     if (use_gpu()) {
-      int bpc = 0;
-      if ((he = persistent_blocks_per_cu(kargs, &bpc)) != hipSuccess) return hip_fail(he, "run: occupancy");
+      // resident workgroups per CU: a property of the compiled kernel, asked once per payload
+      const int occ_key = kernel_id * 2 + (kargs.strict ? 1 : 0);
+      int bpc = occ_key < kOccSlots ? occ_cache[occ_key] : 0;
+      if (bpc == 0) {
+        if ((he = persistent_blocks_per_cu(kargs, &bpc)) != hipSuccess) return hip_fail(he, "run: occupancy");
+        if (occ_key < kOccSlots) occ_cache[occ_key] = bpc;
+      }
       grid = (uint32_t)std::max(1, bpc) * (uint32_t)n_cu;
       gather_wgs = gather ? std::min<uint32_t>(16, std::max<uint32_t>(1, grid / 4)) : 0;
       const uint32_t all_tiles = gpu_tiles(kargs, 0, G);
