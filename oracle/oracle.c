@@ -194,6 +194,47 @@ void orc_nbody_acc_f64(const float* pos4, uint32_t n, double eps2, uint32_t i0, 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Binomial option pricing (the Binomial Options program of sections 6.1 and
+ * 7.2: one output per work-group of steps+1 work-items, an out pattern of
+ * 1:255 for 254 steps). The paper gives the program's shape, not its
+ * arithmetic; this is the textbook Cox-Ross-Rubinstein tree for a European
+ * call. Per step dt = T/N, up factor u = exp(sigma sqrt(dt)), down d = 1/u,
+ * risk-neutral p = (exp(r dt) - d)/(u - d), discount exp(-r dt). The tree's
+ * constants are computed in double and rounded once to FP32: pu = disc*p,
+ * pd = disc*(1-p), and the leaf factors f_j = u^(2j-N) for j = 0..N. */
+void orc_binomial_table(uint32_t steps, double sigma, double rate, double T, float* factors, float* pu,
+                        float* pd) {
+  const double dt = T / (double)steps;
+  const double lu = sigma * sqrt(dt);
+  const double u = exp(lu);
+  const double d = 1.0 / u;
+  const double p = (exp(rate * dt) - d) / (u - d);
+  const double disc = exp(-rate * dt);
+  *pu = (float)(disc * p);
+  *pd = (float)(disc * (1.0 - p));
+  for (uint32_t j = 0; j <= steps; ++j) factors[j] = (float)exp(lu * ((double)(2 * (int64_t)j) - (double)steps));
+}
+
+/* Price of one call with spot S and strike X, in FP32: leaves
+ * V_j = max(S*f_j - X, 0), then for each level L = N-1 .. 0 and j = 0..L,
+ * V_j = pu*V_{j+1} + pd*V_j (two products, then their sum); the price is V_0. */
+float orc_binomial_price(float S, float X, uint32_t steps, const float* factors, float pu, float pd) {
+  float v[1024];
+  if (steps >= 1024) return -1.0f;
+  for (uint32_t j = 0; j <= steps; ++j) {
+    const float t = S * factors[j] - X;
+    v[j] = t > 0.0f ? t : 0.0f;
+  }
+  for (uint32_t L = steps; L-- > 0;)
+    for (uint32_t j = 0; j <= L; ++j) {
+      const float up = pu * v[j + 1];
+      const float dn = pd * v[j];
+      v[j] = up + dn;
+    }
+  return v[0];
+}
+
+/* ------------------------------------------------------------------------ */
 /* Static scheduler (section 5.3): before the run the index space is cut into
  * one contiguous part per device, sized by the given proportions. The API
  * listing of section 6.2 passes n-1 proportions for n devices; the last device

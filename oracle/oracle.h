@@ -53,6 +53,13 @@ void orc_nbody_step_body(const float* pos4, const float* vel4, uint32_t n, float
 void orc_nbody_step(const float* pos4, const float* vel4, uint32_t n, float eps2, float dt, int strict,
                     float* pos_out4, float* vel_out4);
 
+/* ---- Binomial option pricing (Binomial Options program, sections 6.1 and 7.2):
+ * Cox-Ross-Rubinstein tree of `steps` steps for a European call; the tree's
+ * constants rounded once from double; the backward induction in FP32. */
+void orc_binomial_table(uint32_t steps, double sigma, double rate, double T, float* factors, float* pu,
+                        float* pd);
+float orc_binomial_price(float S, float X, uint32_t steps, const float* factors, float pu, float pd);
+
 /* ---- schedulers (section 5.3) */
 /* Static: n devices, props[0..n-2] fractions in device order, last gets the
  * rest; order[k] = device placed k-th along the index space. With n_bands > 0

@@ -57,6 +57,11 @@ def lib():
                                           _f32p, _f32p]
         L.orc_nbody_step.restype = None
         L.orc_nbody_step.argtypes = [_f32p, _f32p, C.c_uint32, C.c_float, C.c_float, C.c_int, _f32p, _f32p]
+        L.orc_binomial_table.restype = None
+        L.orc_binomial_table.argtypes = [C.c_uint32, C.c_double, C.c_double, C.c_double, _f32p,
+                                         C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.orc_binomial_price.restype = C.c_float
+        L.orc_binomial_price.argtypes = [C.c_float, C.c_float, C.c_uint32, _f32p, C.c_float, C.c_float]
         L.orc_static_plan.restype = C.c_int
         L.orc_static_plan.argtypes = [C.c_uint64, C.c_uint32, _f64p, _u32p, C.c_uint32, _u64p, _u64p]
         L.orc_hguided_size.restype = C.c_uint64
@@ -132,6 +137,29 @@ def nbody_step_body(pos4: np.ndarray, vel4: np.ndarray, eps2: float, dt: float, 
     po, vo = np.empty(4, np.float32), np.empty(4, np.float32)
     lib().orc_nbody_step_body(pos4, vel4, pos4.shape[0], eps2, dt, int(strict), i, po, vo)
     return po, vo
+
+
+def binomial_table(steps: int, sigma: float, rate: float, T: float):
+    """(leaf factors f_0..f_N as float32, pu, pd) of the Cox-Ross-Rubinstein tree."""
+    f = np.empty(steps + 1, np.float32)
+    pu, pd = C.c_float(), C.c_float()
+    lib().orc_binomial_table(steps, sigma, rate, T, f, C.byref(pu), C.byref(pd))
+    return f, np.float32(pu.value), np.float32(pd.value)
+
+
+def binomial_price(S: float, X: float, steps: int, factors: np.ndarray, pu, pd) -> np.float32:
+    f = np.ascontiguousarray(factors, dtype=np.float32)
+    return np.float32(lib().orc_binomial_price(S, X, steps, f, float(pu), float(pd)))
+
+
+def binomial(spots: np.ndarray, X: float, steps: int, factors: np.ndarray, pu, pd) -> np.ndarray:
+    """Prices of every spot (any shape, float32), one call each."""
+    s = np.ascontiguousarray(spots, dtype=np.float32)
+    out = np.empty_like(s)
+    flat, of = s.reshape(-1), out.reshape(-1)
+    for k in range(flat.size):
+        of[k] = binomial_price(float(flat[k]), X, steps, factors, pu, pd)
+    return out
 
 
 def nbody_acc_f64(pos4: np.ndarray, eps2: float, i0: int = 0, i1: int | None = None) -> np.ndarray:

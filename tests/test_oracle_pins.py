@@ -314,6 +314,58 @@ def test_nbody_step_two_body_circular_orbit():
     assert abs(angle - 90.0) < 2.0
 
 
+# ------------------------------------------------------ binomial options
+BIN_SIGMA, BIN_RATE, BIN_T, BIN_X, BIN_N = 0.3, 0.05, 1.0, 100.0, 254
+
+
+def _black_scholes_call(S, X, sigma, r, T):
+    from math import erf, exp, log, sqrt
+    nd = lambda x: 0.5 * (1.0 + erf(x / sqrt(2.0)))
+    d1 = (log(S / X) + (r + 0.5 * sigma * sigma) * T) / (sigma * sqrt(T))
+    return S * nd(d1) - X * exp(-r * T) * nd(d1 - sigma * sqrt(T))
+
+
+def test_binomial_converges_to_black_scholes():
+    """254 steps of the tree are within a few cents of the closed form (the
+    tree's error is of order 1/N)."""
+    f, pu, pd = O.binomial_table(BIN_N, BIN_SIGMA, BIN_RATE, BIN_T)
+    for S in (60.0, 80.0, 100.0, 120.0, 140.0):
+        c = float(O.binomial_price(S, BIN_X, BIN_N, f, pu, pd))
+        assert abs(c - _black_scholes_call(S, BIN_X, BIN_SIGMA, BIN_RATE, BIN_T)) < 0.05, S
+
+
+def test_binomial_one_step_closed_form():
+    import math
+    sigma, r, T, S, X = 0.25, 0.04, 0.5, 105.0, 100.0
+    f, pu, pd = O.binomial_table(1, sigma, r, T)
+    u = math.exp(sigma * math.sqrt(T))
+    d = 1 / u
+    p = (math.exp(r * T) - d) / (u - d)
+    ref = math.exp(-r * T) * (p * max(S * u - X, 0) + (1 - p) * max(S * d - X, 0))
+    assert abs(float(O.binomial_price(S, X, 1, f, pu, pd)) - ref) <= 1e-5 * ref
+
+
+def test_binomial_table_symmetry():
+    import math
+    f, pu, pd = O.binomial_table(BIN_N, BIN_SIGMA, BIN_RATE, BIN_T)
+    assert f[BIN_N // 2] == np.float32(1.0)
+    prod = f.astype(np.float64) * f[::-1].astype(np.float64)
+    assert np.all(np.abs(prod - 1.0) <= 4 * 2.0 ** -24)
+    assert abs(float(pu) + float(pd) - math.exp(-BIN_RATE * BIN_T / BIN_N)) <= 2 * 2.0 ** -24
+
+
+def test_binomial_bounds_and_monotonicity():
+    import math
+    f, pu, pd = O.binomial_table(BIN_N, BIN_SIGMA, BIN_RATE, BIN_T)
+    spots = np.linspace(1.0, 300.0, 120).astype(np.float32)
+    c = O.binomial(spots, BIN_X, BIN_N, f, pu, pd).astype(np.float64)
+    lower = np.maximum(spots - BIN_X * math.exp(-BIN_RATE * BIN_T), 0.0)
+    assert np.all(c >= lower - 1e-3) and np.all(c <= spots)
+    assert np.all(np.diff(c) >= 0)
+    # no leaf is in the money below X / f_N: the price is exactly zero
+    assert O.binomial_price(0.5, BIN_X, BIN_N, f, pu, pd) == 0.0
+
+
 # -------------------------------------------------------------- schedulers
 def test_static_listing_example():
     g = _gold("static_listing_example.json")
