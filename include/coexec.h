@@ -54,6 +54,8 @@ typedef int32_t ce_status;
 #define CE_KERNEL_BLUR5 2     /* 5x5 Gaussian blur, 2-D, 2 in (image, weights) : 1 out */
 #define CE_KERNEL_NBODY_ACC 3 /* all-pairs N-body acceleration, 1-D, 1 in : 1 out      */
 #define CE_KERNEL_NBODY_STEP 4 /* N-body integration step, 1-D, 2 in (pos, vel) : 2 out (pos, vel) */
+#define CE_KERNEL_BINOMIAL 5    /* binomial option pricing, 1-D, 2 in (spots, leaf factors) : 1 out,
+                                   out pattern 1 : steps+1                                         */
 
 /* Schedulers (section 5.3). */
 #define CE_SCHED_STATIC 0
@@ -105,6 +107,25 @@ typedef struct {
   float dt;
   uint32_t strict;
 } ce_nbody_step_params;
+
+/* Binomial option pricing (the Binomial Options program of sections 6.1 and
+ * 7.2): European calls priced on a Cox-Ross-Rubinstein tree of `steps`
+ * steps (1..255). One work-group of steps+1 work-items prices four options
+ * (one float4 of spots) and writes one float4 of prices: the index space is
+ * gws = (steps+1) * n_groups with lws = steps+1, and the out pattern is one
+ * output element per steps+1 work-items (section 6.1's 1:255 for 254 steps).
+ * Slot 0 in: n_groups float4 spot prices; slot 1 in: steps+1 FP32 leaf
+ * factors f_j = u^(2j-steps). Out: n_groups float4 prices. In FP32: leaves
+ * V_j = max(S*f_j - strike, 0), then for each level L = steps-1 .. 0 and
+ * j = 0..L, V_j = pu*V_{j+1} + pd*V_j (two products, then their sum); the
+ * price is V_0. ce_binomial_table gives the factors, pu and pd. */
+typedef struct {
+  uint32_t n_groups;
+  uint32_t steps;
+  float strike;
+  float pu;  /* discounted up probability   */
+  float pd;  /* discounted down probability */
+} ce_binomial_params;
 
 /* Scheduler description (section 5.3). Arrays are indexed by engine device
  * index (GPU = 0 when used, then host).
@@ -381,6 +402,13 @@ uint64_t ce_sched_hguided_size(uint64_t G_r, const uint64_t* power, uint32_t n, 
 
 /* 5x5 Gaussian weights for sigma (normalised in double, rounded to FP32). */
 ce_status ce_gauss5_weights(double sigma, float* w25);
+/* Tree constants of CE_KERNEL_BINOMIAL for volatility sigma, rate r and
+ * maturity T: dt = T/steps, u = exp(sigma*sqrt(dt)), d = 1/u,
+ * p = (exp(r*dt) - d)/(u - d), disc = exp(-r*dt); pu = disc*p,
+ * pd = disc*(1-p) and factors[j] = u^(2j-steps), j = 0..steps (steps+1
+ * floats), each computed in double and rounded once. */
+ce_status ce_binomial_table(uint32_t steps, double sigma, double rate, double T, float* factors, float* pu,
+                            float* pd);
 
 /* Library version string. */
 const char* ce_version(void);

@@ -37,6 +37,7 @@ CE_KERNEL_ESCAPE = 1
 CE_KERNEL_BLUR5 = 2
 CE_KERNEL_NBODY_ACC = 3
 CE_KERNEL_NBODY_STEP = 4
+CE_KERNEL_BINOMIAL = 5
 
 CE_SCHED_STATIC = 0
 CE_SCHED_DYNAMIC = 1
@@ -52,7 +53,7 @@ EXPORTED_SYMBOLS = (
     "ce_engine_stream", "ce_engine_output_merge", "ce_engine_kernel_events", "ce_program_kernel", "ce_program_in", "ce_program_out", "ce_program_out_pattern",
     "ce_engine_run", "ce_engine_stats", "ce_engine_trace", "ce_engine_has_errors", "ce_engine_error_count",
     "ce_engine_error", "ce_engine_clear_errors", "ce_bare_run", "ce_bare_run_outs", "ce_sched_static_plan", "ce_sched_hguided_size",
-    "ce_gauss5_weights", "ce_version", "ce_batch_create", "ce_batch_destroy", "ce_batch_add_escape",
+    "ce_gauss5_weights", "ce_binomial_table", "ce_version", "ce_batch_create", "ce_batch_destroy", "ce_batch_add_escape",
     "ce_batch_clear", "ce_batch_set_config", "ce_batch_get_config", "ce_batch_tune", "ce_batch_run",
     "ce_batch_run_separate", "ce_batch_stats", "ce_batch_error", "ce_server_create", "ce_server_destroy",
     "ce_server_submit", "ce_server_poll", "ce_server_wait", "ce_server_output", "ce_server_copy_output",
@@ -80,6 +81,11 @@ class ce_nbody_params(C.Structure):
 
 class ce_nbody_step_params(C.Structure):
     _fields_ = [("n", C.c_uint32), ("eps2", C.c_float), ("dt", C.c_float), ("strict", C.c_uint32)]
+
+
+class ce_binomial_params(C.Structure):
+    _fields_ = [("n_groups", C.c_uint32), ("steps", C.c_uint32), ("strike", C.c_float), ("pu", C.c_float),
+                ("pd", C.c_float)]
 
 
 class ce_sched_desc(C.Structure):
@@ -176,6 +182,8 @@ def load(path: str):
                                        C.POINTER(u64)]),
         "ce_sched_hguided_size": (u64, [u64, C.POINTER(u64), u32, u32, u32, u64]),
         "ce_gauss5_weights": (i32, [C.c_double, C.POINTER(C.c_float)]),
+        "ce_binomial_table": (i32, [C.c_uint32, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_float),
+                                    C.POINTER(C.c_float), C.POINTER(C.c_float)]),
         "ce_version": (C.c_char_p, []),
         "ce_batch_create": (i32, [C.POINTER(vp), vp]),
         "ce_batch_destroy": (None, [vp]),
@@ -246,6 +254,18 @@ def _nbytes(x) -> int:
 # ---------------------------------------------------------------- free functions
 def ce_version() -> str:
     return lib().ce_version().decode()
+
+
+def ce_binomial_table(steps: int, sigma: float, rate: float, T: float):
+    """Leaf factors (steps+1 float32), pu and pd of CE_KERNEL_BINOMIAL's tree."""
+    import numpy as np
+    f = np.empty(steps + 1, dtype=np.float32)
+    pu, pd = C.c_float(), C.c_float()
+    st = lib().ce_binomial_table(steps, sigma, rate, T, f.ctypes.data_as(C.POINTER(C.c_float)), C.byref(pu),
+                                 C.byref(pd))
+    if st != CE_OK:
+        raise CoexecError(st, "ce_binomial_table")
+    return f, np.float32(pu.value), np.float32(pd.value)
 
 
 def ce_gauss5_weights(sigma: float = 1.0):

@@ -328,4 +328,46 @@ struct NbodyStepTile {
   }
 };
 
+// Binomial option pricing: a granule is one work-group pricing four calls
+// (one float4 of spots). Thread j holds leaf j of all four trees; each level
+// of the backward induction reads the neighbour's value through LDS between
+// two barriers that every thread of the workgroup passes.
+struct BinomialTile {
+  static constexpr int kMinBlocksPerCu = 1;
+  ce_binomial_params p;
+  const float4* spots;
+  const float* factors;
+  float4* out;
+  __device__ void load_constants() {}
+  __host__ __device__ uint64_t granules() const { return p.n_groups; }
+  __host__ __device__ uint32_t ntiles(uint64_t g0, uint64_t g1) const { return (uint32_t)(g1 - g0); }
+  __device__ void run(uint64_t g0, uint64_t, uint32_t t) const {
+    __shared__ float4 sh[kBlockThreads];
+    const uint64_t grp = g0 + t;
+    const uint32_t j = threadIdx.x;
+    const uint32_t n = p.steps;
+    const float4 S = spots[grp];
+    const float X = p.strike, pu = p.pu, pd = p.pd;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (j <= n) {
+      const float f = factors[j];
+      const float a = S.x * f - X, b = S.y * f - X, c = S.z * f - X, d = S.w * f - X;
+      v = make_float4(a > 0.0f ? a : 0.0f, b > 0.0f ? b : 0.0f, c > 0.0f ? c : 0.0f, d > 0.0f ? d : 0.0f);
+    }
+    for (uint32_t L = n; L-- > 0;) {
+      __syncthreads();
+      sh[j] = v;
+      __syncthreads();
+      if (j <= L) {
+        const float4 up = sh[j + 1];
+        v.x = pu * up.x + pd * v.x;
+        v.y = pu * up.y + pd * v.y;
+        v.z = pu * up.z + pd * v.z;
+        v.w = pu * up.w + pd * v.w;
+      }
+    }
+    if (j == 0) out[grp] = v;
+  }
+};
+
 }  // namespace ce

@@ -161,6 +161,7 @@ struct ce_engine {
   ce_blur5_params blur{};
   ce_nbody_params nb{};
   ce_nbody_step_params nbs{};
+  ce_binomial_params bin{};
   static constexpr int kOccSlots = 16;
   int occ_cache[kOccSlots] = {};  // persistent workgroups per CU by (kernel id, strict)
   Binding in[kMaxSlots];
@@ -248,6 +249,7 @@ struct ce_engine {
       case CE_KERNEL_BLUR5: return blur.h;
       case CE_KERNEL_NBODY_ACC: return ceil_div(nb.n, kNbodyGranule);
       case CE_KERNEL_NBODY_STEP: return ceil_div(nbs.n, kNbodyGranule);
+      case CE_KERNEL_BINOMIAL: return bin.n_groups;
     }
     return 0;
   }
@@ -262,11 +264,15 @@ struct ce_engine {
         const uint64_t a = g0 * kNbodyGranule, b = std::min<uint64_t>(g1 * kNbodyGranule, n_bodies());
         return b > a ? b - a : 0;
       }
+      case CE_KERNEL_BINOMIAL: return (g1 - g0) * (bin.steps + 1);  // one work-group per granule
     }
     return 0;
   }
-  size_t out_elem_bytes() const { return is_nbody() ? 16 : 4; }
+  // output elements: one float4 per body, per option group, or one word per pixel
+  size_t out_elem_bytes() const { return (is_nbody() || kernel_id == CE_KERNEL_BINOMIAL) ? 16 : 4; }
+  // first output element of granule g (out pattern 1:(steps+1) for binomial)
   uint64_t item_offset(uint64_t g) const {
+    if (kernel_id == CE_KERNEL_BINOMIAL) return g;
     return is_nbody() ? std::min<uint64_t>(g * kNbodyGranule, n_bodies()) : g * gws[0];
   }
   size_t in_bytes(int slot) const {
@@ -275,6 +281,7 @@ struct ce_engine {
         return slot == 0 ? (size_t)blur.w * blur.h * 4 : (slot == 1 ? 25 * 4 : 0);
       case CE_KERNEL_NBODY_ACC: return slot == 0 ? (size_t)nb.n * 16 : 0;
       case CE_KERNEL_NBODY_STEP: return slot < 2 ? (size_t)nbs.n * 16 : 0;
+      case CE_KERNEL_BINOMIAL: return slot == 0 ? (size_t)bin.n_groups * 16 : (slot == 1 ? (size_t)(bin.steps + 1) * 4 : 0);
     }
     return 0;
   }
@@ -283,6 +290,7 @@ struct ce_engine {
       case CE_KERNEL_BLUR5: return 2;
       case CE_KERNEL_NBODY_ACC: return 1;
       case CE_KERNEL_NBODY_STEP: return 2;
+      case CE_KERNEL_BINOMIAL: return 2;
     }
     return 0;
   }
@@ -293,6 +301,7 @@ struct ce_engine {
       case CE_KERNEL_BLUR5: return (size_t)blur.w * blur.h * 4;
       case CE_KERNEL_NBODY_ACC: return (size_t)nb.n * 16;
       case CE_KERNEL_NBODY_STEP: return (size_t)nbs.n * 16;
+      case CE_KERNEL_BINOMIAL: return (size_t)bin.n_groups * 16;
     }
     return 0;
   }
@@ -441,6 +450,10 @@ struct ce_engine {
                           (float*)host_out1);
         break;
       }
+      case CE_KERNEL_BINOMIAL:
+        binomial_groups((const float*)host_in0, (const float*)host_in1, bin.steps, bin.strike, bin.pu, bin.pd,
+                        p.g0 + ti, p.g0 + ti + 1, (float*)host_out);
+        break;
     }
   }
 
@@ -452,6 +465,9 @@ struct ce_engine {
       const uint64_t i1 = std::min<uint64_t>(i0 + kHostNbodyTile, end);
       *off = i0 * 16;
       *len = (i1 - i0) * 16;
+    } else if (kernel_id == CE_KERNEL_BINOMIAL) {
+      *off = (p.g0 + ti) * 16;
+      *len = 16;
     } else {
       *off = (p.g0 + ti) * gws[0] * 4;
       *len = gws[0] * 4;
@@ -719,6 +735,9 @@ struct ce_engine {
     if (is_nbody()) {
       if (ndim != 1 || gws[0] != n_bodies() || lws0 != kNbodyGranule)
         return fail(CE_E_INVALID, "run: n-body needs a 1-D space of n items with lws 256");
+    } else if (kernel_id == CE_KERNEL_BINOMIAL) {
+      if (ndim != 1 || lws0 != bin.steps + 1 || gws[0] != (uint64_t)(bin.steps + 1) * bin.n_groups)
+        return fail(CE_E_INVALID, "run: binomial needs gws = (steps+1) * n_groups and lws = steps+1");
     } else {
       const uint64_t w = kernel_id == CE_KERNEL_ESCAPE ? esc.w : blur.w;
       const uint64_t h = kernel_id == CE_KERNEL_ESCAPE ? esc.h : blur.h;
@@ -747,6 +766,7 @@ struct ce_engine {
     kargs.blur = blur;
     kargs.nb = nb;
     kargs.nbs = nbs;
+    kargs.bin = bin;
     const void* gin[kMaxSlots] = {nullptr, nullptr};
     if (use_gpu()) {
       for (int s = 0; s < n_in_slots(); ++s) {
@@ -1318,6 +1338,18 @@ ce_status ce_program_kernel(ce_engine* e, int kernel_id, const void* params, siz
       e->nb = p;
       break;
     }
+    case CE_KERNEL_BINOMIAL: {
+      if (params_size != sizeof(ce_binomial_params)) return e->fail(CE_E_INVALID, "kernel: binomial params size");
+      ce_binomial_params p;
+      memcpy(&p, params, sizeof p);
+      if (p.n_groups == 0) return e->fail(CE_E_INVALID, "kernel: no option groups");
+      if (p.steps == 0 || p.steps + 1 > kBlockThreads)
+        return e->fail(CE_E_INVALID, "kernel: binomial steps must be in [1, %u]", kBlockThreads - 1);
+      if (!std::isfinite(p.strike) || !std::isfinite(p.pu) || !std::isfinite(p.pd))
+        return e->fail(CE_E_INVALID, "kernel: binomial strike and probabilities must be finite");
+      e->bin = p;
+      break;
+    }
     case CE_KERNEL_NBODY_STEP: {
       if (params_size != sizeof(ce_nbody_step_params)) return e->fail(CE_E_INVALID, "kernel: n-body step params size");
       ce_nbody_step_params p;
@@ -1361,9 +1393,12 @@ ce_status ce_program_out(ce_engine* e, uint32_t slot, void* host_ptr, void* dev_
 ce_status ce_program_out_pattern(ce_engine* e, uint32_t outs, uint32_t items) {
   if (!e) return CE_E_INVALID;
   if (outs == 0 || items == 0) return e->fail(CE_E_INVALID, "out_pattern: zero term");
-  if (outs != items) return e->fail(CE_E_UNSUPPORTED, "out_pattern: only 1:1 payloads are built");
-  e->pat_outs = 1;
-  e->pat_items = 1;
+  // the pattern is fixed by the payload: 1:(steps+1) for binomial, 1:1 otherwise
+  const uint32_t want = e->kernel_id == CE_KERNEL_BINOMIAL ? e->bin.steps + 1 : 1;
+  if (outs != 1 || items != want)
+    return e->fail(CE_E_UNSUPPORTED, "out_pattern: this payload writes 1 output per %u work-items", want);
+  e->pat_outs = outs;
+  e->pat_items = items;
   return CE_OK;
 }
 
@@ -1442,6 +1477,13 @@ ce_status ce_bare_run_outs(int kernel_id, const void* params, size_t params_size
       if (a.nb.n == 0 || !(a.nb.eps2 >= 1.17549435e-38f)) return CE_E_INVALID;
       a.strict = a.nb.strict;
       a.in0 = ins[0];
+      break;
+    case CE_KERNEL_BINOMIAL:
+      if (params_size != sizeof(ce_binomial_params) || !ins || !ins[0] || !ins[1]) return CE_E_INVALID;
+      memcpy(&a.bin, params, sizeof a.bin);
+      if (a.bin.n_groups == 0 || a.bin.steps == 0 || a.bin.steps + 1 > kBlockThreads) return CE_E_INVALID;
+      a.in0 = ins[0];
+      a.in1 = ins[1];
       break;
     case CE_KERNEL_NBODY_STEP:
       if (params_size != sizeof(ce_nbody_step_params) || !ins || !ins[0] || !ins[1] || !outs[1]) return CE_E_INVALID;
@@ -1534,6 +1576,22 @@ ce_status ce_gauss5_weights(double sigma, float* w25) {
       sum += v;
     }
   for (int k = 0; k < 25; ++k) w25[k] = (float)(e[k] / sum);
+  return CE_OK;
+}
+
+ce_status ce_binomial_table(uint32_t steps, double sigma, double rate, double T, float* factors, float* pu,
+                            float* pd) {
+  if (!factors || !pu || !pd || steps == 0 || !(sigma > 0.0) || !(T > 0.0) || !std::isfinite(rate))
+    return CE_E_INVALID;
+  const double dt = T / (double)steps;
+  const double lu = sigma * std::sqrt(dt);
+  const double u = std::exp(lu);
+  const double d = 1.0 / u;
+  const double p = (std::exp(rate * dt) - d) / (u - d);
+  const double disc = std::exp(-rate * dt);
+  *pu = (float)(disc * p);
+  *pd = (float)(disc * (1.0 - p));
+  for (uint32_t j = 0; j <= steps; ++j) factors[j] = (float)std::exp(lu * ((double)(2 * (int64_t)j) - (double)steps));
   return CE_OK;
 }
 

@@ -246,6 +246,27 @@ void nbody_step_update(const float* pos4, const float* vel4, float dt, uint64_t 
   }
 }
 
+void binomial_groups(const float* spots4, const float* factors, uint32_t steps, float strike, float pu, float pd,
+                     uint64_t g0, uint64_t g1, float* out4) {
+  float v[256];
+  for (uint64_t g = g0; g < g1; ++g) {
+    for (int c = 0; c < 4; ++c) {
+      const float S = spots4[4 * g + c];
+      for (uint32_t j = 0; j <= steps; ++j) {
+        const float t = S * factors[j] - strike;
+        v[j] = t > 0.0f ? t : 0.0f;
+      }
+      for (uint32_t L = steps; L-- > 0;)
+        for (uint32_t j = 0; j <= L; ++j) {
+          const float up = pu * v[j + 1];
+          const float dn = pd * v[j];
+          v[j] = up + dn;
+        }
+      out4[4 * g + c] = v[0];
+    }
+  }
+}
+
 const HostPayloadFns* host_payloads() {
   __builtin_cpu_init();
   if (__builtin_cpu_supports("avx512f") && __builtin_cpu_supports("avx512dq") &&

@@ -33,4 +33,10 @@ const HostPayloadFns* host_payloads();
 void nbody_step_update(const float* pos4, const float* vel4, float dt, uint64_t i0, uint64_t i1, float* pos_out4,
                        float* vel_out4);
 
+// Binomial option pricing of groups [g0, g1) (four calls per float4 of
+// spots), with the GPU's FP32 operations: leaves max(S*f_j - strike, 0), then
+// V_j = pu*V_{j+1} + pd*V_j level by level; out4 gets V_0 of each call.
+void binomial_groups(const float* spots4, const float* factors, uint32_t steps, float strike, float pu, float pd,
+                     uint64_t g0, uint64_t g1, float* out4);
+
 }  // namespace ce

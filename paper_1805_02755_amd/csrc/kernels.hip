@@ -573,6 +573,9 @@ template <bool S>
 NbodyTile<S> make_nbody(const KernelArgs& a) {
   return NbodyTile<S>{a.nb, (const float4*)a.in0, (float4*)a.out};
 }
+BinomialTile make_binomial(const KernelArgs& a) {
+  return BinomialTile{a.bin, (const float4*)a.in0, (const float*)a.in1, (float4*)a.out};
+}
 template <bool S>
 NbodyStepTile<S> make_nbody_step(const KernelArgs& a) {
   return NbodyStepTile<S>{a.nbs, (const float4*)a.in0, (const float4*)a.in1, (float4*)a.out, (float4*)a.out1};
@@ -585,6 +588,7 @@ uint64_t gpu_granules(const KernelArgs& a) {
     case CE_KERNEL_BLUR5: return make_blur(a).granules();
     case CE_KERNEL_NBODY_ACC: return make_nbody<true>(a).granules();
     case CE_KERNEL_NBODY_STEP: return make_nbody_step<true>(a).granules();
+    case CE_KERNEL_BINOMIAL: return make_binomial(a).granules();
   }
   return 0;
 }
@@ -595,6 +599,7 @@ uint32_t gpu_tiles(const KernelArgs& a, uint64_t g0, uint64_t g1) {
     case CE_KERNEL_BLUR5: return make_blur(a).ntiles(g0, g1);
     case CE_KERNEL_NBODY_ACC: return make_nbody<true>(a).ntiles(g0, g1);
     case CE_KERNEL_NBODY_STEP: return make_nbody_step<true>(a).ntiles(g0, g1);
+    case CE_KERNEL_BINOMIAL: return make_binomial(a).ntiles(g0, g1);
   }
   return 0;
 }
@@ -615,6 +620,8 @@ hipError_t persistent_blocks_per_cu(const KernelArgs& a, int* blocks) {
                                                                      kBlockThreads, 0)
                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_persistent<NbodyStepTile<false>>,
                                                                      kBlockThreads, 0);
+    case CE_KERNEL_BINOMIAL:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_persistent<BinomialTile>, kBlockThreads, 0);
   }
   return hipErrorInvalidValue;
 }
@@ -636,6 +643,7 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t g
       else
         hipLaunchKernelGGL(k_persistent<NbodyStepTile<false>>, g, b, 0, st, make_nbody_step<false>(a), s);
       break;
+    case CE_KERNEL_BINOMIAL: hipLaunchKernelGGL(k_persistent<BinomialTile>, g, b, 0, st, make_binomial(a), s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -661,6 +669,7 @@ hipError_t launch_bare(const KernelArgs& a, hipStream_t st) {
       else
         hipLaunchKernelGGL(k_bare<NbodyStepTile<false>>, g, b, 0, st, make_nbody_step<false>(a), G);
       break;
+    case CE_KERNEL_BINOMIAL: hipLaunchKernelGGL(k_bare<BinomialTile>, g, b, 0, st, make_binomial(a), G); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

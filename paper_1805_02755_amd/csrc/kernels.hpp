@@ -17,6 +17,7 @@ struct KernelArgs {
   ce_blur5_params blur;
   ce_nbody_params nb;
   ce_nbody_step_params nbs;
+  ce_binomial_params bin;
   const void* in0;          // device pointers
   const void* in1;
   void* out;

@@ -128,6 +128,17 @@ def nbody_velocities(n: int = 65536, seed: int = SEED_NBODY) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
+# Binomial option spots
+# --------------------------------------------------------------------------
+SEED_BINOMIAL = 0xB10A
+
+
+def binomial_spots(n_groups: int, seed: int = SEED_BINOMIAL) -> np.ndarray:
+    """(n_groups, 4) FP32 spot prices uniform in [50, 150): four options per group."""
+    return uniform_f32(seed, 1, n_groups * 4, 50.0, 150.0).reshape(n_groups, 4)
+
+
+# --------------------------------------------------------------------------
 # Batched escape-time jobs
 # --------------------------------------------------------------------------
 def batch_jobs(n_jobs: int = 256, seed: int = SEED_BATCH, side_lo: int = 64, side_hi: int = 2048,

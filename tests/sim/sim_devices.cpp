@@ -112,7 +112,9 @@ namespace ce {
 // ------------------------------------------------ coverage-marking payloads
 namespace {
 size_t item_words(int kernel_id) {
-  return (kernel_id == CE_KERNEL_NBODY_ACC || kernel_id == CE_KERNEL_NBODY_STEP) ? 4 : 1;
+  return (kernel_id == CE_KERNEL_NBODY_ACC || kernel_id == CE_KERNEL_NBODY_STEP || kernel_id == CE_KERNEL_BINOMIAL)
+             ? 4
+             : 1;
 }
 uint32_t bodies_of(const KernelArgs& a) { return a.kernel_id == CE_KERNEL_NBODY_STEP ? a.nbs.n : a.nb.n; }
 // the second output of the step payload gets the same item indices, uncounted
@@ -145,12 +147,14 @@ void h_nbody(const float*, uint32_t, float, int, uint64_t i0, uint64_t i1, float
 const HostPayloadFns kSim = {h_escape, h_blur, h_nbody, "sim"};
 
 uint64_t items_of(const KernelArgs& a, uint64_t g0, uint64_t g1) {
+  if (a.kernel_id == CE_KERNEL_BINOMIAL) return g1 - g0;  // one output element per option group
   if (a.kernel_id == CE_KERNEL_ESCAPE) return (g1 - g0) * a.esc.w;
   if (a.kernel_id == CE_KERNEL_BLUR5) return (g1 - g0) * a.blur.w;
   const uint64_t lo = g0 * 256, hi = std::min<uint64_t>(g1 * 256, bodies_of(a));
   return hi > lo ? hi - lo : 0;
 }
 uint64_t first_item(const KernelArgs& a, uint64_t g) {
+  if (a.kernel_id == CE_KERNEL_BINOMIAL) return g;
   if (a.kernel_id == CE_KERNEL_ESCAPE) return g * a.esc.w;
   if (a.kernel_id == CE_KERNEL_BLUR5) return g * a.blur.w;
   return std::min<uint64_t>(g * 256, bodies_of(a));
@@ -161,6 +165,14 @@ const HostPayloadFns* host_payloads() { return &kSim; }
 
 // The step's update after the (coverage-counting) force payload: the
 // position output gets the same item indices.
+// Binomial groups: one coverage mark per output element.
+void binomial_groups(const float*, const float*, uint32_t, float, float, float, uint64_t g0, uint64_t g1,
+                     float* out4) {
+  const int64_t until = now_ns() + (int64_t)(g_host_ns_per_item * (double)(g1 - g0));
+  mark((uint32_t*)out4, g0, g1, 4);
+  spin_until(until);
+}
+
 void nbody_step_update(const float*, const float*, float, uint64_t i0, uint64_t i1, float* pos_out4, float* vel_out4) {
   uint32_t* po = (uint32_t*)pos_out4;
   const uint32_t* vo = (const uint32_t*)vel_out4;
@@ -171,6 +183,7 @@ void nbody_step_update(const float*, const float*, float, uint64_t i0, uint64_t 
 uint64_t gpu_granules(const KernelArgs& a) {
   if (a.kernel_id == CE_KERNEL_ESCAPE) return a.esc.h;
   if (a.kernel_id == CE_KERNEL_BLUR5) return a.blur.h;
+  if (a.kernel_id == CE_KERNEL_BINOMIAL) return a.bin.n_groups;
   return (bodies_of(a) + 255) / 256;
 }
 uint32_t gpu_tiles(const KernelArgs& a, uint64_t g0, uint64_t g1) {

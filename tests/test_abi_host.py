@@ -73,6 +73,15 @@ def test_hguided_size_matches_oracle():
         assert ce.ce_sched_hguided_size(G_r, P, k, i, m) == O.hguided_size(G_r, P, k, i, m)
 
 
+def test_binomial_table_matches_oracle_bitwise():
+    for steps, sigma, rate, T in [(254, 0.3, 0.05, 1.0), (1, 0.25, 0.04, 0.5), (255, 0.1, 0.0, 2.0), (17, 0.6, 0.1, 0.25)]:
+        f, pu, pd = ce.ce_binomial_table(steps, sigma, rate, T)
+        g, qu, qd = O.binomial_table(steps, sigma, rate, T)
+        assert np.array_equal(f.view(np.uint32), g.view(np.uint32)) and pu == qu and pd == qd
+    with pytest.raises(ce.CoexecError):
+        ce.ce_binomial_table(0, 0.3, 0.05, 1.0)
+
+
 def test_gauss_weights_match_oracle_bitwise():
     for sigma in (0.5, 1.0, 1.7):
         assert np.array_equal(ce.ce_gauss5_weights(sigma), O.gauss5_weights(sigma))

@@ -341,3 +341,78 @@ def test_nbody_step_refusals(simlib):
     L.sim_reset(n)
     eng.run()
     eng.close()
+
+
+def _run_binomial(L, n_groups, steps, devs, sched, residency, merge=ce.CE_MERGE_DMA, rates=(2.0, 50.0, 1000.0)):
+    L.sim_set_rates(*rates)
+    eng = ce.Engine(L)
+    eng.output_merge(merge)
+    eng.use(devs, 0, 4)
+    eng.work_items([(steps + 1) * n_groups], [steps + 1])
+    eng.program_kernel(ce.CE_KERNEL_BINOMIAL, ce.ce_binomial_params(n_groups, steps, 100.0, 0.5, 0.49))
+    eng.program_out_pattern(1, steps + 1)
+    spots = np.zeros((n_groups, 4), np.float32)
+    fac = np.zeros(steps + 1, np.float32)
+    eng.program_in(0, host=spots, dev=spots)
+    eng.program_in(1, host=fac, dev=fac)
+    out = np.zeros((n_groups, 4), np.uint32)
+    mirror = np.zeros((n_groups, 4), np.uint32)
+    if residency == "dev":
+        eng.program_out(0, dev=out)
+    elif residency == "host":
+        eng.program_out(0, host=out)
+    else:
+        eng.program_out(0, host=out, dev=mirror)
+    eng.scheduler(**sched)
+    L.sim_reset(n_groups)
+    eng.run()
+    st, tr = eng.stats(), eng.trace()
+    eng.close()
+    assert np.array_equal(out[:, 0], np.arange(n_groups, dtype=np.uint32))
+    if residency == "both":
+        assert np.array_equal(mirror[:, 0], np.arange(n_groups, dtype=np.uint32))
+    return _coverage(L, n_groups), st, tr
+
+
+@pytest.mark.parametrize("residency", ["dev", "host", "both"])
+@pytest.mark.parametrize("sched", ["hguided", "dynamic", "static8"])
+@pytest.mark.parametrize("devs", [ce.CE_DEV_GPU, ce.CE_DEV_HOST, BOTH])
+def test_binomial_every_group_once(simlib, residency, sched, devs):
+    scheds = dict(SCHEDS, static8=dict(kind=ce.CE_SCHED_STATIC, props=[0.9], order=ce.CE_ORDER_HOST_FIRST,
+                                       n_packages=8))
+    s = scheds[sched] if devs == BOTH else _one_dev(scheds[sched])
+    n_groups = 777
+    cnt, st, tr = _run_binomial(simlib, n_groups, 254, devs, s, residency)
+    assert np.all(cnt == 1)
+    # stats count work-items: steps + 1 per option group
+    assert sum(st.items[:st.n_devices]) == 255 * n_groups
+    covered = np.zeros(n_groups, np.int32)
+    for d, b, e, tc, te in tr:
+        covered[b:e] += 1
+    assert np.all(covered == 1)
+
+
+def test_binomial_pattern_and_space_checks(simlib):
+    eng = ce.Engine(simlib)
+    eng.use(ce.CE_DEV_HOST, 0, 2)
+    with pytest.raises(ce.CoexecError) as ei:  # 256 steps do not fit one workgroup
+        eng.program_kernel(ce.CE_KERNEL_BINOMIAL, ce.ce_binomial_params(10, 256, 100.0, 0.5, 0.49))
+    assert ei.value.status == ce.CE_E_INVALID
+    eng.program_kernel(ce.CE_KERNEL_BINOMIAL, ce.ce_binomial_params(10, 254, 100.0, 0.5, 0.49))
+    with pytest.raises(ce.CoexecError) as ei:
+        eng.program_out_pattern(1, 1)
+    assert ei.value.status == ce.CE_E_UNSUPPORTED
+    eng.program_out_pattern(1, 255)
+    spots, fac = np.zeros((10, 4), np.float32), np.zeros(255, np.float32)
+    eng.program_in(0, host=spots)
+    eng.program_in(1, host=fac)
+    eng.program_out(0, host=np.zeros((10, 4), np.float32))
+    eng.scheduler(ce.CE_SCHED_DYNAMIC, package_granules=2)
+    eng.work_items([2550], [256])  # the work-group must be steps + 1 items
+    with pytest.raises(ce.CoexecError) as ei:
+        eng.run()
+    assert ei.value.status == ce.CE_E_INVALID
+    eng.work_items([2550], [255])
+    simlib.sim_reset(10)
+    eng.run()
+    eng.close()

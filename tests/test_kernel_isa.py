@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1805_02755_amd", "csrc")
 HIPCC = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
 # source file -> (persistent kernel name fragment, number of instantiations)
-SOURCES = {"kernels.hip": ("k_persistent", 6), "batch_kernels.hip": ("k_batch_escape", 5),
+SOURCES = {"kernels.hip": ("k_persistent", 7), "batch_kernels.hip": ("k_batch_escape", 5),
            "serve_kernels.hip": ("k_serve", 1)}
 
 
