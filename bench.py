@@ -70,7 +70,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["blur", "escape", "nbody", "nbody-step", "batch", "serve", "copy"],
+    ap.add_argument("--workload", choices=["blur", "escape", "nbody", "nbody-step", "binomial", "batch", "serve",
+                                           "copy"],
                     default="blur")
     ap.add_argument("--serve-jobs", type=int, default=2000)
     ap.add_argument("--trace-out", default=None, help="write the last co-executed run's package trace (JSON) here")
@@ -159,6 +160,8 @@ def main():
         return bench_copy(args, torch, stream)
     if args.workload == "nbody-step":
         return bench_nbody_step(args, ce, synth, torch, np, stream)
+    if args.workload == "binomial":
+        return bench_binomial(args, ce, synth, torch, np, stream)
 
     eng = ce.Engine()
     eng.stream(stream.cuda_stream)
@@ -553,6 +556,135 @@ def bench_nbody_step(args, ce, synth, torch, np, stream):
             "t_bare_ms": T_bare * 1e3, "t_bare_kernel_ms": k_bare_ms, "t_engine_gpu_ms": T_gpu * 1e3,
             "t_engine_host_ms": T_host * 1e3, "t_coexec_ms_median": med(per_run) * 1e3,
             "host_threads": host_threads_used, "gpu_share": gpu_share,
+            "packages_gpu": med([s_.packages[0] for s_ in stats]), "packages_host": med([s_.packages[1] for s_ in stats]),
+            "t_device_ms": [med([s_.t_device[0] for s_ in stats]) * 1e3, med([s_.t_device[1] for s_ in stats]) * 1e3],
+        },
+    }
+    print(json.dumps(res), flush=True)
+    eng.close()
+
+
+def bench_binomial(args, ce, synth, torch, np, stream):
+    """Binomial option pricing at the paper's listing size: 16,777,216 calls
+    (4,194,304 work-groups of 255 work-items, 254 steps), spots uniform in
+    [50, 150), strike 100, sigma 0.3, rate 0.05, T 1; HGuided over GPU + every
+    host core, inputs resident in HBM with host mirrors, output in HBM. The
+    host alone is timed on 16,384 groups and scaled to the full size (a full
+    host-only run would take tens of seconds)."""
+    K, W = args.steps, args.warmup
+    n_groups, steps = 4194304, 254
+    dev = torch.device("cuda:0")
+    spots = synth.binomial_spots(n_groups)
+    f, pu, pd = ce.ce_binomial_table(steps, 0.3, 0.05, 1.0)
+    params = ce.ce_binomial_params(n_groups, steps, 100.0, pu, pd)
+    kid = ce.CE_KERNEL_BINOMIAL
+    s_d, f_d = torch.from_numpy(spots).to(dev), torch.from_numpy(f).to(dev)
+    out_d = torch.empty((n_groups, 4), device=dev)
+    sync = torch.cuda.synchronize
+    sync()
+    items = (steps + 1) * n_groups
+    hev = HipEvents()
+    ev_s = [hev.create() for _ in range(K)]
+    ev_e = [hev.create() for _ in range(K)]
+    log("bare launch")
+    def bare():
+        ce.ce_bare_run(kid, params, [s_d, f_d], out_d, stream=stream.cuda_stream, sync=True)
+    t_bare = timed_runs(bare, W, K, sync)
+    for i in range(K):
+        hev.record(ev_s[i], stream.cuda_stream)
+        ce.ce_bare_run(kid, params, [s_d, f_d], out_d, stream=stream.cuda_stream, sync=False)
+        hev.record(ev_e[i], stream.cuda_stream)
+    sync()
+    k_bare_ms = med([hev.elapsed_ms(ev_s[i], ev_e[i]) for i in range(K)])
+
+    def engine_for(ng, sp, sd, od):
+        e = ce.Engine()
+        e.stream(stream.cuda_stream)
+        e.work_items([(steps + 1) * ng], [steps + 1])
+        e.program_kernel(kid, ce.ce_binomial_params(ng, steps, 100.0, pu, pd))
+        e.program_out_pattern(1, steps + 1)
+        e.program_in(0, host=sp, dev=sd, nbytes=sp.nbytes)
+        e.program_in(1, host=f, dev=f_d, nbytes=f.nbytes)
+        e.program_out(0, dev=od, nbytes=od.numel() * 4)
+        return e
+
+    eng = engine_for(n_groups, spots, s_d, out_d)
+    log("engine GPU only")
+    eng.use(ce.CE_DEV_GPU, 0, 0)
+    eng.scheduler(ce.CE_SCHED_STATIC)
+    t_gpu = timed_runs(eng.run, W, K, sync)
+    log("engine host only (16,384 groups, scaled)")
+    sub = 16384
+    small = engine_for(sub, spots[:sub].copy(), s_d[:sub], torch.empty((sub, 4), device=dev))
+    small.use(ce.CE_DEV_HOST, 0, args.host_threads)
+    small.scheduler(ce.CE_SCHED_STATIC)
+    t_host_small = timed_runs(small.run, 1, 2, sync)
+    host_threads_used = small.stats().host_threads
+    small.close()
+    T_bare, T_gpu = med(t_bare), med(t_gpu)
+    T_host = med(t_host_small) * n_groups / sub
+    log("co-execution")
+    power = [max(1, min(1 << 20, int(round(T_host / T_gpu)))), 1]
+    eng.use(ce.CE_DEV_GPU | ce.CE_DEV_HOST, 0, args.host_threads)
+    eng.scheduler(ce.CE_SCHED_HGUIDED, power=power, k=2)
+    for _ in range(W):
+        eng.run()
+    per_run = []
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        a = time.perf_counter()
+        eng.run()
+        per_run.append(time.perf_counter() - a)
+    sync()
+    T_total = time.perf_counter() - t0
+    stats = []
+    for i in range(K):
+        eng.kernel_events(ev_s[i], ev_e[i])
+        eng.run()
+        stats.append(eng.stats())
+    eng.kernel_events(None, None)
+    kern_ms = [hev.elapsed_ms(ev_s[i], ev_e[i]) for i in range(K)]
+    for ev in ev_s + ev_e:
+        hev.destroy(ev)
+    s_real = T_bare / med(per_run)
+    s_max = min(T_bare, T_host) * (1.0 / T_bare + 1.0 / T_host)
+    gpu_share = sum(s_.items[0] for s_ in stats) / (K * items)
+    # per call: 255 leaves (mul, sub, max) and steps*(steps+1)/2 node updates (two muls and an add)
+    ops = 4.0 * n_groups * (3.0 * (steps + 1) + 3.0 * steps * (steps + 1) / 2) * gpu_share
+    achieved = ops / (med(kern_ms) * 1e-3) / 1e12
+    cpu_base = None
+    if not args.no_cpu_baseline:
+        log("oracle CPU baseline")
+        from oracle import oracle as O
+        t0c = time.perf_counter()
+        k = 0
+        flat = spots.reshape(-1)
+        while time.perf_counter() - t0c < 10.0:
+            O.binomial_price(float(flat[k]), 100.0, steps, f, pu, pd)
+            k += 1
+        dtc = time.perf_counter() - t0c
+        cpu_base = {"value": k * (steps + 1) / 4 / dtc, "unit": "work-items/s", "cores": 1, "kind": "oracle",
+                    "sample": f"{k} calls priced ({k / dtc:.0f} calls/s; 255 work-items per four calls)",
+                    "seconds": dtc}
+    res = {
+        "metric": METRIC, "value": items * K / T_total, "unit": "work-items/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": T_total / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded SplitMix64 inputs; see DESIGN.md)",
+        "config": {"workload": "binomial options: 16777216 European calls, 254 steps, 4194304 work-groups of 255, "
+                               "out pattern 1:255", "scheduler": "hguided", "devices": "gpu+host",
+                   "residency": "device", "options_per_s": 4 * n_groups * K / T_total},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "TOP/s (FP32 VALU lane-ops)", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "k_persistent<BinomialTile>", "kernel_ms": med(kern_ms)},
+        "cpu_baseline": cpu_base,
+        "coexec": {
+            "plain_gpu_items_per_s": items / T_bare, "vs_plain_gpu": s_real, "s_real": s_real, "s_max": s_max,
+            "efficiency": s_real / s_max, "balance": med([s_.balance for s_ in stats]),
+            "overhead_pct_gpu_only": (T_gpu - T_bare) / T_bare * 100.0,
+            "t_bare_ms": T_bare * 1e3, "t_bare_kernel_ms": k_bare_ms, "t_engine_gpu_ms": T_gpu * 1e3,
+            "t_engine_host_ms_scaled": T_host * 1e3, "t_coexec_ms_median": med(per_run) * 1e3,
+            "host_threads": host_threads_used, "gpu_share": gpu_share, "scheduler": {"power": power, "k": 2},
             "packages_gpu": med([s_.packages[0] for s_ in stats]), "packages_host": med([s_.packages[1] for s_ in stats]),
             "t_device_ms": [med([s_.t_device[0] for s_ in stats]) * 1e3, med([s_.t_device[1] for s_ in stats]) * 1e3],
         },
