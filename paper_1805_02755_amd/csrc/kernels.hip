@@ -211,9 +211,13 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
     }
     // Only two tickets may claim: the one `lookahead` before the end of the
     // published tiles and the first one past it. Each belongs to exactly one
-    // workgroup, so the lock is never stormed.
+    // workgroup, so the lock is never stormed. A workgroup that has waited
+    // long may also try, now and then: the designated ones may belong to
+    // workgroups that are not resident yet (a grid the occupancy query
+    // overestimated), and the wait must still end.
     uint32_t unlocked = 0;
-    if ((t + s.lookahead == tot || t == tot) &&
+    const bool overdue = spins > 4096 && (spins & 1023) == 0;
+    if ((t + s.lookahead == tot || t == tot || overdue) &&
         __hip_atomic_compare_exchange_strong(&q->lock, &unlocked, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT)) {
       // Everything the claimer reads or writes under the lock is an
