@@ -329,11 +329,18 @@ struct NbodyStepTile {
 };
 
 // Binomial option pricing: a granule is one work-group pricing four calls
-// (one float4 of spots). Thread j holds leaf j of all four trees; each level
-// of the backward induction reads the neighbour's value through LDS between
-// two barriers that every thread of the workgroup passes.
+// (one float4 of spots). Thread j holds leaf j of all four trees. At each
+// level of the backward induction a node needs its upper neighbour, held by
+// the next lane: inside a wave it arrives by a DPP wave shift, and only the
+// first lane of each wave goes through LDS, to the last lane of the wave
+// below, after one barrier per level. Waves whose nodes all lie above the
+// level skip the arithmetic; inside a working wave every lane computes, and
+// lanes above the level produce values that no later level reads. The loop
+// is bound by barrier latency and issue, so the persistent kernel is asked
+// for eight resident workgroups per CU, as many as a plain launch reaches.
 struct BinomialTile {
-  static constexpr int kMinBlocksPerCu = 1;
+  static constexpr int kMinBlocksPerCu = 8;
+  static constexpr uint32_t kWaves = kBlockThreads / 64;
   ce_binomial_params p;
   const float4* spots;
   const float* factors;
@@ -341,10 +348,18 @@ struct BinomialTile {
   __device__ void load_constants() {}
   __host__ __device__ uint64_t granules() const { return p.n_groups; }
   __host__ __device__ uint32_t ntiles(uint64_t g0, uint64_t g1) const { return (uint32_t)(g1 - g0); }
+  // Lane i receives lane i + 1's value (DPP wave_shl:1); the last lane,
+  // which has no source, keeps `top`.
+  static __device__ float from_next_lane(float x, float top) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(top), __float_as_int(x), 0x130, 0xf, 0xf, false));
+  }
   __device__ void run(uint64_t g0, uint64_t, uint32_t t) const {
-    __shared__ float4 sh[kBlockThreads];
+    // edge[L & 1][w] holds the level-L value of the first lane of wave w;
+    // slot kWaves is never written and feeds only the unused last leaf.
+    __shared__ float4 edge[2][kWaves + 1];
     const uint64_t grp = g0 + t;
     const uint32_t j = threadIdx.x;
+    const uint32_t w = __builtin_amdgcn_readfirstlane(j >> 6);
     const uint32_t n = p.steps;
     const float4 S = spots[grp];
     const float X = p.strike, pu = p.pu, pd = p.pd;
@@ -354,16 +369,20 @@ struct BinomialTile {
       const float a = S.x * f - X, b = S.y * f - X, c = S.z * f - X, d = S.w * f - X;
       v = make_float4(a > 0.0f ? a : 0.0f, b > 0.0f ? b : 0.0f, c > 0.0f ? c : 0.0f, d > 0.0f ? d : 0.0f);
     }
+    // Level L's copy of edge is rewritten at level L - 2, after the barrier of
+    // level L - 1 that follows every read of it, so one barrier per level suffices.
     for (uint32_t L = n; L-- > 0;) {
+      float4* e = edge[L & 1];
+      if ((j & 63) == 0) e[w] = v;
       __syncthreads();
-      sh[j] = v;
-      __syncthreads();
-      if (j <= L) {
-        const float4 up = sh[j + 1];
-        v.x = pu * up.x + pd * v.x;
-        v.y = pu * up.y + pd * v.y;
-        v.z = pu * up.z + pd * v.z;
-        v.w = pu * up.w + pd * v.w;
+      if (w * 64 <= L) {
+        const float4 top = e[w + 1];
+        const float ux = from_next_lane(v.x, top.x), uy = from_next_lane(v.y, top.y);
+        const float uz = from_next_lane(v.z, top.z), uw = from_next_lane(v.w, top.w);
+        v.x = pu * ux + pd * v.x;
+        v.y = pu * uy + pd * v.y;
+        v.z = pu * uz + pd * v.z;
+        v.w = pu * uw + pd * v.w;
       }
     }
     if (j == 0) out[grp] = v;

@@ -890,8 +890,15 @@ struct ce_engine {
       // blur and n-body tiles all cost the same: a fixed round-robin needs no
       // atomics; escape-time tiles vary a lot, so they are dealt dynamically
       // (with gatherers sharing some CUs the fixed round-robin would leave the
-      // workgroups on those CUs behind, so tiles are dealt dynamically then)
-      gs.stride = (kernel_id == CE_KERNEL_ESCAPE || gather) ? 0u : 1u;
+      // workgroups on those CUs behind, so tiles are dealt dynamically then).
+      // A binomial tile runs for tens of microseconds, so one atomic per tile
+      // costs nothing, and dealing them one at a time keeps the GPU balanced
+      // even when part of the grid becomes resident only as the rest leaves:
+      // under the round-robin those late workgroups would still own a full
+      // share of tickets and run them on an otherwise idle GPU.
+      const bool long_tiles = kernel_id == CE_KERNEL_BINOMIAL;
+      if (long_tiles) gs.chunk = 1;
+      gs.stride = (kernel_id == CE_KERNEL_ESCAPE || gather || long_tiles) ? 0u : 1u;
       gs.wait_ticks = (uint64_t)wallclock_hz * 60;
       if (gather) {
         const uint64_t max_host_tiles =

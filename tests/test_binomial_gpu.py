@@ -46,7 +46,7 @@ def test_binomial_bitexact_every_schedule(eng, mode):
             check_trace(tr, 600, st.n_devices)
 
 
-@pytest.mark.parametrize("steps", [1, 2, 63, 64, 65, 200, 255])
+@pytest.mark.parametrize("steps", [1, 2, 3, 63, 64, 65, 127, 128, 129, 191, 192, 193, 200, 254, 255])
 def test_binomial_tree_depths(eng, steps):
     spots, f, prm, ref = setup(97, steps, steps)
     out, st, tr = run_payload(eng, ce.CE_KERNEL_BINOMIAL, prm, [(steps + 1) * 97], [steps + 1], [spots, f], (97, 4),
