@@ -40,7 +40,8 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 DEVICE_SOURCES = ("paper_1805_02755_amd/csrc/kernels.hip", "paper_1805_02755_amd/csrc/device_tiles.hpp",
                   "paper_1805_02755_amd/csrc/device_atomics.hpp", "paper_1805_02755_amd/csrc/device_payloads.hpp",
-                  "paper_1805_02755_amd/csrc/common.hpp")
+                  "paper_1805_02755_amd/csrc/common.hpp", "paper_1805_02755_amd/csrc/sched_device.hpp",
+                  "paper_1805_02755_amd/csrc/rt_tile.hpp")
 
 
 def measured_traffic(name):
@@ -70,7 +71,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["blur", "escape", "nbody", "nbody-step", "binomial", "batch", "serve",
+    ap.add_argument("--workload", choices=["blur", "escape", "runtime", "nbody", "nbody-step", "binomial", "batch", "serve",
                                            "copy"],
                     default="blur")
     ap.add_argument("--serve-jobs", type=int, default=2000)
@@ -190,7 +191,7 @@ def main():
         config = {"workload": "blur5x5 8192x8192 fp32, sigma 1, clamp-to-edge", "scheduler": "hguided",
                   "devices": "gpu+host", "residency": args.mode, "output_merge": args.merge}
         bound = "hbm"
-    elif wl == "escape":
+    elif wl in ("escape", "runtime"):
         p = synth.escape_small()
         params = ce.ce_escape_params(p.w, p.h, *p.as_f32(), p.max_iter)
         kid = ce.CE_KERNEL_ESCAPE
@@ -205,6 +206,19 @@ def main():
         config = {"workload": "escape-time 1024x1024 over [-2,1]x[-1.5,1.5], max_iter 256", "scheduler": "static x8",
                   "devices": "gpu+1 host thread", "residency": args.mode}
         bound = "alu"
+        if wl == "runtime":
+            if args.mode != "device":
+                raise SystemExit("--workload runtime runs with device residency only")
+            from paper_1805_02755_amd import rt_examples
+            config["workload"] += ", supplied as HIP source at run time (hipRTC) with a C host version"
+            # The plain C host version needs about 0.16 ms per 1024-pixel row,
+            # more than the GPU's whole run: 64-pixel granules and HGuided let
+            # the host take only what it finishes in time.
+            rt_lws = 64
+            G = n_items // rt_lws
+            host_threads = args.host_threads
+            coexec = dict(kind=ce.CE_SCHED_HGUIDED, k=2)
+            config.update({"scheduler": "hguided", "devices": "gpu+host", "granule": "64 pixels"})
     else:
         n = 65536
         bodies = synth.nbody_bodies(n)
@@ -225,7 +239,15 @@ def main():
     sync()
 
     eng.work_items(gws, lws)
-    eng.program_kernel(kid, params)
+    if wl == "runtime":
+        eng.work_items([n_items], [rt_lws])
+        t_c = time.perf_counter()
+        eng.program_source(rt_examples.source("escape.hiprtc"), "escape_item",
+                           host=rt_examples.host_fn("escape_host"), n_in=0, n_out=1, out_item_bytes=4,
+                           scalars=rt_examples.escape_scalars(p.w, *p.as_f32(), p.max_iter))
+        config["compile_s"] = time.perf_counter() - t_c
+    else:
+        eng.program_kernel(kid, params)
     for slot in range(len(ins_host)):
         if args.mode == "host":
             eng.program_in(slot, host=ins_host[slot])
@@ -240,6 +262,13 @@ def main():
 
     # ---------------------------------------------- plain single-GPU launch
     log("bare launch")
+    def bare_launch(do_sync):
+        if wl == "runtime":
+            eng.bare_run_source(n_items, rt_lws, [], [out_d], stream=stream.cuda_stream, sync=do_sync)
+        else:
+            ce.ce_bare_run(kid, params, ins_dev if args.mode != "host" else ins_dev_b, out_d,
+                           stream=stream.cuda_stream, sync=do_sync)
+
     def bare():
         if args.mode == "host":
             for i, a in enumerate(ins_host):
@@ -247,7 +276,7 @@ def main():
             ce.ce_bare_run(kid, params, ins_dev_b, out_d, stream=stream.cuda_stream, sync=True)
             out_h_b[...] = out_d.cpu().numpy().view(out_h_b.dtype).reshape(out_h_b.shape)
         else:
-            ce.ce_bare_run(kid, params, ins_dev, out_d, stream=stream.cuda_stream, sync=True)
+            bare_launch(True)
     if args.mode == "host":
         ins_dev_b = [torch.empty(a.shape, dtype=torch.from_numpy(a).dtype, device=dev) for a in ins_host]
         out_h_b = np.empty_like(out_h)
@@ -258,8 +287,7 @@ def main():
     # kernel time of the plain launch, from events on its stream
     for i in range(K):
         hev.record(ev_s[i], stream.cuda_stream)
-        ce.ce_bare_run(kid, params, ins_dev if args.mode != "host" else ins_dev_b, out_d, stream=stream.cuda_stream,
-                       sync=False)
+        bare_launch(False)
         hev.record(ev_e[i], stream.cuda_stream)
     sync()
     k_bare_ms = med([hev.elapsed_ms(ev_s[i], ev_e[i]) for i in range(K)])
@@ -344,13 +372,14 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes per launch",
                 "kernel": "k_persistent<Blur5Tile>", "kernel_ms": med(kern_ms),
                 "algorithmic_bytes_per_item": bytes_per_item}
-    elif wl == "escape":
+    elif wl in ("escape", "runtime"):
         cnt = out_d.cpu().numpy().view(np.uint32).astype(np.int64)
         iters = int(cnt.sum())
         ops = 8.0 * iters * (sum(gpu_items) / (K * n_items))
         achieved = ops / (med(kern_ms) * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (FP32 VALU lane-ops)",
-                "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "k_persistent<EscapeTile>",
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                "kernel": "k_persistent<RtTile> (hipRTC)" if wl == "runtime" else "k_persistent<EscapeTile>",
                 "kernel_ms": med(kern_ms), "iterations": iters}
     else:
         n = n_items
@@ -375,7 +404,7 @@ def main():
                 passes += 1
                 done_items += n_items
             sample = f"{passes} full passes over the 8192x8192 image"
-        elif wl == "escape":
+        elif wl in ("escape", "runtime"):
             passes = 0
             while passes < 40 and (time.perf_counter() - t0 < 10.0):
                 O.escape(p.w, p.h, *[float(v) for v in p.as_f32()], p.max_iter)
@@ -404,7 +433,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32" if wl == "escape" else "f32",
+        "dtype": "u32" if wl in ("escape", "runtime") else "f32",
         "data": "synthetic (seeded SplitMix64 inputs; see DESIGN.md)",
         "config": config,
         "roofline": roof,

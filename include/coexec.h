@@ -56,6 +56,7 @@ typedef int32_t ce_status;
 #define CE_KERNEL_NBODY_STEP 4 /* N-body integration step, 1-D, 2 in (pos, vel) : 2 out (pos, vel) */
 #define CE_KERNEL_BINOMIAL 5    /* binomial option pricing, 1-D, 2 in (spots, leaf factors) : 1 out,
                                    out pattern 1 : steps+1                                         */
+#define CE_KERNEL_RUNTIME 6     /* a payload given as HIP source at run time (ce_program_source), 1-D */
 
 /* Schedulers (section 5.3). */
 #define CE_SCHED_STATIC 0
@@ -224,6 +225,58 @@ ce_status ce_program_out(ce_engine* e, uint32_t slot, void* host_ptr, void* dev_
  * writes `outs` output elements. The payloads here write one element per
  * work-item, so only 1:1 is accepted (others: CE_E_UNSUPPORTED). */
 ce_status ce_program_out_pattern(ce_engine* e, uint32_t outs, uint32_t items);
+
+/* ---- payloads supplied at run time (section 3: each device may need its own
+ * kernel, given as source or binary; section 6.2: a device is declared with
+ * its own kernel). The GPU's version is HIP C++ source compiled with hipRTC
+ * for gfx950 when it is programmed; the host workers' version is a C
+ * function. The two are separate implementations of one work-item function
+ * and must agree bit for bit where the caller needs identical results.
+ *
+ * Arguments (the generic form of a kernel's argument list): every work-item
+ * receives the buffers of the bound slots, inputs first (buf[0..n_in)), then
+ * outputs (buf[n_in..n_in+n_out)), as device pointers on the GPU and host
+ * pointers on the host, and a block of scalar bytes copied at programming
+ * time. Work-item i (0 <= i < gws) writes out_item_bytes bytes at byte
+ * offset i * out_item_bytes of each output (output pattern 1:1); it may read
+ * any part of the inputs. The index space is 1-D; a granule is lws work-items. */
+#define CE_RT_MAX_BUFS 4
+#define CE_RT_SCALAR_BYTES 128
+typedef struct {
+  void* buf[CE_RT_MAX_BUFS];
+  unsigned char scalars[CE_RT_SCALAR_BYTES];
+} ce_rt_args;
+/* Host version: computes work-items [i0, i1). */
+typedef void (*ce_rt_host_fn)(uint64_t i0, uint64_t i1, const ce_rt_args* a);
+typedef struct {
+  const char* source;         /* HIP C++ source; must define `entry` as
+                               *   __device__ void entry(uint64_t i, const ce_rt_args* a)
+                               * (ce_rt_args and <stdint.h> are already declared) */
+  const char* entry;          /* name of that function (a C identifier)           */
+  ce_rt_host_fn host;         /* host workers' version; NULL: GPU only            */
+  uint32_t n_in, n_out;       /* 0..2 inputs, 1..2 outputs                        */
+  uint64_t in_bytes[2];       /* size of each input buffer                        */
+  uint32_t out_item_bytes;    /* bytes per work-item in every output (1..256)     */
+  uint32_t scalar_bytes;      /* 0..CE_RT_SCALAR_BYTES                            */
+  const void* scalars;        /* copied                                           */
+} ce_rt_desc;
+/* Compiles desc->source for gfx950 and binds the result as the engine's
+ * payload (kernel id CE_KERNEL_RUNTIME), replacing any bound payload and
+ * unbinding the slots. On a compile error returns CE_E_INVALID and writes
+ * the compiler's log (NUL-terminated, truncated) into log[0..log_len) if
+ * log is not NULL; the previous payload is then unbound too. Slots are then
+ * bound with ce_program_in / ce_program_out as for the fixed payloads
+ * (input sizes in_bytes, output sizes gws * out_item_bytes). A run whose
+ * device set includes the host needs desc->host. */
+ce_status ce_program_source(ce_engine* e, const ce_rt_desc* desc, char* log, size_t log_len);
+/* Compiles a runtime payload's source without binding it (no GPU needed):
+ * CE_OK, or CE_E_INVALID with the compiler's log as above. */
+ce_status ce_rt_compile_check(const char* source, const char* entry, char* log, size_t log_len);
+/* Plain single launch of the engine's bound runtime payload over gws
+ * work-items of granule lws (the "native" side of the overhead metric):
+ * device pointers, ins[] / outs[] follow its slots, on `hip_stream`. */
+ce_status ce_engine_bare_run_source(ce_engine* e, uint64_t gws, uint32_t lws, const void* const* ins,
+                                    void* const* outs, void* hip_stream, int sync);
 
 /* How the host's share of a device-resident output (output bound only as a
  * device pointer, host in the device set) reaches HBM during the run

@@ -38,6 +38,9 @@ CE_KERNEL_BLUR5 = 2
 CE_KERNEL_NBODY_ACC = 3
 CE_KERNEL_NBODY_STEP = 4
 CE_KERNEL_BINOMIAL = 5
+CE_KERNEL_RUNTIME = 6
+CE_RT_MAX_BUFS = 4
+CE_RT_SCALAR_BYTES = 128
 
 CE_SCHED_STATIC = 0
 CE_SCHED_DYNAMIC = 1
@@ -57,7 +60,8 @@ EXPORTED_SYMBOLS = (
     "ce_batch_clear", "ce_batch_set_config", "ce_batch_get_config", "ce_batch_tune", "ce_batch_run",
     "ce_batch_run_separate", "ce_batch_stats", "ce_batch_error", "ce_server_create", "ce_server_destroy",
     "ce_server_submit", "ce_server_poll", "ce_server_wait", "ce_server_output", "ce_server_copy_output",
-    "ce_server_release", "ce_server_drain", "ce_server_stats", "ce_server_error",
+    "ce_server_release", "ce_server_drain", "ce_server_stats", "ce_server_error", "ce_program_source",
+    "ce_rt_compile_check", "ce_engine_bare_run_source",
 )
 
 CE_JOB_QUEUED = 0
@@ -86,6 +90,20 @@ class ce_nbody_step_params(C.Structure):
 class ce_binomial_params(C.Structure):
     _fields_ = [("n_groups", C.c_uint32), ("steps", C.c_uint32), ("strike", C.c_float), ("pu", C.c_float),
                 ("pd", C.c_float)]
+
+
+class ce_rt_args(C.Structure):
+    _fields_ = [("buf", C.c_void_p * CE_RT_MAX_BUFS), ("scalars", C.c_ubyte * CE_RT_SCALAR_BYTES)]
+
+
+# host version of a runtime payload: (i0, i1, const ce_rt_args*)
+CE_RT_HOST_FN = C.CFUNCTYPE(None, C.c_uint64, C.c_uint64, C.POINTER(ce_rt_args))
+
+
+class ce_rt_desc(C.Structure):
+    _fields_ = [("source", C.c_char_p), ("entry", C.c_char_p), ("host", C.c_void_p), ("n_in", C.c_uint32),
+                ("n_out", C.c_uint32), ("in_bytes", C.c_uint64 * 2), ("out_item_bytes", C.c_uint32),
+                ("scalar_bytes", C.c_uint32), ("scalars", C.c_void_p)]
 
 
 class ce_sched_desc(C.Structure):
@@ -178,6 +196,9 @@ def load(path: str):
         "ce_engine_clear_errors": (None, [vp]),
         "ce_bare_run": (i32, [C.c_int, vp, sz, C.POINTER(vp), vp, vp, C.c_int]),
         "ce_bare_run_outs": (i32, [C.c_int, vp, sz, C.POINTER(vp), C.POINTER(vp), C.c_uint32, vp, C.c_int]),
+        "ce_program_source": (i32, [vp, C.POINTER(ce_rt_desc), C.c_char_p, sz]),
+        "ce_rt_compile_check": (i32, [C.c_char_p, C.c_char_p, C.c_char_p, sz]),
+        "ce_engine_bare_run_source": (i32, [vp, u64, u32, C.POINTER(vp), C.POINTER(vp), vp, C.c_int]),
         "ce_sched_static_plan": (i32, [u64, u32, C.POINTER(C.c_double), C.POINTER(u32), u32, C.POINTER(u64),
                                        C.POINTER(u64)]),
         "ce_sched_hguided_size": (u64, [u64, C.POINTER(u64), u32, u32, u32, u64]),
@@ -317,6 +338,14 @@ def ce_bare_run_outs(kernel_id: int, params, ins, outs, stream=None, sync: bool 
         raise CoexecError(st, "ce_bare_run_outs")
 
 
+def ce_rt_compile_check(source: str, entry: str):
+    """Compiles a runtime payload's source for gfx950 (no GPU needed).
+    Returns (status, compiler log)."""
+    buf = C.create_string_buffer(1 << 16)
+    st = lib().ce_rt_compile_check(source.encode(), entry.encode(), buf, len(buf))
+    return st, buf.value.decode(errors="replace")
+
+
 def stream_handle(stream) -> Optional[int]:
     """hipStream_t of a torch.cuda.Stream (or None)."""
     if stream is None:
@@ -415,6 +444,42 @@ class Engine:
 
     def program_out_pattern(self, outs: int, items: int):
         return self._check(self._L.ce_program_out_pattern(self._h, outs, items), "ce_program_out_pattern")
+
+    def program_source(self, source: str, entry: str, host=None, n_in: int = 0, n_out: int = 1, in_bytes=(),
+                       out_item_bytes: int = 4, scalars: bytes = b""):
+        """Binds a payload given as HIP source (compiled for gfx950 now) and,
+        for the host workers, `host`: a CE_RT_HOST_FN or a raw C function
+        address. Returns the compiler's log; raises CoexecError on failure."""
+        d = ce_rt_desc()
+        src, ent = source.encode(), entry.encode()
+        d.source, d.entry = src, ent
+        if host is None:
+            d.host = None
+        elif isinstance(host, int):
+            d.host = host
+        else:
+            d.host = C.cast(host, C.c_void_p).value
+        d.n_in, d.n_out = n_in, n_out
+        for k, b in enumerate(in_bytes):
+            d.in_bytes[k] = b
+        d.out_item_bytes = out_item_bytes
+        sc = C.create_string_buffer(bytes(scalars), max(1, len(scalars)))
+        d.scalar_bytes, d.scalars = len(scalars), C.cast(sc, C.c_void_p).value if scalars else None
+        self._keep += [src, ent, host, sc]
+        log = C.create_string_buffer(1 << 16)
+        st = self._L.ce_program_source(self._h, C.byref(d), log, len(log))
+        text = log.value.decode(errors="replace")
+        if st != CE_OK:
+            raise CoexecError(st, "ce_program_source", self.errors()[-3:] + ([text] if text else []))
+        return text
+
+    def bare_run_source(self, gws: int, lws: int, ins, outs, stream=None, sync: bool = True):
+        """Plain single launch of the bound runtime payload (device pointers)."""
+        arr = (C.c_void_p * max(1, len(ins)))(*[_ptr(x) for x in ins]) if ins else None
+        oarr = (C.c_void_p * len(outs))(*[_ptr(x) for x in outs])
+        return self._check(self._L.ce_engine_bare_run_source(self._h, gws, lws, arr, oarr,
+                                                             _ptr(stream) if stream is not None else None,
+                                                             int(sync)), "ce_engine_bare_run_source")
 
     def run(self):
         return self._check(self._L.ce_engine_run(self._h), "ce_engine_run")

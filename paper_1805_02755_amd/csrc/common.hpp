@@ -4,7 +4,7 @@
 
 #include <stdint.h>
 
-#if defined(__HIPCC__)
+#if defined(__HIPCC__) || defined(__HIPCC_RTC__)
 #define CE_HD __host__ __device__ inline
 #else
 #define CE_HD inline

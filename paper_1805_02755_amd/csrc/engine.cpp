@@ -205,6 +205,16 @@ struct ce_engine {
   int64_t t0_ns = 0;
   const void* host_in0 = nullptr;
   const void* host_in1 = nullptr;
+  // payload supplied as source at run time: its loaded module, its host
+  // version, its slots and scalars, and the host workers' arguments
+  void* rt_module = nullptr;
+  void* rt_fn_persistent = nullptr;
+  void* rt_fn_bare = nullptr;
+  ce_rt_host_fn rt_host = nullptr;
+  uint32_t rt_n_in = 0, rt_n_out = 0, rt_item_bytes = 0;
+  uint64_t rt_in_bytes[2] = {0, 0};
+  unsigned char rt_scalars[CE_RT_SCALAR_BYTES] = {};
+  ce_rt_args rt_host_args{};
   void* host_out = nullptr;    // output slot 0 as the host workers write it
   void* host_out1 = nullptr;   // output slot 1 (n-body step velocities)
   std::atomic<int> host_error{0};
@@ -250,9 +260,12 @@ struct ce_engine {
       case CE_KERNEL_NBODY_ACC: return ceil_div(nb.n, kNbodyGranule);
       case CE_KERNEL_NBODY_STEP: return ceil_div(nbs.n, kNbodyGranule);
       case CE_KERNEL_BINOMIAL: return bin.n_groups;
+      case CE_KERNEL_RUNTIME: return lws0 ? ceil_div(gws[0], lws0) : 0;
     }
     return 0;
   }
+  // first work-item of granule g of a runtime payload
+  uint64_t rt_item(uint64_t g) const { return std::min<uint64_t>(g * lws0, gws[0]); }
   uint32_t n_bodies() const { return kernel_id == CE_KERNEL_NBODY_STEP ? nbs.n : nb.n; }
   bool is_nbody() const { return kernel_id == CE_KERNEL_NBODY_ACC || kernel_id == CE_KERNEL_NBODY_STEP; }
   uint64_t items_in(uint64_t g0, uint64_t g1) const {
@@ -265,14 +278,19 @@ struct ce_engine {
         return b > a ? b - a : 0;
       }
       case CE_KERNEL_BINOMIAL: return (g1 - g0) * (bin.steps + 1);  // one work-group per granule
+      case CE_KERNEL_RUNTIME: return rt_item(g1) - rt_item(g0);
     }
     return 0;
   }
   // output elements: one float4 per body, per option group, or one word per pixel
-  size_t out_elem_bytes() const { return (is_nbody() || kernel_id == CE_KERNEL_BINOMIAL) ? 16 : 4; }
+  size_t out_elem_bytes() const {
+    if (kernel_id == CE_KERNEL_RUNTIME) return rt_item_bytes;
+    return (is_nbody() || kernel_id == CE_KERNEL_BINOMIAL) ? 16 : 4;
+  }
   // first output element of granule g (out pattern 1:(steps+1) for binomial)
   uint64_t item_offset(uint64_t g) const {
     if (kernel_id == CE_KERNEL_BINOMIAL) return g;
+    if (kernel_id == CE_KERNEL_RUNTIME) return rt_item(g);
     return is_nbody() ? std::min<uint64_t>(g * kNbodyGranule, n_bodies()) : g * gws[0];
   }
   size_t in_bytes(int slot) const {
@@ -282,6 +300,7 @@ struct ce_engine {
       case CE_KERNEL_NBODY_ACC: return slot == 0 ? (size_t)nb.n * 16 : 0;
       case CE_KERNEL_NBODY_STEP: return slot < 2 ? (size_t)nbs.n * 16 : 0;
       case CE_KERNEL_BINOMIAL: return slot == 0 ? (size_t)bin.n_groups * 16 : (slot == 1 ? (size_t)(bin.steps + 1) * 4 : 0);
+      case CE_KERNEL_RUNTIME: return slot >= 0 && (uint32_t)slot < rt_n_in ? (size_t)rt_in_bytes[slot] : 0;
     }
     return 0;
   }
@@ -291,10 +310,14 @@ struct ce_engine {
       case CE_KERNEL_NBODY_ACC: return 1;
       case CE_KERNEL_NBODY_STEP: return 2;
       case CE_KERNEL_BINOMIAL: return 2;
+      case CE_KERNEL_RUNTIME: return (int)rt_n_in;
     }
     return 0;
   }
-  int n_out_slots() const { return kernel_id == CE_KERNEL_NBODY_STEP ? 2 : 1; }
+  int n_out_slots() const {
+    if (kernel_id == CE_KERNEL_RUNTIME) return (int)rt_n_out;
+    return kernel_id == CE_KERNEL_NBODY_STEP ? 2 : 1;
+  }
   size_t out_bytes() const {
     switch (kernel_id) {
       case CE_KERNEL_ESCAPE: return (size_t)esc.w * esc.h * 4;
@@ -302,6 +325,7 @@ struct ce_engine {
       case CE_KERNEL_NBODY_ACC: return (size_t)nb.n * 16;
       case CE_KERNEL_NBODY_STEP: return (size_t)nbs.n * 16;
       case CE_KERNEL_BINOMIAL: return (size_t)bin.n_groups * 16;
+      case CE_KERNEL_RUNTIME: return (size_t)gws[0] * rt_item_bytes;
     }
     return 0;
   }
@@ -454,6 +478,7 @@ struct ce_engine {
         binomial_groups((const float*)host_in0, (const float*)host_in1, bin.steps, bin.strike, bin.pu, bin.pd,
                         p.g0 + ti, p.g0 + ti + 1, (float*)host_out);
         break;
+      case CE_KERNEL_RUNTIME: rt_host(rt_item(p.g0 + ti), rt_item(p.g0 + ti + 1), &rt_host_args); break;
     }
   }
 
@@ -468,6 +493,9 @@ struct ce_engine {
     } else if (kernel_id == CE_KERNEL_BINOMIAL) {
       *off = (p.g0 + ti) * 16;
       *len = 16;
+    } else if (kernel_id == CE_KERNEL_RUNTIME) {
+      *off = rt_item(p.g0 + ti) * rt_item_bytes;
+      *len = (rt_item(p.g0 + ti + 1) - rt_item(p.g0 + ti)) * rt_item_bytes;
     } else {
       *off = (p.g0 + ti) * gws[0] * 4;
       *len = gws[0] * 4;
@@ -730,7 +758,7 @@ struct ce_engine {
     if (!sched_set) return fail(CE_E_STATE, "run: no scheduler set");
     if (ndim == 0) return fail(CE_E_STATE, "run: work_items not set");
     if (n_devices() == 0) return fail(CE_E_STATE, "run: empty device set");
-    if (use_host() && !hp) return fail(CE_E_UNSUPPORTED, "run: host CPU lacks AVX2/FMA");
+    if (use_host() && !hp && kernel_id != CE_KERNEL_RUNTIME) return fail(CE_E_UNSUPPORTED, "run: host CPU lacks AVX2/FMA");
     // index space must match the kernel
     if (is_nbody()) {
       if (ndim != 1 || gws[0] != n_bodies() || lws0 != kNbodyGranule)
@@ -738,6 +766,10 @@ struct ce_engine {
     } else if (kernel_id == CE_KERNEL_BINOMIAL) {
       if (ndim != 1 || lws0 != bin.steps + 1 || gws[0] != (uint64_t)(bin.steps + 1) * bin.n_groups)
         return fail(CE_E_INVALID, "run: binomial needs gws = (steps+1) * n_groups and lws = steps+1");
+    } else if (kernel_id == CE_KERNEL_RUNTIME) {
+      if (ndim != 1 || gws[0] == 0 || lws0 == 0) return fail(CE_E_INVALID, "run: a runtime payload needs a 1-D space");
+      if (use_host() && !rt_host) return fail(CE_E_UNSUPPORTED, "run: the runtime payload has no host version");
+      if (use_gpu() && !rt_fn_persistent) return fail(CE_E_STATE, "run: the runtime payload is not loaded");
     } else {
       const uint64_t w = kernel_id == CE_KERNEL_ESCAPE ? esc.w : blur.w;
       const uint64_t h = kernel_id == CE_KERNEL_ESCAPE ? esc.h : blur.h;
@@ -792,6 +824,17 @@ struct ce_engine {
     }
     kargs.out = gpu_out[0];
     kargs.out1 = gpu_out[1];
+    if (kernel_id == CE_KERNEL_RUNTIME) {
+      // generic arguments: inputs, then outputs, then the scalar block
+      for (uint32_t k = 0; k < rt_n_in; ++k) kargs.rt.buf[k] = const_cast<void*>(gin[k]);
+      for (uint32_t k = 0; k < rt_n_out; ++k) kargs.rt.buf[rt_n_in + k] = gpu_out[k];
+      memcpy(kargs.rt.scalars, rt_scalars, sizeof rt_scalars);
+      kargs.rt_items = gws[0];
+      kargs.rt_lws = lws0;
+      kargs.rt_item_bytes = rt_item_bytes;
+      kargs.rt_fn_persistent = rt_fn_persistent;
+      kargs.rt_fn_bare = rt_fn_bare;
+    }
 
     // host-side pointers
     host_in0 = host_in1 = nullptr;
@@ -822,6 +865,12 @@ struct ce_engine {
       }
       host_out = hout[0];
       host_out1 = hout[1];
+      if (kernel_id == CE_KERNEL_RUNTIME) {
+        rt_host_args = ce_rt_args{};
+        for (uint32_t k = 0; k < rt_n_in; ++k) rt_host_args.buf[k] = const_cast<void*>(hin[k]);
+        for (uint32_t k = 0; k < rt_n_out; ++k) rt_host_args.buf[rt_n_in + k] = hout[k];
+        memcpy(rt_host_args.scalars, rt_scalars, sizeof rt_scalars);
+      }
       bool downloaded = false;
       for (int s = 0; s < n_in_slots(); ++s) downloaded |= (in[s].host == nullptr);
       if (downloaded) {
@@ -896,9 +945,11 @@ struct ce_engine {
       // even when part of the grid becomes resident only as the rest leaves:
       // under the round-robin those late workgroups would still own a full
       // share of tickets and run them on an otherwise idle GPU.
+      // A payload supplied at run time has tiles of unknown cost: dealt
+      // dynamically too.
       const bool long_tiles = kernel_id == CE_KERNEL_BINOMIAL;
       if (long_tiles) gs.chunk = 1;
-      gs.stride = (kernel_id == CE_KERNEL_ESCAPE || gather || long_tiles) ? 0u : 1u;
+      gs.stride = (kernel_id == CE_KERNEL_ESCAPE || kernel_id == CE_KERNEL_RUNTIME || gather || long_tiles) ? 0u : 1u;
       gs.wait_ticks = (uint64_t)wallclock_hz * 60;
       if (gather) {
         const uint64_t max_host_tiles =
@@ -1224,6 +1275,7 @@ struct ce_engine {
   ~ce_engine() {
     pool_stop();
     if (stream) (void)hipStreamSynchronize(stream);
+    rt_release(rt_module);
     // SdmaCopier's destructor waits for copies still queued
     if (own_stream) (void)hipStreamDestroy(own_stream);
     if (l2) (void)hipFree(l2);
@@ -1406,6 +1458,90 @@ ce_status ce_program_out_pattern(ce_engine* e, uint32_t outs, uint32_t items) {
     return e->fail(CE_E_UNSUPPORTED, "out_pattern: this payload writes 1 output per %u work-items", want);
   e->pat_outs = outs;
   e->pat_items = items;
+  return CE_OK;
+}
+
+namespace {
+void copy_log(const std::string& text, char* log, size_t log_len) {
+  if (!log || log_len == 0) return;
+  const size_t n = std::min(text.size(), log_len - 1);
+  memcpy(log, text.data(), n);
+  log[n] = '\0';
+}
+}  // namespace
+
+ce_status ce_rt_compile_check(const char* source, const char* entry, char* log, size_t log_len) {
+  std::string code, lp, lb, text;
+  const int rc = rt_compile(source, entry, &code, &lp, &lb, &text);
+  copy_log(text, log, log_len);
+  return rc == 0 ? CE_OK : (rc == -1 ? CE_E_INVALID : CE_E_DEVICE);
+}
+
+ce_status ce_program_source(ce_engine* e, const ce_rt_desc* d, char* log, size_t log_len) {
+  if (!e) return CE_E_INVALID;
+  copy_log("", log, log_len);
+  if (!d || !d->source || !d->entry) return e->fail(CE_E_INVALID, "source: NULL descriptor, source or entry");
+  if (d->n_in > 2 || d->n_out < 1 || d->n_out > 2)
+    return e->fail(CE_E_INVALID, "source: 0..2 inputs and 1..2 outputs (got %u, %u)", d->n_in, d->n_out);
+  if (d->out_item_bytes == 0 || d->out_item_bytes > 256)
+    return e->fail(CE_E_INVALID, "source: out_item_bytes must be in [1, 256]");
+  if (d->scalar_bytes > CE_RT_SCALAR_BYTES || (d->scalar_bytes && !d->scalars))
+    return e->fail(CE_E_INVALID, "source: at most %d scalar bytes", CE_RT_SCALAR_BYTES);
+  for (uint32_t k = 0; k < d->n_in; ++k)
+    if (d->in_bytes[k] == 0) return e->fail(CE_E_INVALID, "source: input %u has no bytes", k);
+  // the previous payload is unbound whatever happens next
+  e->kernel_id = 0;
+  for (auto& b : e->in) b = Binding{};
+  for (auto& b : e->out) b = Binding{};
+  rt_release(e->rt_module);
+  e->rt_module = e->rt_fn_persistent = e->rt_fn_bare = nullptr;
+  std::string text;
+  const int rc = rt_build(d->source, d->entry, &e->rt_module, &e->rt_fn_persistent, &e->rt_fn_bare, &text);
+  copy_log(text, log, log_len);
+  if (rc != 0) {
+    if (rc == -1) return e->fail(CE_E_INVALID, "source: the payload did not compile (see the log)");
+    return e->fail(CE_E_DEVICE, "source: hipRTC or module load failed: %s", text.c_str());
+  }
+  e->rt_host = d->host;
+  e->rt_n_in = d->n_in;
+  e->rt_n_out = d->n_out;
+  e->rt_item_bytes = d->out_item_bytes;
+  e->rt_in_bytes[0] = d->n_in > 0 ? d->in_bytes[0] : 0;
+  e->rt_in_bytes[1] = d->n_in > 1 ? d->in_bytes[1] : 0;
+  memset(e->rt_scalars, 0, sizeof e->rt_scalars);
+  if (d->scalar_bytes) memcpy(e->rt_scalars, d->scalars, d->scalar_bytes);
+  // a new module: its occupancy is asked afresh
+  for (int k = 0; k < 2; ++k)
+    if (CE_KERNEL_RUNTIME * 2 + k < ce_engine::kOccSlots) e->occ_cache[CE_KERNEL_RUNTIME * 2 + k] = 0;
+  e->kernel_id = CE_KERNEL_RUNTIME;
+  return CE_OK;
+}
+
+ce_status ce_engine_bare_run_source(ce_engine* e, uint64_t gws, uint32_t lws, const void* const* ins,
+                                    void* const* outs, void* hip_stream, int sync) {
+  if (!e) return CE_E_INVALID;
+  if (e->kernel_id != CE_KERNEL_RUNTIME || !e->rt_fn_bare) return e->fail(CE_E_STATE, "bare: no runtime payload bound");
+  if (gws == 0 || lws == 0 || !outs) return e->fail(CE_E_INVALID, "bare: empty space or no outputs");
+  KernelArgs a{};
+  a.kernel_id = CE_KERNEL_RUNTIME;
+  for (uint32_t k = 0; k < e->rt_n_in; ++k) {
+    if (!ins || !ins[k]) return e->fail(CE_E_INVALID, "bare: input %u missing", k);
+    a.rt.buf[k] = const_cast<void*>(ins[k]);
+  }
+  for (uint32_t k = 0; k < e->rt_n_out; ++k) {
+    if (!outs[k]) return e->fail(CE_E_INVALID, "bare: output %u missing", k);
+    a.rt.buf[e->rt_n_in + k] = outs[k];
+  }
+  memcpy(a.rt.scalars, e->rt_scalars, sizeof e->rt_scalars);
+  a.rt_items = gws;
+  a.rt_lws = lws;
+  a.rt_item_bytes = e->rt_item_bytes;
+  a.rt_fn_persistent = e->rt_fn_persistent;
+  a.rt_fn_bare = e->rt_fn_bare;
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t he;
+  if ((he = launch_bare(a, st)) != hipSuccess) return e->hip_fail(he, "bare: launch");
+  if (sync && (he = hipStreamSynchronize(st)) != hipSuccess) return e->hip_fail(he, "bare: sync");
   return CE_OK;
 }
 

@@ -20,538 +20,10 @@
 #include "device_atomics.hpp"
 #include "device_tiles.hpp"
 #include "kernels.hpp"
+#include "rt_tile.hpp"
+#include "sched_device.hpp"
 
 namespace ce {
-
-__device__ __forceinline__ uint64_t max_u64(uint64_t a, uint64_t b) { return a > b ? a : b; }
-
-// ---------------------------------------------------------------- dispenser
-// Claims the next level-1 package for the GPU. Only the holder of the claim
-// lock runs this.
-__device__ bool claim_package(const SchedArgs& s, uint64_t* g0, uint64_t* g1, bool* timed_out) {
-  L2State* q = s.l2;
-  if (s.kind == kStatic) {
-    const uint32_t bk = dev_load(&q->st_next);
-    const uint32_t b = bk + s.st_first;
-    if (s.st_nbands == 0) {
-      // one package per device, cut only if it exceeds the descriptor's size field
-      const uint64_t a = s.st_begin + (uint64_t)b * kPubMaxSize;
-      if (a >= s.st_end) return false;
-      *g0 = a;
-      *g1 = (s.st_end - a > kPubMaxSize) ? a + kPubMaxSize : s.st_end;
-    } else {
-      const uint64_t b0 = s.st_begin + b;  // st_begin/st_end hold band indices here
-      if (b0 >= s.st_end) return false;
-      *g0 = band_edge(b0, s.G, s.st_nbands);
-      *g1 = band_edge(b0 + 1, s.G, s.st_nbands);
-    }
-    dev_store(&q->st_next, bk + 1);
-    return true;
-  }
-  if (s.kind == kDynamic) {
-    // `batch` consecutive packages with one atomic (split up by the caller)
-    const uint64_t span = s.pkg * s.batch;
-    const uint64_t a = sys_fetch_add(&s.l1->next, span);
-    if (a >= s.G) return false;
-    *g0 = a;
-    *g1 = (a + span < s.G) ? a + span : s.G;
-    return true;
-  }
-  // HGuided: the size follows the pending granules at the moment of the claim.
-  uint64_t cur = sys_load(&s.l1->next);
-  for (uint64_t tries = 0;; ++tries) {
-    if (cur >= s.G) return false;
-    uint64_t sz = hguided_size(s.G - cur, s.P_self, s.sumP, s.n_dev, s.k, s.min_self);
-    if (sz > kPubMaxSize) sz = kPubMaxSize;
-    if (sys_cas(&s.l1->next, &cur, cur + sz)) {
-      *g0 = cur;
-      *g1 = cur + sz;
-      return true;
-    }
-    if (tries > s.spin_limit) {
-      *timed_out = true;
-      return false;
-    }
-  }
-}
-
-// Publishes one package at the end of the GPU's tile sequence (lock held).
-template <class T>
-__device__ void publish(const T& pay, const SchedArgs& s, uint64_t tot, uint64_t g0, uint64_t g1, uint64_t tc) {
-  L2State* q = s.l2;
-  const uint32_t nk = dev_load(&q->n_pkgs);   // packages published by the kernel
-  const uint32_t n = nk + (s.pre_nt ? 1u : 0u);  // slot 0 holds the pre-claimed one
-  const uint32_t nt = pay.ntiles(g0, g1);
-  PkgSlot* ps = &s.pkgs[n];  // trace record, read by the host after the run;
-  ps->g0 = g0;               // its tile counter was cleared at the end of the last run
-  ps->g1 = g1;
-  ps->base = tot;
-  ps->ntiles = nt;
-  ps->t_claim = tc;
-  // t_end is written by the workgroup that runs the package's last ticket.
-  if (n == 0) dev_store(&q->t_first, tc);
-  dev_store(&q->n_pkgs, nk + 1);
-  dev_store(&q->granules, dev_load(&q->granules) + (g1 - g0));
-  dev_store(&s.pub[n], pub_word(g0, g1 - g0));  // readers spin until it is visible
-  dev_store(&q->total, tot + nt);
-}
-
-// Publishes the packages of one Dynamic claim ([g0, g1) holds `batch`
-// packages of `pkg` granules, the last one possibly short). The publication
-// words and the published count go out first, so workgroups start on the
-// packages at once; the trace records, which only the host reads after the
-// run, follow.
-template <class T>
-__device__ void publish_dynamic(const T& pay, const SchedArgs& s, uint64_t tot, uint64_t g0, uint64_t g1,
-                                uint64_t tc) {
-  // The arguments live in LDS and the stores below are flat ones, which may
-  // alias LDS and count against its counter: with the fields re-read from
-  // LDS after every store, each package would wait for all stores before it.
-  L2State* const q = s.l2;
-  PkgSlot* const pkgs = s.pkgs;
-  uint64_t* const pub = s.pub;
-  const uint64_t pkg = s.pkg;
-  const uint32_t max_pkgs = s.max_pkgs;
-  const uint32_t pre = s.pre_nt ? 1u : 0u;
-  const uint32_t nk0 = dev_load(&q->n_pkgs);
-  // packages that fit the table (the host sizes it so that all do)
-  uint64_t end = g1;
-  const uint64_t room = max_pkgs > nk0 + pre ? (uint64_t)(max_pkgs - nk0 - pre) : 0;
-  if (ceil_div(g1 - g0, pkg) > room) end = g0 + room * pkg;
-  const uint64_t tot0 = tot;  // first ticket of the claim
-  uint32_t nk = nk0;
-  for (uint64_t x = g0; x < end; x += pkg) {
-    const uint64_t y = (x + pkg < end) ? x + pkg : end;
-    dev_store(&pub[nk + pre], pub_word(x, y - x));
-    tot += pay.ntiles(x, y);
-    ++nk;
-    // the published count is the line every waiting workgroup polls: move
-    // it in steps of 32 packages rather than once per package
-    if (((nk - nk0) & 31u) == 0) dev_store(&q->total, tot);
-  }
-  dev_store(&q->total, tot);
-  uint64_t base = tot0;
-  if (nk0 + pre == 0) dev_store(&q->t_first, tc);
-  nk = nk0;
-  for (uint64_t x = g0; x < end; x += pkg) {
-    const uint64_t y = (x + pkg < end) ? x + pkg : end;
-    const uint32_t nt = pay.ntiles(x, y);
-    PkgSlot* ps = &pkgs[nk + pre];
-    ps->g0 = x;
-    ps->g1 = y;
-    ps->base = base;
-    ps->ntiles = nt;
-    ps->t_claim = tc;
-    base += nt;
-    ++nk;
-  }
-  dev_store(&q->n_pkgs, nk);
-  dev_store(&q->granules, dev_load(&q->granules) + (end - g0));
-  if (end < g1) sys_store(&s.l1->gpu_flags, 1);
-}
-
-// What one workgroup knows of the ticket chain, held by the lane that talks
-// to the dispenser: tickets taken but not yet run, the published total it
-// last read (it only grows, so it is a safe lower bound), the package of its
-// current ticket and that ticket. Completion needs no per-tile atomics: the
-// workgroup that runs a package's last ticket stamps the package's end, and
-// the GPU's end is the moment the last workgroup leaves (a report from every
-// workgroup at the end of a run would queue ~1000 atomics on one line).
-struct Cursor {  // zero-initialised at the start of a run
-  uint64_t t_next, t_end;
-  uint64_t tot_seen;
-  uint64_t base, g0, g1;
-  uint64_t cur_t;  // ticket of the tile being run
-  uint32_t p, nt;  // nt == 0: no package yet
-};
-
-// After a tile: if it held its package's last ticket, stamp the package end.
-__device__ __forceinline__ void tile_finished(const SchedArgs& s, const Cursor& c) {
-  if (c.nt == 0 || c.cur_t + 1 != c.base + c.nt) return;
-  uint64_t* te = (c.p == 0 && s.pre_nt) ? &s.l2->t_end0 : &s.pkgs[c.p].t_end;
-  dev_store(te, now_tick());
-}
-
-// Ticket chain with lookahead. Every workgroup's first ticket is its own
-// index among the n computing workgroups. After that, with uniform-cost
-// tiles (s.stride) workgroup w simply runs tickets w + n, w + 2n, ... with no
-// atomic at all; otherwise it takes s.chunk tickets per atomic from a
-// counter that starts past the first round. When a ticket is within `lookahead` tiles of the end of the
-// published tiles it tries to take the claim lock and append the next
-// level-1 package, so the PCIe round trip of the claim overlaps the last
-// round of tiles. The GPU thus acts as one device towards the scheduler while
-// its workgroups share each package. Returns false when this workgroup
-// should leave.
-template <class T>
-__device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t* ti_out) {
-  L2State* q = s.l2;
-  if (c.t_next == c.t_end) {
-    const uint64_t n = gridDim.x - s.gather_wgs;
-    if (s.stride) {
-      c.t_next = c.t_end - 1 + n;
-      c.t_end = c.t_next + 1;
-    } else {
-      c.t_next = n + dev_add(&q->ticket, (uint64_t)s.chunk);
-      c.t_end = c.t_next + s.chunk;
-    }
-  }
-  const uint64_t t = c.t_next++;
-  uint64_t spins = 0;
-  while (t + s.lookahead >= c.tot_seen) {
-    // The published tile count and the "no more packages" flag share one
-    // word, so a workgroup never pairs a stale count with a fresh flag (which
-    // would make it leave with a ticket that did get published).
-    const uint64_t w = dev_load(&q->total);
-    const uint64_t tot = max_u64(w & kTotalMask, s.pre_nt);
-    c.tot_seen = tot;
-    if (t + s.lookahead < tot) break;
-    if (w & kTotalDone) {
-      if (t < tot) break;
-      return false;
-    }
-    // Only two tickets may claim: the one `lookahead` before the end of the
-    // published tiles and the first one past it. Each belongs to exactly one
-    // workgroup, so the lock is never stormed. A workgroup that has waited
-    // long may also try, now and then: the designated ones may belong to
-    // workgroups that are not resident yet (a grid the occupancy query
-    // overestimated), and the wait must still end.
-    uint32_t unlocked = 0;
-    const bool overdue = spins > 4096 && (spins & 1023) == 0;
-    if ((t + s.lookahead == tot || t == tot || overdue) &&
-        __hip_atomic_compare_exchange_strong(&q->lock, &unlocked, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT)) {
-      // Everything the claimer reads or writes under the lock is an
-      // agent-scope atomic, performed where every XCD sees it, so the lock
-      // needs no cache maintenance: its loads start after the CAS returned,
-      // and the unlock waits until its stores are done.
-      const uint64_t w2 = dev_load(&q->total);
-      const uint64_t tot2 = max_u64(w2 & kTotalMask, s.pre_nt);
-      if (!(w2 & kTotalDone) && t + s.lookahead >= tot2) {
-        uint64_t g0 = 0, g1 = 0;
-        bool timed_out = false;
-        const uint64_t tc = now_tick();
-        // slots in use: the kernel's packages plus the one claimed before the launch
-        const uint32_t pre = s.pre_nt ? 1u : 0u;
-        if (dev_load(&q->n_pkgs) + pre >= s.max_pkgs || !claim_package(s, &g0, &g1, &timed_out)) {
-          if (timed_out || dev_load(&q->n_pkgs) + pre >= s.max_pkgs) sys_store(&s.l1->gpu_flags, 1);
-          dev_store(&q->total, tot2 | kTotalDone);
-        } else if (s.kind == kDynamic) {
-          publish_dynamic(pay, s, tot2, g0, g1, tc);
-        } else {
-          publish(pay, s, tot2, g0, g1, tc);
-          // A static plan fixes all of this device's bands in advance: publish
-          // the rest of them now rather than one claim round trip per band.
-          uint64_t tot3 = tot2 + pay.ntiles(g0, g1);
-          while (s.kind == kStatic && dev_load(&q->n_pkgs) + pre < s.max_pkgs && claim_package(s, &g0, &g1, &timed_out)) {
-            publish(pay, s, tot3, g0, g1, tc);
-            tot3 += pay.ntiles(g0, g1);
-          }
-        }
-      }
-      __builtin_amdgcn_s_waitcnt(0);
-      dev_store(&q->lock, 0u);
-      continue;
-    }
-    if (t < tot) break;
-    if (++spins > s.spin_limit) {
-      sys_store(&s.l1->gpu_flags, 1);
-      __hip_atomic_fetch_or(&q->total, kTotalDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
-    }
-    // waiting workgroups poll gently so the claimer's stores are not queued
-    // behind their loads; those far from the published end poll least
-    if (t - tot < 64)
-      __builtin_amdgcn_s_sleep(4);
-    else if (t - tot < 512)
-      __builtin_amdgcn_s_sleep(32);
-    else
-      __builtin_amdgcn_s_sleep(127);
-  }
-  if (c.nt == 0 || t >= c.base + c.nt) {
-    // Walk the publication words forward from the last package used; a
-    // workgroup's tickets only grow, so it never walks back. Dynamic
-    // packages all have the same tile count, so the walk starts at the
-    // ticket's own package (one load instead of one per package before it).
-    uint32_t p = c.nt ? c.p : 0;
-    uint64_t base = c.nt ? c.base : 0;
-    if (s.dyn_tiles) {
-      p = (uint32_t)(t / s.dyn_tiles);
-      base = (uint64_t)p * s.dyn_tiles;
-    }
-    for (uint64_t spins2 = 0;;) {
-      const uint64_t w = (p == 0 && s.pre_nt) ? pub_word(s.pre_g0, s.pre_g1 - s.pre_g0) : dev_load(&s.pub[p]);
-      if (w == 0) {  // published by the claimer but not visible here yet
-        if (++spins2 > s.spin_limit) {
-          sys_store(&s.l1->gpu_flags, 1);
-          return false;
-        }
-        continue;
-      }
-      const uint64_t g0 = pub_g0(w), g1 = g0 + pub_size(w);
-      const uint32_t nt = pay.ntiles(g0, g1);
-      if (t < base + nt) {
-        c.p = p;
-        c.base = base;
-        c.g0 = g0;
-        c.g1 = g1;
-        c.nt = nt;
-        break;
-      }
-      base += nt;
-      ++p;
-    }
-  }
-  c.cur_t = t;
-  *ti_out = (uint32_t)(t - c.base);
-  return true;
-}
-
-
-// The last workgroup out publishes the GPU's summary to the host, clears the
-// publication words and resets the level-2 state for the next run.
-__device__ void leave(const SchedArgs& s) {
-  L2State* q = s.l2;
-  // This workgroup's dispenser atomics are done before it counts itself out
-  // (waiting for them is enough; an agent-scope release would also write back
-  // this XCD's L2, once per workgroup).
-  __builtin_amdgcn_s_waitcnt(0);
-  const uint32_t ex = dev_add(&q->exit_count, 1u);
-  if (ex + 1 != gridDim.x) return;
-  uint64_t tf = dev_load(&q->t_first);
-  const uint64_t tl = dev_load(&q->t_last);
-  uint64_t gr = dev_load(&q->granules);
-  const uint32_t np = dev_load(&q->n_pkgs) + (s.pre_nt ? 1u : 0u);
-  if (s.pre_nt) {
-    // trace record of the pre-claimed package (read by the host after the run)
-    PkgSlot* ps = &s.pkgs[0];
-    const uint64_t tp = dev_load(&q->t_pre);
-    ps->g0 = s.pre_g0;
-    ps->g1 = s.pre_g1;
-    ps->base = 0;
-    ps->ntiles = s.pre_nt;
-    ps->t_claim = tp;
-    ps->t_end = dev_load(&q->t_end0);
-    tf = tp;
-    gr += s.pre_g1 - s.pre_g0;
-    dev_store(&q->t_pre, (uint64_t)0);
-    dev_store(&q->t_end0, (uint64_t)0);
-  }
-  for (uint32_t i = 0; i < np && i < s.max_pkgs; ++i) {
-    dev_store(&s.pub[i], (uint64_t)0);
-  }
-  sys_store(&s.l1->gpu_t_first, tf);
-  sys_store(&s.l1->gpu_t_last, tl);
-  sys_store(&s.l1->gpu_granules, gr);
-  sys_store(&s.l1->gpu_packages, np);
-  dev_store(&q->ticket, (uint64_t)0);
-  dev_store(&q->total, (uint64_t)0);
-  dev_store(&q->n_pkgs, 0u);
-  dev_store(&q->st_next, 0u);
-  dev_store(&q->granules, (uint64_t)0);
-  dev_store(&q->t_first, (uint64_t)0);
-  dev_store(&q->t_last, (uint64_t)0);
-  dev_store(&q->exit_compute, 0u);
-  dev_store(&q->lock, 0u);
-  dev_store(&q->gather_next, (uint64_t)0);
-  dev_store(&q->exit_count, 0u);
-  sys_store(&s.l1->gpu_t_gather, dev_load(&q->t_gather));
-  dev_store(&q->t_gather, (uint64_t)0);
-  sys_store(&s.l1->gpu_t_leave, now_tick());  // lets the host re-anchor its clock mapping
-  sys_store_release(&s.l1->gpu_run_id, s.run_id);
-}
-
-// Gather (device-resident output with the host in the device set): the host
-// workers publish each finished host tile as a byte range of their output
-// buffer in a ring in host-coherent memory; workgroups 0 .. gather_wgs-1 read
-// those ranges over PCIe and write them into the device output while the
-// other workgroups compute, so no copy is left for after the kernel.
-__device__ bool gather_entry(const SchedArgs& s, uint64_t* off, uint32_t* len) {
-  const uint64_t j = dev_add(&s.l2->gather_next, (uint64_t)1);
-  const uint64_t t0 = now_tick();
-  const uint64_t want = host_final_word(s.run_id, 0) >> 40;
-  for (;;) {
-    if (j < s.ring_cap) {
-      const uint64_t w = __hip_atomic_load(const_cast<uint64_t*>(&s.ring[j]), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_SYSTEM);
-      if (w != 0) {
-        *off = ring_off(w);
-        *len = (uint32_t)ring_len(w);
-        return true;
-      }
-    }
-    const uint64_t f = sys_load(&s.l1->host_final);
-    if ((f >> 40) == want && j >= (f & ((1ull << 40) - 1))) return false;
-    if (now_tick() - t0 > s.wait_ticks) {
-      sys_store(&s.l1->gpu_flags, 2);
-      return false;
-    }
-    __builtin_amdgcn_s_sleep(8);
-  }
-}
-
-// Host memory is reached over PCIe with a latency of microseconds, so each
-// thread issues a batch of independent loads before it stores any of them.
-// The loads are system-scope atomics: a plain load could be served from a
-// line this XCD cached while copying a neighbouring tile that shares it,
-// before the host had written this tile's part (ragged rows share lines).
-__device__ void gather_copy(const SchedArgs& s, uint64_t off, uint32_t len) {
-  constexpr uint32_t kBatch = 8;
-  const char* src = s.gsrc + off;
-  char* dst = s.gdst + off;
-  if (((off | len) & 7u) == 0) {
-    uint64_t* a = reinterpret_cast<uint64_t*>(const_cast<char*>(src));
-    uint64_t* b = reinterpret_cast<uint64_t*>(dst);
-    const uint32_t n = len / 8;
-    for (uint32_t i0 = 0; i0 < n; i0 += kBlockThreads * kBatch) {
-      uint64_t v[kBatch];
-#pragma unroll
-      for (uint32_t k = 0; k < kBatch; ++k) {
-        const uint32_t i = i0 + k * kBlockThreads + threadIdx.x;
-        if (i < n) v[k] = __hip_atomic_load(a + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      }
-#pragma unroll
-      for (uint32_t k = 0; k < kBatch; ++k) {
-        const uint32_t i = i0 + k * kBlockThreads + threadIdx.x;
-        if (i < n) b[i] = v[k];
-      }
-    }
-  } else {
-    uint32_t* a = reinterpret_cast<uint32_t*>(const_cast<char*>(src));
-    uint32_t* b = reinterpret_cast<uint32_t*>(dst);
-    const uint32_t n = len / 4;
-    for (uint32_t i0 = 0; i0 < n; i0 += kBlockThreads * kBatch) {
-      uint32_t v[kBatch];
-#pragma unroll
-      for (uint32_t k = 0; k < kBatch; ++k) {
-        const uint32_t i = i0 + k * kBlockThreads + threadIdx.x;
-        if (i < n) v[k] = __hip_atomic_load(a + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      }
-#pragma unroll
-      for (uint32_t k = 0; k < kBatch; ++k) {
-        const uint32_t i = i0 + k * kBlockThreads + threadIdx.x;
-        if (i < n) b[i] = v[k];
-      }
-    }
-  }
-}
-
-// Persistent workgroup loop. Every branch around the barriers is uniform
-// across the workgroup: the claim block is entered by the whole first wave
-// (readfirstlane of the thread id) and only its lane 0 touches the
-// dispenser; the loop exit reads the shared flag through readfirstlane.
-// With a per-lane "thread 0 only" condition instead, the compiler may
-// rotate the loop so that lane 0 leaves an inner loop through an exec-mask
-// update while the other lanes keep passing the barriers, which never ends.
-template <class T>
-__global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persistent(T pay, SchedArgs s) {
-  __shared__ uint32_t sh_go, sh_p, sh_ti;
-  __shared__ uint64_t sh_g0, sh_g1;
-  const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) == 0;
-  const bool lane0 = threadIdx.x == 0;
-  pay.load_constants();
-  // The scheduler arguments are read from LDS inside the tile loop: kept in
-  // scalar registers across the payload they would crowd out its own.
-  __shared__ SchedArgs sh_args;
-  if (threadIdx.x == 0) sh_args = s;
-  __syncthreads();
-  const SchedArgs& sa = sh_args;
-  // The cursor lives in LDS too: only lane 0 of wave 0 uses it, and keeping
-  // it in registers across the tile loop would cost the payload occupancy.
-  __shared__ Cursor sh_cursor;
-  Cursor& c = sh_cursor;
-  if (wave0) {
-    if (lane0) {
-      c = Cursor{};
-      c.t_next = blockIdx.x - s.gather_wgs;  // the first ticket needs no atomic
-      c.t_end = c.t_next + 1;
-      c.tot_seen = s.pre_nt;
-      if (s.pre_nt && c.t_next == 0) dev_store(&s.l2->t_pre, now_tick());
-    }
-  }
-  uint32_t prev_p = 0xFFFFFFFFu;
-  if (blockIdx.x < s.gather_wgs) {
-    __shared__ uint64_t sh_off;
-    __shared__ uint32_t sh_len;
-    for (;;) {
-      if (wave0) {
-        if (lane0) {
-          uint64_t off = 0;
-          uint32_t len = 0;
-          sh_go = gather_entry(s, &off, &len) ? 1u : 0u;
-          sh_off = off;
-          sh_len = len;
-        }
-      }
-      __syncthreads();
-      if (__builtin_amdgcn_readfirstlane(sh_go) == 0) break;
-      const uint64_t off = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sh_off >> 32)) << 32) |
-                           __builtin_amdgcn_readfirstlane((uint32_t)sh_off);
-      const uint32_t len = __builtin_amdgcn_readfirstlane(sh_len);
-      gather_copy(s, off, len);
-      if (wave0) {
-        if (lane0) {
-          sys_fetch_add(&s.l1->gathered, (uint64_t)len);  // progress for the host's throttle
-          __hip_atomic_fetch_max(&s.l2->t_gather, now_tick(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-      }
-      __syncthreads();
-    }
-    if (wave0) {
-      if (lane0) leave(s);
-    }
-    return;
-  }
-  for (;;) {
-    if (wave0) {
-      if (lane0) {
-        uint32_t p = 0, ti = 0;
-        uint64_t g0 = 0, g1 = 0;
-        bool go;
-        if (prev_p != 0xFFFFFFFFu) tile_finished(sa, c);
-        go = next_tile(pay, sa, c, &ti);
-        p = c.p;
-        g0 = c.g0;
-        g1 = c.g1;
-        sh_go = go ? 1u : 0u;
-        sh_p = p;
-        sh_ti = ti;
-        sh_g0 = g0;
-        sh_g1 = g1;
-      }
-    }
-    __syncthreads();
-    const uint32_t go = __builtin_amdgcn_readfirstlane(sh_go);
-    if (go == 0) break;
-    const uint32_t p = __builtin_amdgcn_readfirstlane(sh_p);
-    const uint32_t ti = __builtin_amdgcn_readfirstlane(sh_ti);
-    const uint64_t g0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sh_g0 >> 32)) << 32) |
-                        __builtin_amdgcn_readfirstlane((uint32_t)sh_g0);
-    const uint64_t g1 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sh_g1 >> 32)) << 32) |
-                        __builtin_amdgcn_readfirstlane((uint32_t)sh_g1);
-    // Nothing of the scheduler's may still be in flight when the payload
-    // starts: its pointers come from LDS, so its accesses are flat ones,
-    // which count against the LDS counter too; with one pending, every LDS
-    // wait inside the payload would have to drain all of them.
-    __builtin_amdgcn_s_waitcnt(0);
-    pay.run(g0, g1, ti);
-    prev_p = p;
-    __syncthreads();  // the tile is complete and the shared slots may be reused
-  }
-  if (wave0) {
-    if (lane0) {
-      // the last computing workgroup out marks the end of the GPU's work
-      // (gather workgroups may still be copying the host's output)
-      if (dev_add(&sa.l2->exit_compute, 1u) + 1 == gridDim.x - sa.gather_wgs) dev_store(&sa.l2->t_last, now_tick());
-      leave(sa);
-    }
-  }
-}
-
-template <class T>
-__global__ __launch_bounds__(kBlockThreads) void k_bare(T pay, uint64_t G) {
-  pay.load_constants();
-  pay.run(0, G, blockIdx.x);
-}
 
 __global__ void k_calibrate(L1State* l1, uint32_t rounds, uint64_t spin_limit) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -584,6 +56,7 @@ template <bool S>
 NbodyStepTile<S> make_nbody_step(const KernelArgs& a) {
   return NbodyStepTile<S>{a.nbs, (const float4*)a.in0, (const float4*)a.in1, (float4*)a.out, (float4*)a.out1};
 }
+RtTile make_rt(const KernelArgs& a) { return RtTile{a.rt, a.rt_items, a.rt_lws}; }
 }  // namespace
 
 uint64_t gpu_granules(const KernelArgs& a) {
@@ -593,6 +66,7 @@ uint64_t gpu_granules(const KernelArgs& a) {
     case CE_KERNEL_NBODY_ACC: return make_nbody<true>(a).granules();
     case CE_KERNEL_NBODY_STEP: return make_nbody_step<true>(a).granules();
     case CE_KERNEL_BINOMIAL: return make_binomial(a).granules();
+    case CE_KERNEL_RUNTIME: return make_rt(a).granules();
   }
   return 0;
 }
@@ -604,6 +78,7 @@ uint32_t gpu_tiles(const KernelArgs& a, uint64_t g0, uint64_t g1) {
     case CE_KERNEL_NBODY_ACC: return make_nbody<true>(a).ntiles(g0, g1);
     case CE_KERNEL_NBODY_STEP: return make_nbody_step<true>(a).ntiles(g0, g1);
     case CE_KERNEL_BINOMIAL: return make_binomial(a).ntiles(g0, g1);
+    case CE_KERNEL_RUNTIME: return make_rt(a).ntiles(g0, g1);
   }
   return 0;
 }
@@ -626,6 +101,10 @@ hipError_t persistent_blocks_per_cu(const KernelArgs& a, int* blocks) {
                                                                      kBlockThreads, 0);
     case CE_KERNEL_BINOMIAL:
       return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_persistent<BinomialTile>, kBlockThreads, 0);
+    case CE_KERNEL_RUNTIME:
+      if (!a.rt_fn_persistent) return hipErrorInvalidValue;
+      return hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (hipFunction_t)a.rt_fn_persistent,
+                                                                kBlockThreads, 0);
   }
   return hipErrorInvalidValue;
 }
@@ -648,6 +127,14 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t g
         hipLaunchKernelGGL(k_persistent<NbodyStepTile<false>>, g, b, 0, st, make_nbody_step<false>(a), s);
       break;
     case CE_KERNEL_BINOMIAL: hipLaunchKernelGGL(k_persistent<BinomialTile>, g, b, 0, st, make_binomial(a), s); break;
+    case CE_KERNEL_RUNTIME: {
+      if (!a.rt_fn_persistent) return hipErrorInvalidValue;
+      RtTile pay = make_rt(a);
+      SchedArgs sa = s;
+      void* params[] = {&pay, &sa};
+      return hipModuleLaunchKernel((hipFunction_t)a.rt_fn_persistent, grid, 1, 1, kBlockThreads, 1, 1, 0, st, params,
+                                   nullptr);
+    }
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -674,6 +161,14 @@ hipError_t launch_bare(const KernelArgs& a, hipStream_t st) {
         hipLaunchKernelGGL(k_bare<NbodyStepTile<false>>, g, b, 0, st, make_nbody_step<false>(a), G);
       break;
     case CE_KERNEL_BINOMIAL: hipLaunchKernelGGL(k_bare<BinomialTile>, g, b, 0, st, make_binomial(a), G); break;
+    case CE_KERNEL_RUNTIME: {
+      if (!a.rt_fn_bare) return hipErrorInvalidValue;
+      RtTile pay = make_rt(a);
+      uint64_t g_arg = G;
+      void* params[] = {&pay, &g_arg};
+      return hipModuleLaunchKernel((hipFunction_t)a.rt_fn_bare, tiles, 1, 1, kBlockThreads, 1, 1, 0, st, params,
+                                   nullptr);
+    }
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/coexec.h"
 #include "common.hpp"
 
@@ -22,6 +24,14 @@ struct KernelArgs {
   const void* in1;
   void* out;
   void* out1;               // second output (n-body step: velocities)
+  // payload supplied at run time: device arguments, index space and the
+  // loaded module's kernels (hipFunction_t)
+  ce_rt_args rt;
+  uint64_t rt_items;
+  uint64_t rt_lws;
+  uint32_t rt_item_bytes;
+  void* rt_fn_persistent;
+  void* rt_fn_bare;
 };
 
 // Granules of the index space and tiles of a package, as the GPU cuts them.
@@ -32,6 +42,14 @@ uint32_t gpu_tiles(const KernelArgs& a, uint64_t g0, uint64_t g1);
 hipError_t persistent_blocks_per_cu(const KernelArgs& a, int* blocks);
 hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t grid, hipStream_t st);
 hipError_t launch_bare(const KernelArgs& a, hipStream_t st);
+// Runtime payloads (rt_module.cpp): compile the caller's work-item source
+// for gfx950 (no GPU needed), and compile and load it on the current device.
+// 0 on success; otherwise negative with the compiler's log.
+int rt_compile(const char* source, const char* entry, std::string* code, std::string* lowered_persistent,
+               std::string* lowered_bare, std::string* log);
+int rt_build(const char* source, const char* entry, void** module, void** fn_persistent, void** fn_bare,
+             std::string* log);
+void rt_release(void* module);
 // Clock calibration: one thread answers `rounds` pings through the mailbox.
 hipError_t launch_calibrate(L1State* l1, uint32_t rounds, uint64_t spin_limit, hipStream_t st);
 

@@ -111,7 +111,9 @@ namespace ce {
 
 // ------------------------------------------------ coverage-marking payloads
 namespace {
-size_t item_words(int kernel_id) {
+size_t item_words(const KernelArgs& a) {
+  if (a.kernel_id == CE_KERNEL_RUNTIME) return a.rt_item_bytes / 4;
+  const int kernel_id = a.kernel_id;
   return (kernel_id == CE_KERNEL_NBODY_ACC || kernel_id == CE_KERNEL_NBODY_STEP || kernel_id == CE_KERNEL_BINOMIAL)
              ? 4
              : 1;
@@ -146,7 +148,9 @@ void h_nbody(const float*, uint32_t, float, int, uint64_t i0, uint64_t i1, float
 }
 const HostPayloadFns kSim = {h_escape, h_blur, h_nbody, "sim"};
 
+uint64_t rt_item(const KernelArgs& a, uint64_t g) { return std::min<uint64_t>(g * a.rt_lws, a.rt_items); }
 uint64_t items_of(const KernelArgs& a, uint64_t g0, uint64_t g1) {
+  if (a.kernel_id == CE_KERNEL_RUNTIME) return rt_item(a, g1) - rt_item(a, g0);
   if (a.kernel_id == CE_KERNEL_BINOMIAL) return g1 - g0;  // one output element per option group
   if (a.kernel_id == CE_KERNEL_ESCAPE) return (g1 - g0) * a.esc.w;
   if (a.kernel_id == CE_KERNEL_BLUR5) return (g1 - g0) * a.blur.w;
@@ -154,6 +158,7 @@ uint64_t items_of(const KernelArgs& a, uint64_t g0, uint64_t g1) {
   return hi > lo ? hi - lo : 0;
 }
 uint64_t first_item(const KernelArgs& a, uint64_t g) {
+  if (a.kernel_id == CE_KERNEL_RUNTIME) return rt_item(a, g);
   if (a.kernel_id == CE_KERNEL_BINOMIAL) return g;
   if (a.kernel_id == CE_KERNEL_ESCAPE) return g * a.esc.w;
   if (a.kernel_id == CE_KERNEL_BLUR5) return g * a.blur.w;
@@ -162,6 +167,14 @@ uint64_t first_item(const KernelArgs& a, uint64_t g) {
 }  // namespace
 
 const HostPayloadFns* host_payloads() { return &kSim; }
+
+// Host version of a simulated runtime payload: scalars[0] is the index of
+// the output buffer, scalars[1] its 32-bit words per work-item.
+extern "C" void sim_rt_host(uint64_t i0, uint64_t i1, const ce_rt_args* a) {
+  const int64_t until = now_ns() + (int64_t)(g_host_ns_per_item * (double)(i1 - i0));
+  mark((uint32_t*)a->buf[a->scalars[0]], i0, i1, a->scalars[1]);
+  spin_until(until);
+}
 
 // The step's update after the (coverage-counting) force payload: the
 // position output gets the same item indices.
@@ -181,12 +194,14 @@ void nbody_step_update(const float*, const float*, float, uint64_t i0, uint64_t 
 
 // ------------------------------------------------------ fake GPU kernels
 uint64_t gpu_granules(const KernelArgs& a) {
+  if (a.kernel_id == CE_KERNEL_RUNTIME) return (a.rt_items + a.rt_lws - 1) / a.rt_lws;
   if (a.kernel_id == CE_KERNEL_ESCAPE) return a.esc.h;
   if (a.kernel_id == CE_KERNEL_BLUR5) return a.blur.h;
   if (a.kernel_id == CE_KERNEL_BINOMIAL) return a.bin.n_groups;
   return (bodies_of(a) + 255) / 256;
 }
 uint32_t gpu_tiles(const KernelArgs& a, uint64_t g0, uint64_t g1) {
+  if (a.kernel_id == CE_KERNEL_RUNTIME) return (uint32_t)ceil_div(items_of(a, g0, g1), 2048);
   if (a.kernel_id == CE_KERNEL_ESCAPE) return (uint32_t)(ceil_div(g1 - g0, kEscapeTileRows) * ceil_div(a.esc.w, kEscapeTileCols));
   if (a.kernel_id == CE_KERNEL_BLUR5) return (uint32_t)(ceil_div(g1 - g0, kBlurTileRows) * ceil_div(a.blur.w, kBlurTileCols));
   return (uint32_t)(g1 - g0);
@@ -248,7 +263,7 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, 
       if (!np) t_first = tc;
       const uint64_t n = items_of(a, g0, g1);
       const int64_t until = now_ns() + (int64_t)(g_gpu_ns_per_item * (double)n);
-      mark((uint32_t*)a.out, first_item(a, g0), first_item(a, g0) + n, item_words(a.kernel_id));
+      mark((uint32_t*)a.out, first_item(a, g0), first_item(a, g0) + n, item_words(a));
       mark_second((uint32_t*)a.out1, first_item(a, g0), first_item(a, g0) + n);
       spin_until(until);
       PkgSlot& ps = s.pkgs[np];
@@ -296,10 +311,32 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, 
 
 hipError_t launch_bare(const KernelArgs& a, hipStream_t) {
   const uint64_t G = gpu_granules(a);
-  mark((uint32_t*)a.out, 0, items_of(a, 0, G), item_words(a.kernel_id));
+  mark((uint32_t*)a.out, 0, items_of(a, 0, G), item_words(a));
   mark_second((uint32_t*)a.out1, 0, items_of(a, 0, G));
   return hipSuccess;
 }
+
+// Runtime payloads: the stand-in "compiler" accepts a source that names its
+// entry; the simulated GPU marks coverage like the fixed payloads.
+int rt_compile(const char* source, const char* entry, std::string* code, std::string* lp, std::string* lb,
+               std::string* log) {
+  if (!source || !entry || !*entry || !strstr(source, entry)) {
+    *log = "payload.hip: error: entry not found (simulated compiler)";
+    return -1;
+  }
+  *code = "sim";
+  *lp = *lb = entry;
+  return 0;
+}
+int rt_build(const char* source, const char* entry, void** module, void** fn_persistent, void** fn_bare,
+             std::string* log) {
+  std::string c, a, b;
+  const int rc = rt_compile(source, entry, &c, &a, &b, log);
+  if (rc != 0) return rc;
+  *module = *fn_persistent = *fn_bare = (void*)1;
+  return 0;
+}
+void rt_release(void*) {}
 
 hipError_t launch_calibrate(L1State* l1, uint32_t rounds, uint64_t, hipStream_t st) {
   join_gpu();

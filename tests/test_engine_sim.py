@@ -416,3 +416,76 @@ def test_binomial_pattern_and_space_checks(simlib):
     simlib.sim_reset(10)
     eng.run()
     eng.close()
+
+
+# ------------------------------------------------------ runtime payloads
+SIM_RT_SRC = "__device__ void sim_entry(uint64_t i, const ce_rt_args* a) {}"
+
+
+def _run_runtime(L, n, lws, devs, sched, residency="device", rates=(2.0, 5.0, 1000.0)):
+    L.sim_set_rates(*rates)
+    eng = ce.Engine(L)
+    eng.use(devs, 0, 4)
+    eng.work_items([n], [lws])
+    host_fn = C.cast(L.sim_rt_host, C.c_void_p).value
+    # one 16-byte input, one output of one word per item (scalars: output index, words)
+    eng.program_source(SIM_RT_SRC, "sim_entry", host=host_fn, n_in=1, n_out=1, in_bytes=[16], out_item_bytes=4,
+                       scalars=bytes([1, 1]))
+    x = np.zeros(4, np.float32)
+    eng.program_in(0, host=x, dev=x)
+    out = np.zeros(n, np.uint32)
+    if residency == "device":
+        eng.program_out(0, dev=out)
+    else:
+        eng.program_out(0, host=out)
+    eng.scheduler(**sched)
+    L.sim_reset(n)
+    eng.run()
+    st, tr = eng.stats(), eng.trace()
+    eng.close()
+    assert np.array_equal(out, np.arange(n, dtype=np.uint32))
+    return _coverage(L, n), st, tr
+
+
+@pytest.mark.parametrize("residency", ["device", "host"])
+@pytest.mark.parametrize("sched", ["static", "dynamic", "hguided"])
+@pytest.mark.parametrize("devs", ["gpu", "host", "both"])
+def test_runtime_payload_every_item_once(simlib, residency, sched, devs):
+    d = {"gpu": ce.CE_DEV_GPU, "host": ce.CE_DEV_HOST, "both": BOTH}[devs]
+    s = SCHEDS[sched] if devs == "both" else _one_dev(SCHEDS[sched])
+    # a ragged space: the last granule holds 37 of 100 items
+    cov, st, tr = _run_runtime(simlib, 100 * 57 + 37, 100, d, s, residency)
+    assert np.all(cov == 1)
+    assert sum(e - b for _, b, e, _, _ in tr) == 58
+
+
+def test_runtime_payload_refusals(simlib):
+    eng = ce.Engine(simlib)
+    eng.work_items([1000], [10])
+    with pytest.raises(ce.CoexecError) as ei:
+        eng.program_source("__device__ void other(uint64_t, const ce_rt_args*) {}", "sim_entry", n_out=1)
+    assert ei.value.status == ce.CE_E_INVALID and "entry not found" in str(ei.value)
+    # the failed compile left no payload bound
+    assert eng.run_status() == ce.CE_E_STATE
+    for kw in (dict(n_out=0), dict(n_out=3), dict(n_in=3), dict(out_item_bytes=0), dict(out_item_bytes=257),
+               dict(scalars=bytes(129)), dict(n_in=1, in_bytes=[0])):
+        args = dict(n_out=1)
+        args.update(kw)
+        with pytest.raises(ce.CoexecError) as ei:
+            eng.program_source(SIM_RT_SRC, "sim_entry", **args)
+        assert ei.value.status == ce.CE_E_INVALID, kw
+    # a payload without a host version cannot run on the host
+    eng.program_source(SIM_RT_SRC, "sim_entry", n_out=1, out_item_bytes=4)
+    out = np.zeros(1000, np.uint32)
+    eng.program_out(0, host=out)
+    eng.use(BOTH, 0, 2)
+    eng.scheduler(kind=ce.CE_SCHED_DYNAMIC, package_granules=5)
+    assert eng.run_status() == ce.CE_E_UNSUPPORTED
+    # slots follow the descriptor; only the 1:1 pattern
+    with pytest.raises(ce.CoexecError):
+        eng.program_in(0, host=out)
+    with pytest.raises(ce.CoexecError):
+        eng.program_out(1, host=out)
+    with pytest.raises(ce.CoexecError):
+        eng.program_out_pattern(1, 10)
+    eng.close()
