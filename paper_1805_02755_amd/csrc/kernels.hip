@@ -56,7 +56,7 @@ template <bool S>
 NbodyStepTile<S> make_nbody_step(const KernelArgs& a) {
   return NbodyStepTile<S>{a.nbs, (const float4*)a.in0, (const float4*)a.in1, (float4*)a.out, (float4*)a.out1};
 }
-RtTile make_rt(const KernelArgs& a) { return RtTile{a.rt, a.rt_items, a.rt_lws}; }
+RtTile make_rt(const KernelArgs& a) { return RtTile{a.rt, a.rt_items, a.rt_lws, rt_tile_items(a.rt_items)}; }
 }  // namespace
 
 uint64_t gpu_granules(const KernelArgs& a) {
