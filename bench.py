@@ -201,10 +201,10 @@ def main():
         ins_host, ins_dev = [], []
         n_items = p.w * p.h
         G = p.h
-        host_threads = 1
-        coexec = dict(kind=ce.CE_SCHED_STATIC, n_packages=8, order=ce.CE_ORDER_HOST_FIRST)
-        config = {"workload": "escape-time 1024x1024 over [-2,1]x[-1.5,1.5], max_iter 256", "scheduler": "static x8",
-                  "devices": "gpu+1 host thread", "residency": args.mode}
+        host_threads = args.host_threads
+        coexec = dict(kind=ce.CE_SCHED_HGUIDED, k=2)
+        config = {"workload": "escape-time 1024x1024 over [-2,1]x[-1.5,1.5], max_iter 256", "scheduler": "hguided",
+                  "devices": "gpu+host", "residency": args.mode}
         bound = "alu"
         if wl == "runtime":
             if args.mode != "device":
@@ -216,9 +216,7 @@ def main():
             # the host take only what it finishes in time.
             rt_lws = 64
             G = n_items // rt_lws
-            host_threads = args.host_threads
-            coexec = dict(kind=ce.CE_SCHED_HGUIDED, k=2)
-            config.update({"scheduler": "hguided", "devices": "gpu+host", "granule": "64 pixels"})
+            config["granule"] = "64 pixels"
     else:
         n = 65536
         bodies = synth.nbody_bodies(n)

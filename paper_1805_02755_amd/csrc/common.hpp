@@ -16,8 +16,8 @@ enum SchedKind : uint32_t { kStatic = 0, kDynamic = 1, kHGuided = 2 };
 
 // Tiles: how a package of granules is cut for the GPU's workgroups.
 // 2-D payloads: a tile is kTileRows rows by one column block.
-constexpr uint32_t kEscapeTileRows = 16;
-constexpr uint32_t kEscapeTileCols = 64;
+constexpr uint32_t kEscapeTileRows = 1;
+constexpr uint32_t kEscapeTileCols = 512;
 constexpr uint32_t kBlurTileRows = 32;
 constexpr uint32_t kBlurTileCols = 1024;  // 256 threads x 4 columns
 constexpr uint32_t kNbodyGranule = 256;   // bodies per granule (1-D lws)

@@ -24,18 +24,17 @@ struct EscapeTile {
   __host__ __device__ uint32_t ntiles(uint64_t g0, uint64_t g1) const {
     return (uint32_t)(ceil_div(g1 - g0, kEscapeTileRows) * ncb());
   }
-  // A tile is 16 rows x 64 columns; each wave covers four 8 x 8 blocks so
-  // the lanes of a wave iterate over neighbouring pixels.
+  // A tile is kEscapeTileRows x kEscapeTileCols pixels walked as strips of 64
+  // consecutive pixels of one row: thread j takes pixels j, j + 256, ... of
+  // the tile in row-major order.
   __device__ void run(uint64_t g0, uint64_t g1, uint32_t t) const {
     const uint32_t nc = ncb();
     const uint64_t rb = g0 + (uint64_t)(t / nc) * kEscapeTileRows;
     const uint32_t cb = (t % nc) * kEscapeTileCols;
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
 #pragma unroll 1
-    for (uint32_t i = 0; i < 4; ++i) {
-      const uint32_t b = wave * 4u + i;
-      const uint64_t r = rb + (b >> 3) * 8u + (lane >> 3);
-      const uint32_t c = cb + (b & 7u) * 8u + (lane & 7u);
+    for (uint32_t q = threadIdx.x; q < kEscapeTileRows * kEscapeTileCols; q += kBlockThreads) {
+      const uint64_t r = rb + q / kEscapeTileCols;
+      const uint32_t c = cb + q % kEscapeTileCols;
       if (r < g1 && c < p.w) {
         const float cr = p.x0 + (float)c * p.dx;
         const float ci = p.y0 + (float)r * p.dy;
