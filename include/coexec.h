@@ -272,6 +272,12 @@ ce_status ce_program_source(ce_engine* e, const ce_rt_desc* desc, char* log, siz
 /* Compiles a runtime payload's source without binding it (no GPU needed):
  * CE_OK, or CE_E_INVALID with the compiler's log as above. */
 ce_status ce_rt_compile_check(const char* source, const char* entry, char* log, size_t log_len);
+/* As ce_rt_compile_check, and hands out the gfx950 code object (an ELF
+ * shared object holding the payload's persistent and plain kernels): *size
+ * receives its length; it is copied into buf when cap >= *size (buf may be
+ * NULL to ask for the size). For inspecting what the GPU will run. */
+ce_status ce_rt_code_object(const char* source, const char* entry, void* buf, size_t cap, size_t* size, char* log,
+                            size_t log_len);
 /* Plain single launch of the engine's bound runtime payload over gws
  * work-items of granule lws (the "native" side of the overhead metric):
  * device pointers, ins[] / outs[] follow its slots, on `hip_stream`. */

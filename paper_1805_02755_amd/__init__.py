@@ -61,7 +61,7 @@ EXPORTED_SYMBOLS = (
     "ce_batch_run_separate", "ce_batch_stats", "ce_batch_error", "ce_server_create", "ce_server_destroy",
     "ce_server_submit", "ce_server_poll", "ce_server_wait", "ce_server_output", "ce_server_copy_output",
     "ce_server_release", "ce_server_drain", "ce_server_stats", "ce_server_error", "ce_program_source",
-    "ce_rt_compile_check", "ce_engine_bare_run_source",
+    "ce_rt_compile_check", "ce_rt_code_object", "ce_engine_bare_run_source",
 )
 
 CE_JOB_QUEUED = 0
@@ -198,6 +198,7 @@ def load(path: str):
         "ce_bare_run_outs": (i32, [C.c_int, vp, sz, C.POINTER(vp), C.POINTER(vp), C.c_uint32, vp, C.c_int]),
         "ce_program_source": (i32, [vp, C.POINTER(ce_rt_desc), C.c_char_p, sz]),
         "ce_rt_compile_check": (i32, [C.c_char_p, C.c_char_p, C.c_char_p, sz]),
+        "ce_rt_code_object": (i32, [C.c_char_p, C.c_char_p, vp, sz, C.POINTER(sz), C.c_char_p, sz]),
         "ce_engine_bare_run_source": (i32, [vp, u64, u32, C.POINTER(vp), C.POINTER(vp), vp, C.c_int]),
         "ce_sched_static_plan": (i32, [u64, u32, C.POINTER(C.c_double), C.POINTER(u32), u32, C.POINTER(u64),
                                        C.POINTER(u64)]),
@@ -344,6 +345,20 @@ def ce_rt_compile_check(source: str, entry: str):
     buf = C.create_string_buffer(1 << 16)
     st = lib().ce_rt_compile_check(source.encode(), entry.encode(), buf, len(buf))
     return st, buf.value.decode(errors="replace")
+
+
+def ce_rt_code_object(source: str, entry: str) -> bytes:
+    """The gfx950 code object hipRTC builds for a runtime payload."""
+    n = C.c_size_t(0)
+    log = C.create_string_buffer(1 << 16)
+    st = lib().ce_rt_code_object(source.encode(), entry.encode(), None, 0, C.byref(n), log, len(log))
+    if st != CE_OK:
+        raise CoexecError(st, "ce_rt_code_object", [log.value.decode(errors="replace")])
+    buf = C.create_string_buffer(n.value)
+    st = lib().ce_rt_code_object(source.encode(), entry.encode(), buf, n.value, C.byref(n), log, len(log))
+    if st != CE_OK:
+        raise CoexecError(st, "ce_rt_code_object", [log.value.decode(errors="replace")])
+    return buf.raw[:n.value]
 
 
 def stream_handle(stream) -> Optional[int]:

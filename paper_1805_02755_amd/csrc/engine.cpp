@@ -1477,6 +1477,19 @@ ce_status ce_rt_compile_check(const char* source, const char* entry, char* log, 
   return rc == 0 ? CE_OK : (rc == -1 ? CE_E_INVALID : CE_E_DEVICE);
 }
 
+ce_status ce_rt_code_object(const char* source, const char* entry, void* buf, size_t cap, size_t* size, char* log,
+                            size_t log_len) {
+  if (!size) return CE_E_INVALID;
+  *size = 0;
+  std::string code, lp, lb, text;
+  const int rc = rt_compile(source, entry, &code, &lp, &lb, &text);
+  copy_log(text, log, log_len);
+  if (rc != 0) return rc == -1 ? CE_E_INVALID : CE_E_DEVICE;
+  *size = code.size();
+  if (buf && cap >= code.size()) memcpy(buf, code.data(), code.size());
+  return CE_OK;
+}
+
 ce_status ce_program_source(ce_engine* e, const ce_rt_desc* d, char* log, size_t log_len) {
   if (!e) return CE_E_INVALID;
   copy_log("", log, log_len);

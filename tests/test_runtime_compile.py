@@ -45,3 +45,24 @@ def test_host_escape_version_matches_the_oracle():
     fn(0, 700, C.byref(a))
     fn(700, w * h, C.byref(a))
     assert np.array_equal(out.reshape(h, w), O.escape(w, h, x0, y0, dx, dy, it))
+
+
+def test_runtime_module_has_no_packed_fp32_or_scratch(tmp_path):
+    """The module hipRTC builds is compiled like the library's own device
+    code: no packed FP32 instructions, no scratch (private) memory."""
+    import os
+    import subprocess
+    objdump = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "llvm", "bin", "llvm-objdump")
+    if not os.path.exists(objdump):
+        import pytest
+        pytest.skip("llvm-objdump not available")
+    for name, entry in (("escape.hiprtc", "escape_item"), ("axpy2.hiprtc", "axpy2_item")):
+        co = ce.ce_rt_code_object(rt_util.source(name), entry)
+        path = tmp_path / (entry + ".co")
+        path.write_bytes(co)
+        asm = subprocess.run([objdump, "-d", "--mcpu=gfx950", str(path)], check=True, capture_output=True,
+                             text=True).stdout
+        assert "k_persistent" in asm and "k_bare" in asm
+        assert "v_fma_f32" in asm or "v_mul_f32" in asm or "v_add_f32" in asm
+        for bad in ("v_pk_fma_f32", "v_pk_mul_f32", "v_pk_add_f32", "scratch_store", "scratch_load"):
+            assert bad not in asm, (name, bad)
