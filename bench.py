@@ -432,7 +432,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32" if wl in ("escape", "runtime") else "f32",
-        "data": "synthetic (seeded SplitMix64 inputs; see DESIGN.md)",
+        "data": "synthetic (seeded SplitMix64 inputs, paper_1805_02755_amd/synth.py)",
         "config": config,
         "roofline": roof,
         "cpu_baseline": cpu_base,
@@ -567,7 +567,7 @@ def bench_nbody_step(args, ce, synth, torch, np, stream):
     res = {
         "metric": METRIC, "value": n * K / T_total, "unit": "work-items/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": T_total / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic (seeded SplitMix64 inputs; see DESIGN.md)",
+        "dtype": "f32", "data": "synthetic (seeded SplitMix64 inputs, paper_1805_02755_amd/synth.py)",
         "config": {"workload": "nbody integration step, 65536 bodies fp32, eps2 1e-6, dt 1e-3, strict rsqrt, "
                                "resident ping-pong buffers", "scheduler": "dynamic 256-body packages",
                    "devices": "gpu+host", "residency": "device"},
@@ -697,7 +697,7 @@ def bench_binomial(args, ce, synth, torch, np, stream):
     res = {
         "metric": METRIC, "value": items * K / T_total, "unit": "work-items/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": T_total / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic (seeded SplitMix64 inputs; see DESIGN.md)",
+        "dtype": "f32", "data": "synthetic (seeded SplitMix64 inputs, paper_1805_02755_amd/synth.py)",
         "config": {"workload": "binomial options: 16777216 European calls, 254 steps, 4194304 work-groups of 255, "
                                "out pattern 1:255", "scheduler": "hguided", "devices": "gpu+host",
                    "residency": "device", "options_per_s": 4 * n_groups * K / T_total},
@@ -776,7 +776,7 @@ def bench_batch(args, ce, synth, torch, np, stream):
     res = {
         "metric": METRIC, "value": n_items * K / T, "unit": "work-items/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": T / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u32", "data": "synthetic (seeded SplitMix64 inputs; see DESIGN.md)",
+        "dtype": "u32", "data": "synthetic (seeded SplitMix64 inputs, paper_1805_02755_amd/synth.py)",
         "config": {"workload": "batched escape-time: 256 jobs, side log-uniform [64,2048], max_iter U[64,4096]",
                    "form": "one persistent hipGraph launch", "tile_rows": chosen[0], "tile_cols": chosen[1],
                    "package_tiles": chosen[2]},
@@ -907,7 +907,7 @@ def bench_serve(args, ce, synth, torch, np, stream):
     res = {
         "metric": METRIC, "value": r.items_per_s, "unit": "work-items/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": r.wall_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "mixed (u32 escape, f32 blur and n-body)", "data": "synthetic (seeded SplitMix64 trace; see DESIGN.md)",
+        "dtype": "mixed (u32 escape, f32 blur and n-body)", "data": "synthetic (seeded SplitMix64 trace, paper_1805_02755_amd/synth.py)",
         "config": {"workload": f"serving trace: {len(trace)} Poisson arrivals at 200/s, escape side [256,4096], "
                                "blur side [1024,16384], n-body [4096,131072]", "form": "persistent serving kernel"},
         "roofline": None,

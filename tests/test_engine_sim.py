@@ -1,4 +1,5 @@
-"""CPU tests of the host engine with fake devices (SURVEY §4 "tests/sim").
+"""CPU tests of the host engine with fake devices (tests/sim: a stand-in HIP
+runtime and payloads).
 
 engine.cpp is compiled against a stub HIP runtime (tests/sim) whose "GPU" is
 a CPU thread claiming from the same level-1 dispenser, and whose payloads do
