@@ -266,8 +266,10 @@ typedef struct {
  * the compiler's log (NUL-terminated, truncated) into log[0..log_len) if
  * log is not NULL; the previous payload is then unbound too. Slots are then
  * bound with ce_program_in / ce_program_out as for the fixed payloads
- * (input sizes in_bytes, output sizes gws * out_item_bytes). A run whose
- * device set includes the host needs desc->host. */
+ * (input sizes in_bytes, output sizes gws * out_item_bytes, so the index
+ * space must be set before the outputs are bound). A run whose device set
+ * includes the host needs desc->host; the host function is called from
+ * several host worker threads at once, on disjoint item ranges. */
 ce_status ce_program_source(ce_engine* e, const ce_rt_desc* desc, char* log, size_t log_len);
 /* Compiles a runtime payload's source without binding it (no GPU needed):
  * CE_OK, or CE_E_INVALID with the compiler's log as above. */
