@@ -346,45 +346,67 @@ struct BinomialTile {
   float4* out;
   __device__ void load_constants() {}
   __host__ __device__ uint64_t granules() const { return p.n_groups; }
-  __host__ __device__ uint32_t ntiles(uint64_t g0, uint64_t g1) const { return (uint32_t)(g1 - g0); }
+  // A tile is two consecutive groups (the last tile of a package may hold
+  // one): both trees advance together, so each barrier serves twice the work.
+  static constexpr uint32_t kGroupsPerTile = 2;
+  __host__ __device__ uint32_t ntiles(uint64_t g0, uint64_t g1) const {
+    return (uint32_t)((g1 - g0 + kGroupsPerTile - 1) / kGroupsPerTile);
+  }
   // Lane i receives lane i + 1's value (DPP wave_shl:1); the last lane,
   // which has no source, keeps `top`.
   static __device__ float from_next_lane(float x, float top) {
     return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(top), __float_as_int(x), 0x130, 0xf, 0xf, false));
   }
-  __device__ void run(uint64_t g0, uint64_t, uint32_t t) const {
-    // edge[L & 1][w] holds the level-L value of the first lane of wave w;
-    // slot kWaves is never written and feeds only the unused last leaf.
-    __shared__ float4 edge[2][kWaves + 1];
-    const uint64_t grp = g0 + t;
+  __device__ float4 leaves(float4 S, float f, float X) const {
+    const float a = S.x * f - X, b = S.y * f - X, c = S.z * f - X, d = S.w * f - X;
+    return make_float4(a > 0.0f ? a : 0.0f, b > 0.0f ? b : 0.0f, c > 0.0f ? c : 0.0f, d > 0.0f ? d : 0.0f);
+  }
+  __device__ void level(float4& v, const float4& top, float pu, float pd) const {
+    const float ux = from_next_lane(v.x, top.x), uy = from_next_lane(v.y, top.y);
+    const float uz = from_next_lane(v.z, top.z), uw = from_next_lane(v.w, top.w);
+    v.x = pu * ux + pd * v.x;
+    v.y = pu * uy + pd * v.y;
+    v.z = pu * uz + pd * v.z;
+    v.w = pu * uw + pd * v.w;
+  }
+  __device__ void run(uint64_t g0, uint64_t g1, uint32_t t) const {
+    // edge[L & 1][k][w] holds the level-L value of the first lane of wave w
+    // for the tile's group k; slot kWaves is never written and feeds only
+    // the unused last leaf.
+    __shared__ float4 edge[2][kGroupsPerTile][kWaves + 1];
+    const uint64_t grp = g0 + (uint64_t)t * kGroupsPerTile;
+    const bool two = grp + 1 < g1;  // uniform across the workgroup
     const uint32_t j = threadIdx.x;
     const uint32_t w = __builtin_amdgcn_readfirstlane(j >> 6);
     const uint32_t n = p.steps;
-    const float4 S = spots[grp];
+    const float4 S0 = spots[grp];
+    const float4 S1 = two ? spots[grp + 1] : S0;
     const float X = p.strike, pu = p.pu, pd = p.pd;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), v1 = v0;
     if (j <= n) {
       const float f = factors[j];
-      const float a = S.x * f - X, b = S.y * f - X, c = S.z * f - X, d = S.w * f - X;
-      v = make_float4(a > 0.0f ? a : 0.0f, b > 0.0f ? b : 0.0f, c > 0.0f ? c : 0.0f, d > 0.0f ? d : 0.0f);
+      v0 = leaves(S0, f, X);
+      v1 = leaves(S1, f, X);
     }
     // Level L's copy of edge is rewritten at level L - 2, after the barrier of
     // level L - 1 that follows every read of it, so one barrier per level suffices.
     for (uint32_t L = n; L-- > 0;) {
-      float4* e = edge[L & 1];
-      if ((j & 63) == 0) e[w] = v;
+      float4(*e)[kWaves + 1] = edge[L & 1];
+      if ((j & 63) == 0) {
+        e[0][w] = v0;
+        e[1][w] = v1;
+      }
       __syncthreads();
       if (w * 64 <= L) {
-        const float4 top = e[w + 1];
-        const float ux = from_next_lane(v.x, top.x), uy = from_next_lane(v.y, top.y);
-        const float uz = from_next_lane(v.z, top.z), uw = from_next_lane(v.w, top.w);
-        v.x = pu * ux + pd * v.x;
-        v.y = pu * uy + pd * v.y;
-        v.z = pu * uz + pd * v.z;
-        v.w = pu * uw + pd * v.w;
+        const float4 top0 = e[0][w + 1], top1 = e[1][w + 1];
+        level(v0, top0, pu, pd);
+        level(v1, top1, pu, pd);
       }
     }
-    if (j == 0) out[grp] = v;
+    if (j == 0) {
+      out[grp] = v0;
+      if (two) out[grp + 1] = v1;
+    }
   }
 };
 
