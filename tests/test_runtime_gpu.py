@@ -117,6 +117,20 @@ def test_runtime_two_inputs_two_outputs_and_module_swap(eng):
     assert np.array_equal(z1.cpu().numpy().view(np.uint32), ref1.view(np.uint32))
 
 
+@pytest.mark.parametrize("sched", ["dynamic", "hguided"])
+def test_runtime_escape_gather_merge(eng, sched):
+    # the host's rows reach HBM through gather workgroups of the runtime module's own persistent kernel
+    w, h, it = 256, 97, 100
+    ref = O.escape(w, h, X0, Y0, DX, DY, it)
+    eng.output_merge(ce.CE_MERGE_GPU_GATHER)
+    try:
+        out, st, tr = run_escape(eng, w, h, it, w, BOTH, sched, "dev")
+    finally:
+        eng.output_merge(ce.CE_MERGE_DMA)
+    assert np.array_equal(out, ref)
+    check_trace(tr, h, st.n_devices)
+
+
 def test_runtime_compile_error_leaves_engine_unbound(eng):
     eng.work_items([1000], [10])
     with pytest.raises(ce.CoexecError) as ei:
