@@ -102,18 +102,27 @@ void orc_blur5(const float* in, uint32_t w, uint32_t h, const float wt[25], floa
  * >> 1) followed by three Newton-Raphson steps y <- y * (1.5 - (x/2) y^2), each
  * written as t = y*y; u = fma(-(x/2), t, 1.5); y = y*u. Fast mode uses the
  * correctly rounded 1/sqrtf. */
-float orc_rsqrt_lomont(float x) {
+/* Lomont's integer first estimate of 1/sqrt(x), before any Newton step. */
+float orc_rsqrt_lomont_estimate(float x) {
   uint32_t bits;
   memcpy(&bits, &x, sizeof bits);
   bits = 0x5f375a86u - (bits >> 1);
   float y;
   memcpy(&y, &bits, sizeof y);
+  return y;
+}
+
+/* One Newton-Raphson step for 1/sqrt(x) from the estimate y, with hx = x/2. */
+float orc_rsqrt_newton(float hx, float y) {
+  const float t = y * y;
+  const float u = fmaf(-hx, t, 1.5f);
+  return y * u;
+}
+
+float orc_rsqrt_lomont(float x) {
+  float y = orc_rsqrt_lomont_estimate(x);
   const float hx = 0.5f * x;
-  for (int step = 0; step < 3; ++step) {
-    const float t = y * y;
-    const float u = fmaf(-hx, t, 1.5f);
-    y = y * u;
-  }
+  for (int step = 0; step < 3; ++step) y = orc_rsqrt_newton(hx, y);
   return y;
 }
 

@@ -39,6 +39,8 @@ void orc_blur5(const float* in, uint32_t w, uint32_t h, const float wt[25], floa
 
 /* ---- payload 3: all-pairs N-body acceleration (NBody benchmark, section 6.2
  * and Table 2), force part only. Bodies are float4 (x, y, z, m). */
+float orc_rsqrt_lomont_estimate(float x);
+float orc_rsqrt_newton(float hx, float y);
 float orc_rsqrt_lomont(float x);
 void orc_nbody_acc_body(const float* pos4, uint32_t n, float eps2, int strict, uint32_t i,
                         float out4[4]);

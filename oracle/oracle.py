@@ -46,6 +46,10 @@ def lib():
         L.orc_blur5.argtypes = [_f32p, C.c_uint32, C.c_uint32, _f32p, _f32p]
         L.orc_rsqrt_lomont.restype = C.c_float
         L.orc_rsqrt_lomont.argtypes = [C.c_float]
+        L.orc_rsqrt_lomont_estimate.restype = C.c_float
+        L.orc_rsqrt_lomont_estimate.argtypes = [C.c_float]
+        L.orc_rsqrt_newton.restype = C.c_float
+        L.orc_rsqrt_newton.argtypes = [C.c_float, C.c_float]
         L.orc_nbody_acc_body.restype = None
         L.orc_nbody_acc_body.argtypes = [_f32p, C.c_uint32, C.c_float, C.c_int, C.c_uint32, _f32p]
         L.orc_nbody_acc.restype = None
@@ -105,6 +109,16 @@ def blur5_pixel(img: np.ndarray, wt: np.ndarray, y: int, x: int) -> np.float32:
 
 def rsqrt_lomont(x: float) -> np.float32:
     return np.float32(lib().orc_rsqrt_lomont(x))
+
+
+def rsqrt_lomont_estimate(x: float) -> np.float32:
+    """Lomont's integer first estimate alone (no Newton step)."""
+    return np.float32(lib().orc_rsqrt_lomont_estimate(x))
+
+
+def rsqrt_newton(hx: float, y: float) -> np.float32:
+    """One Newton step for 1/sqrt(x) from y, given hx = x/2."""
+    return np.float32(lib().orc_rsqrt_newton(hx, y))
 
 
 def nbody_acc(pos4: np.ndarray, eps2: float, strict: bool = True) -> np.ndarray:

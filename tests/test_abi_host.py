@@ -74,7 +74,9 @@ def test_hguided_size_matches_oracle():
 
 
 def test_binomial_table_matches_oracle_bitwise():
-    for steps, sigma, rate, T in [(254, 0.3, 0.05, 1.0), (1, 0.25, 0.04, 0.5), (255, 0.1, 0.0, 2.0), (17, 0.6, 0.1, 0.25)]:
+    cases = [(steps, 0.3, 0.05, 1.0) for steps in range(1, 256)]
+    cases += [(1, 0.25, 0.04, 0.5), (255, 0.1, 0.0, 2.0), (17, 0.6, 0.1, 0.25)]
+    for steps, sigma, rate, T in cases:
         f, pu, pd = ce.ce_binomial_table(steps, sigma, rate, T)
         g, qu, qd = O.binomial_table(steps, sigma, rate, T)
         assert np.array_equal(f.view(np.uint32), g.view(np.uint32)) and pu == qu and pd == qd

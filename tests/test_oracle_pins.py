@@ -163,6 +163,48 @@ def test_rsqrt_lomont_accuracy():
     assert worst < 4 * 2 ** -24
 
 
+def _bits(v) -> int:
+    return int(np.float32(v).view(np.uint32))
+
+
+def test_rsqrt_lomont_integer_estimate_bits():
+    """Lomont (2003), first estimate: the float whose bits are 0x5f375a86
+    minus the input's bits shifted right by one. Worked by hand:
+    1.0 = 0x3f800000 -> 0x5f375a86 - 0x1fc00000 = 0x3f775a86;
+    2.0 = 0x40000000 -> - 0x20000000 = 0x3f375a86;
+    0.5 = 0x3f000000 -> - 0x1f800000 = 0x3fb75a86;
+    4.0 = 0x40800000 -> - 0x20400000 = 0x3ef75a86;
+    1.5 = 0x3fc00000 -> - 0x1fe00000 = 0x3f575a86;
+    the bit shifted out is dropped: 0x3f800001 gives the estimate of 1.0.
+    Another constant (0x5f3759df, say) fails every line."""
+    want = {1.0: 0x3F775A86, 2.0: 0x3F375A86, 0.5: 0x3FB75A86, 4.0: 0x3EF75A86, 1.5: 0x3F575A86}
+    for x, b in want.items():
+        assert _bits(O.rsqrt_lomont_estimate(x)) == b, (x, hex(_bits(O.rsqrt_lomont_estimate(x))))
+    x1 = float(np.uint32(0x3F800001).view(np.float32))
+    assert _bits(O.rsqrt_lomont_estimate(x1)) == 0x3F775A86
+
+
+def test_rsqrt_newton_step_by_hand():
+    """One step y <- y (1.5 - (x/2) y^2) on exactly representable values:
+    x = 1, y = 0.5: t = 0.25, u = 1.5 - 0.125 = 1.375, y' = 0.6875;
+    x = 1, y = 0.75: t = 0.5625, u = 1.5 - 0.28125 = 1.21875, y' = 0.9140625;
+    the exact roots are fixed points: x = 4, y = 0.5 and x = 1, y = 1."""
+    assert O.rsqrt_newton(0.5, 0.5) == np.float32(0.6875)
+    assert O.rsqrt_newton(0.5, 0.75) == np.float32(0.9140625)
+    assert O.rsqrt_newton(2.0, 0.5) == np.float32(0.5)
+    assert O.rsqrt_newton(0.5, 1.0) == np.float32(1.0)
+
+
+def test_rsqrt_lomont_is_estimate_then_three_steps():
+    for x in (1e-6, 0.37, 1.0, 2.0, 3.3, 1234.5):
+        xf = np.float32(x)
+        hx = float(np.float32(0.5) * xf)
+        y = O.rsqrt_lomont_estimate(float(xf))
+        for _ in range(3):
+            y = O.rsqrt_newton(hx, float(y))
+        assert _bits(O.rsqrt_lomont(float(xf))) == _bits(y), x
+
+
 def test_rsqrt_lomont_first_estimate_and_scaling():
     # 1/sqrt(4x) is exactly half of 1/sqrt(x) through the bit estimate and Newton steps
     for x in (0.3, 1.7, 123.0, 1e-5):
