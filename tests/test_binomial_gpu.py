@@ -25,9 +25,12 @@ def eng():
 
 
 def setup(n_groups, steps, seed):
+    """The engine gets the library's tree table; the reference is priced on
+    the oracle's own table, so the two sides share no input but the spots."""
     spots = synth.binomial_spots(n_groups, seed=seed)
     f, pu, pd = ce.ce_binomial_table(steps, SIGMA, RATE, T)
-    ref = O.binomial(spots, X, steps, f, pu, pd)
+    fo, puo, pdo = O.binomial_table(steps, SIGMA, RATE, T)
+    ref = O.binomial(spots, X, steps, fo, puo, pdo)
     return spots, f, ce.ce_binomial_params(n_groups, steps, X, pu, pd), ref
 
 
@@ -72,7 +75,8 @@ def test_binomial_paper_size_sampled(eng):
                               np.float32, BOTH, "dynamic")
     check_trace(tr, n_groups, 2)
     rng = np.random.default_rng(21)
+    fo, puo, pdo = O.binomial_table(steps, SIGMA, RATE, T)
     for g in list(rng.choice(n_groups, 40, replace=False)) + [0, n_groups - 1]:
         for c in range(4):
-            assert out[g, c].view(np.uint32) == O.binomial_price(float(spots[g, c]), X, steps, f, pu, pd).view(
+            assert out[g, c].view(np.uint32) == O.binomial_price(float(spots[g, c]), X, steps, fo, puo, pdo).view(
                 np.uint32), (g, c)
