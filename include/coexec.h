@@ -306,6 +306,17 @@ ce_status ce_engine_bare_run_source(ce_engine* e, uint64_t gws, uint32_t lws, co
 #define CE_MERGE_GPU_GATHER 1
 ce_status ce_engine_output_merge(ce_engine* e, int mode);
 
+/* Number of workgroups of the GPU's persistent kernel for the following
+ * runs; 0 (the default) lets the engine choose: the resident workgroups
+ * (occupancy x compute units) spread so that the tiles of the whole index
+ * space make whole rounds, i.e. ceil(T / ceil(T / R)) for T tiles and R
+ * resident workgroups, and never more than T. A caller's value is used as
+ * given (it may exceed what fits on the GPU at once: the dispenser's
+ * waits do not depend on every workgroup being resident), plus the gather
+ * workgroups of CE_MERGE_GPU_GATHER. Affects speed only, never results.
+ * Errors: CE_E_INVALID for a value above 2^20. */
+ce_status ce_engine_gpu_workgroups(ce_engine* e, uint32_t workgroups);
+
 /* Records the caller's HIP events (hipEvent_t handles) on the engine's
  * stream immediately before and after the GPU kernel of each following run,
  * so the caller can time the kernel with hipEventElapsedTime. NULL, NULL

@@ -28,15 +28,16 @@ constexpr uint32_t kBlockThreads = 256;
 struct alignas(64) L1State {
   uint64_t next;        // next granule not yet handed to any device
   uint64_t pad0[7];
-  // written by the last GPU workgroup of a run (system-scope stores)
-  uint64_t gpu_run_id;  // run id of the finished GPU part
+  // written by the last GPU workgroup of a run (system-scope stores); the
+  // host reads them once the kernel has ended, except the done word, which
+  // it polls
+  uint64_t gpu_done;    // done_word(run id, tick at which the last workgroup left)
   uint64_t gpu_t_first; // s_memrealtime of the first package claim
   uint64_t gpu_t_last;  // s_memrealtime of the last package end
   uint64_t gpu_granules;
   uint64_t gpu_packages;
   uint64_t gpu_flags;   // bit 0: a wait on the dispenser timed out
-  uint64_t gpu_t_leave; // s_memrealtime just before gpu_run_id is written
-  uint64_t pad1[1];
+  uint64_t pad1[2];
   // clock calibration mailbox
   uint64_t ping;
   uint64_t pong;
@@ -51,6 +52,14 @@ struct alignas(64) L1State {
   uint64_t pad4[6];
 };
 
+// The GPU's completion as one word, so the host sees the run id and the
+// moment it was written together: run id low 24 bits over the low 40 bits
+// of the s_memrealtime tick (at 100 MHz they wrap every three hours; the
+// host restores the high bits from its own estimate of the tick).
+constexpr uint64_t kTick40 = (1ull << 40) - 1;
+CE_HD uint64_t done_word(uint64_t run_id, uint64_t tick) { return ((run_id & 0xFFFFFFull) << 40) | (tick & kTick40); }
+CE_HD bool done_is(uint64_t w, uint64_t run_id) { return (w >> 40) == (run_id & 0xFFFFFFull); }
+
 // The host's final ring size and the run it belongs to, in one word so the
 // GPU reads both with one atomic load: run id low 24 bits over a 40-bit count.
 CE_HD uint64_t host_final_word(uint64_t run_id, uint64_t count) { return ((run_id & 0xFFFFFFull) << 40) | count; }
@@ -60,6 +69,8 @@ CE_HD uint64_t host_final_word(uint64_t run_id, uint64_t count) { return ((run_i
 CE_HD uint64_t ring_word(uint64_t off, uint64_t len) { return (len << 40) | off; }
 CE_HD uint64_t ring_off(uint64_t w) { return w & ((1ull << 40) - 1); }
 CE_HD uint64_t ring_len(uint64_t w) { return w >> 40; }
+
+constexpr uint32_t kExitLines = 8;
 
 // Per-run GPU queue state in HBM (device-scope atomics only). The last
 // workgroup to leave a run resets it to zero for the next run. Contended
@@ -74,17 +85,20 @@ struct alignas(128) L2State {
   uint32_t lock;        // held by the workgroup claiming the next package
   uint32_t pad_lock[31];
   uint32_t n_pkgs;      // packages published
-  uint32_t exit_count;  // workgroups that left
+  uint32_t exit_count;  // exit lines whose workgroups have all left
   uint32_t st_next;     // static: next band of this device
   uint32_t exit_compute;// computing (non-gather) workgroups that left
   uint64_t granules;    // granules published
   uint64_t t_first;     // first claim tick
   uint64_t t_last;      // tick at which the last computing workgroup left
   uint64_t gather_next; // next host completion-ring entry to copy
-  uint64_t t_pre;       // start tick of the package claimed before the launch
-  uint64_t t_end0;      // latest end tick reported for that package
+  uint64_t pad_pre[2];
   uint64_t t_gather;    // latest end tick of a gather copy
   uint64_t pad_misc[7];
+  // Workgroups that left, counted on kExitLines lines of their own by
+  // blockIdx mod kExitLines (the XCD a workgroup is dealt to): a thousand
+  // workgroups leaving together would otherwise queue on one line.
+  uint32_t exit_x[kExitLines][32];
 };
 
 constexpr uint64_t kTotalDone = 1ull << 63;
@@ -123,7 +137,7 @@ struct SchedArgs {
   uint64_t st_begin, st_end;  // Static: this device's granule range
   uint64_t st_nbands;   // Static: band grid (0 = one package)
   uint64_t run_id;
-  uint64_t spin_limit;  // bound on any wait inside the kernel (iterations)
+  uint64_t wait_ticks;  // longest wait on the dispenser, in s_memrealtime ticks
   L1State* l1;          // device address of the host-coherent dispenser
   L2State* l2;          // HBM
   PkgSlot* pkgs;        // trace records of the GPU's packages
@@ -140,14 +154,16 @@ struct SchedArgs {
   // Dynamic: tiles of every GPU package but the one that ends the index
   // space, so ticket t lies in package t / dyn_tiles (0: walk the packages)
   uint32_t dyn_tiles;
-  uint32_t pad_dyn;
+  // 1: the pre-claimed package is all this device will run (a static plan
+  // with one package for it), so no workgroup needs to look for another
+  uint32_t pre_only;
   // gather of host-computed output into HBM (gather_wgs == 0: off)
   const uint64_t* ring; // device view of the host completion ring
   const char* gsrc;     // device view of the host output buffer
   char* gdst;           // device output buffer
   uint32_t gather_wgs;  // workgroups 0 .. gather_wgs-1 only gather
   uint32_t ring_cap;    // entries in the ring
-  uint64_t wait_ticks;  // longest wait for the host, in s_memrealtime ticks
+  uint64_t gather_wait_ticks;  // longest wait for the host's next finished tile
 };
 
 // HGuided package size (section 5.3 equation), integer only. Callers keep

@@ -13,9 +13,10 @@
 namespace ce {
 
 struct EscapeTile {
-  // workgroups per CU the persistent kernel is compiled for (1: no bound; a
-  // bound of 5 made this latency-bound loop measurably slower)
-  static constexpr int kMinBlocksPerCu = 1;
+  // workgroups per CU the persistent kernel is compiled for: eight, the
+  // residency of the plain launch, so that the 2048 tiles of a 1024 x 1024
+  // grid run in one round
+  static constexpr int kMinBlocksPerCu = 8;
   ce_escape_params p;
   uint32_t* out;
   __device__ void load_constants() {}

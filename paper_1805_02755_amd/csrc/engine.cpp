@@ -44,6 +44,11 @@ inline void cpu_relax() { _mm_pause(); }
 
 constexpr uint32_t kHostNbodyTile = 16;  // bodies per host tile
 constexpr int kMaxSlots = 2;
+// Bounds on the waits inside the GPU kernel, and the host's deadline for a
+// kernel's completion word, which is longer than both.
+constexpr uint64_t kDispenserWaitSeconds = 5;
+constexpr uint64_t kGatherWaitSeconds = 60;
+constexpr int64_t kGpuDeadlineNs = 120'000'000'000LL;
 
 struct Binding {
   const void* host = nullptr;  // input: read by host workers
@@ -225,6 +230,7 @@ struct ce_engine {
   std::vector<ce_package_rec> trace;
   uint64_t gpu_pkgs_last = 0;
   uint32_t gpu_grid_last = 0;
+  uint32_t grid_override = 0;  // persistent workgroups chosen by the caller (0: the engine chooses)
 
   std::vector<std::string> errors;
 
@@ -246,6 +252,19 @@ struct ce_engine {
   uint32_t n_devices() const { return (use_gpu() ? 1u : 0u) + (use_host() ? 1u : 0u); }
   int gpu_index() const { return use_gpu() ? 0 : -1; }
   int host_index() const { return use_host() ? (use_gpu() ? 1 : 0) : -1; }
+
+  // The full tick whose low 40 bits are t40, nearest to the host time
+  // host_ns under the current mapping (the mapping is off by far less than
+  // the 2^40-tick wrap).
+  uint64_t unwrap_tick40(uint64_t t40, double host_ns) const {
+    const double est = (host_ns - clock_offset_ns) * ((double)wallclock_hz * 1e-9);
+    const uint64_t e = est > 0.0 ? (uint64_t)est : 0;
+    const uint64_t half = 1ull << 39;
+    uint64_t t = (e & ~kTick40) | t40;
+    if (t > e + half && t > kTick40) t -= kTick40 + 1;
+    else if (t + half < e) t += kTick40 + 1;
+    return t;
+  }
 
   double tick_to_host_s(uint64_t tick) const {
     const double ns = (double)tick * (1e9 / (double)wallclock_hz) + clock_offset_ns;
@@ -378,15 +397,18 @@ struct ce_engine {
   void gpu_preclaim(SchedArgs& gs) {
     gs.pre_nt = 0;
     gs.st_first = 0;
+    gs.pre_only = 0;
     uint64_t g0 = 0, g1 = 0;
     if (gs.kind == kStatic) {
       if (gs.st_begin >= gs.st_end) return;
       if (gs.st_nbands == 0) {
         g0 = gs.st_begin;
         g1 = (gs.st_end - g0 > kPubMaxSize) ? g0 + kPubMaxSize : gs.st_end;
+        gs.pre_only = g1 == gs.st_end ? 1u : 0u;
       } else {
         g0 = band_edge(gs.st_begin, gs.G, gs.st_nbands);
         g1 = band_edge(gs.st_begin + 1, gs.G, gs.st_nbands);
+        gs.pre_only = gs.st_begin + 1 == gs.st_end ? 1u : 0u;
       }
       gs.st_first = 1;
     } else if (gs.kind == kDynamic) {
@@ -656,7 +678,12 @@ struct ce_engine {
     base.k = sched.k ? sched.k : 2;
     base.G = G;
     base.run_id = run_id;
-    base.spin_limit = 1ull << 26;
+    // Waits on the dispenser last microseconds (a claim over PCIe, a
+    // package becoming visible); a workgroup that waits for a claimer that is
+    // not running claims itself after milliseconds. Five seconds is thus only
+    // reached when something is broken, and is well inside the host's own
+    // deadline for the kernel.
+    base.wait_ticks = (uint64_t)wallclock_hz * kDispenserWaitSeconds;
     base.l1 = l1_dev;
     base.l2 = l2;
     *gpu_s = base;
@@ -896,10 +923,21 @@ struct ce_engine {
         if ((he = persistent_blocks_per_cu(kargs, &bpc)) != hipSuccess) return hip_fail(he, "run: occupancy");
         if (occ_key < kOccSlots) occ_cache[occ_key] = bpc;
       }
-      grid = (uint32_t)std::max(1, bpc) * (uint32_t)n_cu;
-      gather_wgs = gather ? std::min<uint32_t>(16, std::max<uint32_t>(1, grid / 4)) : 0;
-      const uint32_t all_tiles = gpu_tiles(kargs, 0, G);
-      if (all_tiles > 0 && grid > all_tiles + gather_wgs) grid = all_tiles + gather_wgs;
+      const uint32_t resident = (uint32_t)std::max(1, bpc) * (uint32_t)n_cu;
+      gather_wgs = gather ? std::min<uint32_t>(16, std::max<uint32_t>(1, resident / 4)) : 0;
+      const uint64_t all_tiles = gpu_tiles(kargs, 0, G);
+      if (grid_override) {
+        grid = grid_override + gather_wgs;
+      } else {
+        // Spread the tiles over whole rounds: with R resident workgroups and
+        // T tiles, ceil(T / R) rounds of ceil(T / rounds) workgroups, so no
+        // round runs with part of the GPU idle (2048 blur tiles on 1280
+        // resident workgroups: 1024 workgroups of two tiles each rather than
+        // a second round at 60 %).
+        const uint64_t r = std::max<uint64_t>(1, resident - gather_wgs);
+        const uint64_t rounds = std::max<uint64_t>(1, ceil_div(all_tiles, r));
+        grid = (uint32_t)std::min<uint64_t>(r, std::max<uint64_t>(1, ceil_div(all_tiles, rounds))) + gather_wgs;
+      }
       if (grid <= gather_wgs) grid = gather_wgs + 1;
     }
 
@@ -954,7 +992,8 @@ struct ce_engine {
       const bool long_tiles = kernel_id == CE_KERNEL_BINOMIAL;
       if (long_tiles) gs.chunk = 1;
       gs.stride = (kernel_id == CE_KERNEL_RUNTIME || gather || long_tiles) ? 0u : 1u;
-      gs.wait_ticks = (uint64_t)wallclock_hz * 60;
+      // the gatherers wait for the host's packages, whose length depends on the problem
+      gs.gather_wait_ticks = (uint64_t)wallclock_hz * kGatherWaitSeconds;
       if (gather) {
         const uint64_t max_host_tiles =
             is_nbody() ? ceil_div(n_bodies(), kHostNbodyTile) : G;
@@ -1017,25 +1056,26 @@ struct ce_engine {
       while (pool_done.load(std::memory_order_acquire) < want) cpu_relax();
     }
     if (use_gpu()) {
-      // the last workgroup out writes the run id; poll it, then sync
-      const int64_t deadline = now_ns() + 120'000'000'000LL;
+      // the last workgroup out writes the done word; poll it, then sync
+      const int64_t deadline = now_ns() + kGpuDeadlineNs;
       bool waited = false;
-      while (__atomic_load_n(&l1->gpu_run_id, __ATOMIC_ACQUIRE) != run_id) {
+      uint64_t dw;
+      while (!done_is(dw = __atomic_load_n(&l1->gpu_done, __ATOMIC_ACQUIRE), run_id)) {
         waited = true;
         if (now_ns() > deadline) break;
         cpu_relax();
       }
-      if (waited && clock_ok && __atomic_load_n(&l1->gpu_run_id, __ATOMIC_ACQUIRE) == run_id) {
+      if (waited && clock_ok && done_is(dw, run_id)) {
         // The host saw the GPU's last store as it happened (give or take the
         // one-way latency measured at calibration): re-anchor the tick -> host
         // mapping here, so the two clocks' drift since creation does not
         // accumulate into the device times.
         const double seen = (double)now_ns() - clock_latency_ns;
-        const uint64_t tl = __atomic_load_n(&l1->gpu_t_leave, __ATOMIC_ACQUIRE);
+        const uint64_t tl = unwrap_tick40(dw & kTick40, seen);
         clock_offset_ns = seen - (double)tl * (1e9 / (double)wallclock_hz);
       }
       if ((he = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(he, "run: kernel");
-      if (__atomic_load_n(&l1->gpu_run_id, __ATOMIC_ACQUIRE) != run_id)
+      if (!done_is(__atomic_load_n(&l1->gpu_done, __ATOMIC_ACQUIRE), run_id))
         return fail(CE_E_TIMEOUT, "run: GPU did not report completion");
       if (gather) memset(ring_buf.p, 0, ring_count.load() * sizeof(uint64_t));  // ready for the next run
       if (__atomic_load_n(&l1->gpu_flags, __ATOMIC_ACQUIRE))
@@ -1359,6 +1399,13 @@ ce_status ce_engine_output_merge(ce_engine* e, int mode) {
   if (mode == CE_MERGE_DMA && !e->sdma.ready())
     return e->fail(CE_E_UNSUPPORTED, "output_merge: no DMA engine (%s)", e->sdma_why);
   e->merge_mode = mode;
+  return CE_OK;
+}
+
+ce_status ce_engine_gpu_workgroups(ce_engine* e, uint32_t workgroups) {
+  if (!e) return CE_E_INVALID;
+  if (workgroups > (1u << 20)) return e->fail(CE_E_INVALID, "gpu_workgroups: %u is above 2^20", workgroups);
+  e->grid_override = workgroups;
   return CE_OK;
 }
 

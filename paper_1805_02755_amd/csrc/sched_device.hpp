@@ -16,6 +16,18 @@ namespace ce {
 __device__ __forceinline__ uint64_t max_u64(uint64_t a, uint64_t b) { return a > b ? a : b; }
 
 // ---------------------------------------------------------------- dispenser
+// Bounded waits: true once more than `limit` ticks have passed since the
+// first call with *t0 == 0 (which starts the clock). Every wait in the
+// dispenser ends this way, well before the host gives up on the kernel.
+__device__ __forceinline__ bool waited_out(uint64_t* t0, uint64_t limit) {
+  const uint64_t now = now_tick();
+  if (*t0 == 0) {
+    *t0 = now;
+    return false;
+  }
+  return now - *t0 > limit;
+}
+
 // Claims the next level-1 package for the GPU. Only the holder of the claim
 // lock runs this.
 __device__ bool claim_package(const SchedArgs& s, uint64_t* g0, uint64_t* g1, bool* timed_out) {
@@ -49,7 +61,7 @@ __device__ bool claim_package(const SchedArgs& s, uint64_t* g0, uint64_t* g1, bo
   }
   // HGuided: the size follows the pending granules at the moment of the claim.
   uint64_t cur = sys_load(&s.l1->next);
-  for (uint64_t tries = 0;; ++tries) {
+  for (uint64_t t0 = 0;;) {
     if (cur >= s.G) return false;
     uint64_t sz = hguided_size(s.G - cur, s.P_self, s.sumP, s.n_dev, s.k, s.min_self);
     if (sz > kPubMaxSize) sz = kPubMaxSize;
@@ -58,7 +70,7 @@ __device__ bool claim_package(const SchedArgs& s, uint64_t* g0, uint64_t* g1, bo
       *g1 = cur + sz;
       return true;
     }
-    if (tries > s.spin_limit) {
+    if (waited_out(&t0, s.wait_ticks)) {
       *timed_out = true;
       return false;
     }
@@ -158,8 +170,7 @@ struct Cursor {  // zero-initialised at the start of a run
 // After a tile: if it held its package's last ticket, stamp the package end.
 __device__ __forceinline__ void tile_finished(const SchedArgs& s, const Cursor& c) {
   if (c.nt == 0 || c.cur_t + 1 != c.base + c.nt) return;
-  uint64_t* te = (c.p == 0 && s.pre_nt) ? &s.l2->t_end0 : &s.pkgs[c.p].t_end;
-  dev_store(te, now_tick());
+  dev_store(&s.pkgs[c.p].t_end, now_tick());
 }
 
 // Ticket chain with lookahead. Every workgroup's first ticket is its own
@@ -186,8 +197,9 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
     }
   }
   const uint64_t t = c.t_next++;
-  uint64_t spins = 0;
-  while (t + s.lookahead >= c.tot_seen) {
+  if (s.pre_only && t >= s.pre_nt) return false;
+  uint64_t spins = 0, t0 = 0;
+  while (!s.pre_only && t + s.lookahead >= c.tot_seen) {
     // The published tile count and the "no more packages" flag share one
     // word, so a workgroup never pairs a stale count with a fresh flag (which
     // would make it leave with a ticket that did get published).
@@ -243,7 +255,8 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
       continue;
     }
     if (t < tot) break;
-    if (++spins > s.spin_limit) {
+    ++spins;
+    if (waited_out(&t0, s.wait_ticks)) {
       sys_store(&s.l1->gpu_flags, 1);
       __hip_atomic_fetch_or(&q->total, kTotalDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
@@ -268,10 +281,10 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
       p = (uint32_t)(t / s.dyn_tiles);
       base = (uint64_t)p * s.dyn_tiles;
     }
-    for (uint64_t spins2 = 0;;) {
+    for (uint64_t t1 = 0;;) {
       const uint64_t w = (p == 0 && s.pre_nt) ? pub_word(s.pre_g0, s.pre_g1 - s.pre_g0) : dev_load(&s.pub[p]);
       if (w == 0) {  // published by the claimer but not visible here yet
-        if (++spins2 > s.spin_limit) {
+        if (waited_out(&t1, s.wait_ticks)) {
           sys_store(&s.l1->gpu_flags, 1);
           return false;
         }
@@ -297,57 +310,80 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
 }
 
 
+// Counts this workgroup out: one atomic on the line of its blockIdx mod
+// kExitLines, and one more on the shared count for the last workgroup of a
+// line. True for the last workgroup of the grid.
+__device__ __forceinline__ bool count_out(L2State* q) {
+  const uint32_t x = blockIdx.x % kExitLines;
+  const uint32_t in_line = (gridDim.x - x + kExitLines - 1) / kExitLines;
+  if (dev_add(&q->exit_x[x][0], 1u) + 1 != in_line) return false;
+  const uint32_t lines = gridDim.x < kExitLines ? gridDim.x : kExitLines;
+  return dev_add(&q->exit_count, 1u) + 1 == lines;
+}
+
 // The last workgroup out publishes the GPU's summary to the host, clears the
-// publication words and resets the level-2 state for the next run.
+// publication words and resets the level-2 state for the next run. It runs
+// after every other workgroup has finished, so its loads are issued together
+// and its stores drained once: each round trip here adds to the kernel.
 __device__ void leave(const SchedArgs& s) {
   L2State* q = s.l2;
   // This workgroup's dispenser atomics are done before it counts itself out
   // (waiting for them is enough; an agent-scope release would also write back
   // this XCD's L2, once per workgroup).
   __builtin_amdgcn_s_waitcnt(0);
-  const uint32_t ex = dev_add(&q->exit_count, 1u);
-  if (ex + 1 != gridDim.x) return;
-  uint64_t tf = dev_load(&q->t_first);
-  const uint64_t tl = dev_load(&q->t_last);
-  uint64_t gr = dev_load(&q->granules);
-  const uint32_t np = dev_load(&q->n_pkgs) + (s.pre_nt ? 1u : 0u);
+  if (!count_out(q)) return;
+  // without gatherers the last workgroup out is the last computing one
+  const uint64_t tl = s.gather_wgs ? dev_load(&q->t_last) : now_tick();
+  // with only the pre-claimed package nothing else was published; its start
+  // was stamped by the workgroup of ticket 0, its end by that of its last one
+  const uint64_t tf = s.pre_nt ? 0 : dev_load(&q->t_first);
+  uint64_t gr = s.pre_only ? 0 : dev_load(&q->granules);
+  const uint32_t np = (s.pre_only ? 0u : dev_load(&q->n_pkgs)) + (s.pre_nt ? 1u : 0u);
+  const uint64_t tg = s.gather_wgs ? dev_load(&q->t_gather) : 0;
   if (s.pre_nt) {
-    // trace record of the pre-claimed package (read by the host after the run)
+    // the rest of the pre-claimed package's trace record
     PkgSlot* ps = &s.pkgs[0];
-    const uint64_t tp = dev_load(&q->t_pre);
     ps->g0 = s.pre_g0;
     ps->g1 = s.pre_g1;
     ps->base = 0;
     ps->ntiles = s.pre_nt;
-    ps->t_claim = tp;
-    ps->t_end = dev_load(&q->t_end0);
-    tf = tp;
     gr += s.pre_g1 - s.pre_g0;
-    dev_store(&q->t_pre, (uint64_t)0);
-    dev_store(&q->t_end0, (uint64_t)0);
+  } else {
+    sys_store(&s.l1->gpu_t_first, tf);
   }
-  for (uint32_t i = 0; i < np && i < s.max_pkgs; ++i) {
+  // the pre-claimed package's word is never stored (workgroups build it from
+  // the arguments), so with it alone there is nothing to clear
+  for (uint32_t i = s.pre_only ? np : 0; i < np && i < s.max_pkgs; ++i) {
     dev_store(&s.pub[i], (uint64_t)0);
   }
-  sys_store(&s.l1->gpu_t_first, tf);
   sys_store(&s.l1->gpu_t_last, tl);
   sys_store(&s.l1->gpu_granules, gr);
   sys_store(&s.l1->gpu_packages, np);
-  dev_store(&q->ticket, (uint64_t)0);
-  dev_store(&q->total, (uint64_t)0);
-  dev_store(&q->n_pkgs, 0u);
-  dev_store(&q->st_next, 0u);
-  dev_store(&q->granules, (uint64_t)0);
-  dev_store(&q->t_first, (uint64_t)0);
-  dev_store(&q->t_last, (uint64_t)0);
-  dev_store(&q->exit_compute, 0u);
-  dev_store(&q->lock, 0u);
-  dev_store(&q->gather_next, (uint64_t)0);
+  sys_store(&s.l1->gpu_t_gather, tg);
+  if (!s.pre_only) {
+    dev_store(&q->ticket, (uint64_t)0);
+    dev_store(&q->total, (uint64_t)0);
+    dev_store(&q->n_pkgs, 0u);
+    dev_store(&q->st_next, 0u);
+    dev_store(&q->granules, (uint64_t)0);
+    dev_store(&q->t_first, (uint64_t)0);
+    dev_store(&q->lock, 0u);
+  } else if (!s.stride) {
+    dev_store(&q->ticket, (uint64_t)0);
+  }
+  if (s.gather_wgs) {
+    dev_store(&q->t_last, (uint64_t)0);
+    dev_store(&q->exit_compute, 0u);
+    dev_store(&q->gather_next, (uint64_t)0);
+    dev_store(&q->t_gather, (uint64_t)0);
+  }
+  for (uint32_t x = 0; x < kExitLines; ++x) dev_store(&q->exit_x[x][0], 0u);
   dev_store(&q->exit_count, 0u);
-  sys_store(&s.l1->gpu_t_gather, dev_load(&q->t_gather));
-  dev_store(&q->t_gather, (uint64_t)0);
-  sys_store(&s.l1->gpu_t_leave, now_tick());  // lets the host re-anchor its clock mapping
-  sys_store_release(&s.l1->gpu_run_id, s.run_id);
+  // The host polls this word and reads everything else only after the
+  // kernel has ended, so no store above needs to be ordered before it (a
+  // release here would also write back this XCD's L2, which the end of the
+  // kernel does anyway). Its tick lets the host re-anchor the clock mapping.
+  sys_store(&s.l1->gpu_done, done_word(s.run_id, now_tick()));
 }
 
 // Gather (device-resident output with the host in the device set): the host
@@ -371,7 +407,7 @@ __device__ bool gather_entry(const SchedArgs& s, uint64_t* off, uint32_t* len) {
     }
     const uint64_t f = sys_load(&s.l1->host_final);
     if ((f >> 40) == want && j >= (f & ((1ull << 40) - 1))) return false;
-    if (now_tick() - t0 > s.wait_ticks) {
+    if (now_tick() - t0 > s.gather_wait_ticks) {
       sys_store(&s.l1->gpu_flags, 2);
       return false;
     }
@@ -455,7 +491,12 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
       c.t_next = blockIdx.x - s.gather_wgs;  // the first ticket needs no atomic
       c.t_end = c.t_next + 1;
       c.tot_seen = s.pre_nt;
-      if (s.pre_nt && c.t_next == 0) dev_store(&s.l2->t_pre, now_tick());
+      if (s.pre_nt && c.t_next == 0) {
+        // the pre-claimed package starts with the first workgroup
+        const uint64_t tp = now_tick();
+        dev_store(&s.pkgs[0].t_claim, tp);
+        sys_store(&s.l1->gpu_t_first, tp);
+      }
     }
   }
   uint32_t prev_p = 0xFFFFFFFFu;
@@ -531,7 +572,8 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
     if (lane0) {
       // the last computing workgroup out marks the end of the GPU's work
       // (gather workgroups may still be copying the host's output)
-      if (dev_add(&sa.l2->exit_compute, 1u) + 1 == gridDim.x - sa.gather_wgs) dev_store(&sa.l2->t_last, now_tick());
+      if (sa.gather_wgs && dev_add(&sa.l2->exit_compute, 1u) + 1 == gridDim.x - sa.gather_wgs)
+        dev_store(&sa.l2->t_last, now_tick());
       leave(sa);
     }
   }

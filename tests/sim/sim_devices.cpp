@@ -303,8 +303,7 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, 
     __atomic_store_n(&s.l1->gpu_t_last, t_last, __ATOMIC_RELEASE);
     __atomic_store_n(&s.l1->gpu_granules, gr, __ATOMIC_RELEASE);
     __atomic_store_n(&s.l1->gpu_packages, np, __ATOMIC_RELEASE);
-    __atomic_store_n(&s.l1->gpu_t_leave, (uint64_t)(now_ns() / 10), __ATOMIC_RELEASE);
-    __atomic_store_n(&s.l1->gpu_run_id, s.run_id, __ATOMIC_RELEASE);
+    __atomic_store_n(&s.l1->gpu_done, done_word(s.run_id, (uint64_t)(now_ns() / 10)), __ATOMIC_RELEASE);
   });
   return hipSuccess;
 }

@@ -1,0 +1,97 @@
+"""The persistent kernel's grid does not change results: the same outputs,
+bit for bit against the oracle, with one workgroup (every tile run in turn
+by one workgroup), a few, and more workgroups than the GPU holds at once
+(the dispenser's waits must not depend on every workgroup being resident),
+for every scheduler over the GPU alone and the GPU with the host."""
+import numpy as np
+import pytest
+
+import paper_1805_02755_amd as ce
+from paper_1805_02755_amd import synth
+from oracle import oracle as O
+
+from gpu_util import BOTH, check_trace, diff_report, escape_params, run_payload
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = [1, 3, 64, 1000, 4096]
+
+
+@pytest.fixture(scope="module")
+def eng():
+    e = ce.Engine()
+    yield e
+    e.close()
+
+
+@pytest.fixture
+def grid(eng, request):
+    eng.gpu_workgroups(request.param)
+    yield request.param
+    eng.gpu_workgroups(0)
+
+
+@pytest.fixture(scope="module")
+def escape_ref():
+    p = synth.escape_region(700, 300, -2.0, 0.6, -1.2, 1.2, 400)
+    return p, O.escape(p.w, p.h, *[float(v) for v in p.as_f32()], p.max_iter)
+
+
+@pytest.mark.parametrize("grid", GRIDS, indirect=True)
+@pytest.mark.parametrize("sched", ["static8", "dynamic", "hguided"])
+@pytest.mark.parametrize("devs", ["gpu", "both"])
+def test_escape_any_grid(eng, escape_ref, grid, sched, devs):
+    p, ref = escape_ref
+    dm = BOTH if devs == "both" else ce.CE_DEV_GPU
+    out, st, tr = run_payload(eng, ce.CE_KERNEL_ESCAPE, escape_params(p), [p.w, p.h], None, [], (p.h, p.w),
+                              np.uint32, dm, sched)
+    assert np.array_equal(out, ref), diff_report(out, ref, tr)
+    check_trace(tr, p.h, st.n_devices)
+    assert st.gpu_workgroups == grid
+
+
+@pytest.mark.parametrize("grid", [1, 7, 3000], indirect=True)
+@pytest.mark.parametrize("w,h", [(1001, 37), (4099, 23)])
+def test_blur_any_grid(eng, grid, w, h):
+    img = synth.blur_image(w, h, seed=w + 31 * h)
+    wt = ce.ce_gauss5_weights(1.0)
+    ref = O.blur5(img, O.gauss5_weights(1.0))
+    for sched in ("hguided", "dynamic", "static_rev"):
+        out, st, tr = run_payload(eng, ce.CE_KERNEL_BLUR5, ce.ce_blur5_params(w, h), [w, h], None, [img, wt],
+                                  (h, w), np.float32, BOTH, sched)
+        assert np.array_equal(out.view(np.uint32), ref.view(np.uint32)), (sched, diff_report(out, ref, tr))
+        check_trace(tr, h, 2)
+
+
+@pytest.mark.parametrize("grid", [1, 5, 4096], indirect=True)
+def test_nbody_any_grid(eng, grid):
+    n = 3000
+    pos = synth.nbody_bodies(n, seed=91)
+    ref = O.nbody_acc(pos, 1e-6, True)
+    for sched in ("dynamic", "hguided", "static"):
+        for dm in (ce.CE_DEV_GPU, BOTH):
+            out, st, tr = run_payload(eng, ce.CE_KERNEL_NBODY_ACC, ce.ce_nbody_params(n, 1e-6, 1), [n], [256],
+                                      [pos], (n, 4), np.float32, dm, sched)
+            assert np.array_equal(out.view(np.uint32), ref.view(np.uint32)), (sched, dm)
+            check_trace(tr, (n + 255) // 256, st.n_devices)
+
+
+def test_default_grid_whole_rounds(eng):
+    """Without an override the grid spreads the tiles of the whole space
+    over whole rounds: ceil(T / ceil(T / R)) workgroups for T tiles, so
+    every workgroup gets the same number of tiles, give or take one."""
+    eng.gpu_workgroups(0)
+    p = synth.escape_small()
+    run_payload(eng, ce.CE_KERNEL_ESCAPE, escape_params(p), [p.w, p.h], None, [], (p.h, p.w), np.uint32,
+                ce.CE_DEV_GPU, "static")
+    g = eng.stats().gpu_workgroups
+    tiles = 1024 * 2  # 1024 rows x two 512-pixel column blocks
+    assert 0 < g <= tiles
+    assert -(-tiles // -(-tiles // g)) == g
+
+
+def test_refuses_huge_grid(eng):
+    with pytest.raises(ce.CoexecError):
+        eng.gpu_workgroups((1 << 20) + 1)
+    eng.clear_errors()
+    eng.gpu_workgroups(0)
