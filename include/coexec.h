@@ -328,6 +328,22 @@ ce_status ce_engine_kernel_events(ce_engine* e, void* start_event, void* stop_ev
  * are unspecified. */
 ce_status ce_engine_run(ce_engine* e);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): runs the
+ * bound program like ce_engine_run, GPU alone, without allocating. The
+ * queue state, publication words and package table live in a static device
+ * array of 1 MiB per GPU (held until the process ends) instead of memory the
+ * engine allocates, so at most (1 MiB - queue state) / 72 B packages, about
+ * 14,000, may be scheduled: a Dynamic or HGuided schedule that could need
+ * more returns CE_E_INVALID before anything runs. The array is cleared by a
+ * fill kernel on the engine's stream at the start of every run. Every bound
+ * input and output must have a device pointer and no output a host pointer
+ * (CE_E_UNSUPPORTED otherwise, as for a device set other than CE_DEV_GPU).
+ * All engines on one GPU share the array: runs of this call that overlap
+ * on one GPU race and give wrong results. Stats and trace work as after
+ * ce_engine_run. */
+ce_status ce_engine_run_noalloc(ce_engine* e);
+
 /* Statistics of the last successful run. */
 ce_status ce_engine_stats(const ce_engine* e, ce_run_stats* out);
 /* Copies up to cap package records of the last run into buf (may be NULL

@@ -54,7 +54,7 @@ CE_MERGE_GPU_GATHER = 1
 EXPORTED_SYMBOLS = (
     "ce_engine_create", "ce_engine_destroy", "ce_engine_use", "ce_engine_work_items", "ce_engine_scheduler",
     "ce_engine_stream", "ce_engine_output_merge", "ce_engine_gpu_workgroups", "ce_engine_kernel_events", "ce_program_kernel", "ce_program_in", "ce_program_out", "ce_program_out_pattern",
-    "ce_engine_run", "ce_engine_stats", "ce_engine_trace", "ce_engine_has_errors", "ce_engine_error_count",
+    "ce_engine_run", "ce_engine_run_noalloc", "ce_engine_stats", "ce_engine_trace", "ce_engine_has_errors", "ce_engine_error_count",
     "ce_engine_error", "ce_engine_clear_errors", "ce_bare_run", "ce_bare_run_outs", "ce_sched_static_plan", "ce_sched_hguided_size",
     "ce_gauss5_weights", "ce_binomial_table", "ce_version", "ce_batch_create", "ce_batch_destroy", "ce_batch_add_escape",
     "ce_batch_clear", "ce_batch_set_config", "ce_batch_get_config", "ce_batch_tune", "ce_batch_run",
@@ -189,6 +189,7 @@ def load(path: str):
         "ce_program_out": (i32, [vp, u32, vp, vp, sz]),
         "ce_program_out_pattern": (i32, [vp, u32, u32]),
         "ce_engine_run": (i32, [vp]),
+        "ce_engine_run_noalloc": (i32, [vp]),
         "ce_engine_stats": (i32, [vp, C.POINTER(ce_run_stats)]),
         "ce_engine_trace": (sz, [vp, C.POINTER(ce_package_rec), sz]),
         "ce_engine_has_errors": (C.c_int, [vp]),
@@ -505,6 +506,12 @@ class Engine:
 
     def run_status(self) -> int:
         return int(self._L.ce_engine_run(self._h))
+
+    def run_noalloc(self):
+        return self._check(self._L.ce_engine_run_noalloc(self._h), "ce_engine_run_noalloc")
+
+    def run_noalloc_status(self) -> int:
+        return int(self._L.ce_engine_run_noalloc(self._h))
 
     def stats(self) -> ce_run_stats:
         s = ce_run_stats()

@@ -72,6 +72,11 @@ CE_HD uint64_t ring_len(uint64_t w) { return w >> 40; }
 
 constexpr uint32_t kExitLines = 8;
 
+// Size of the static device scratch of the allocation-free run: queue state,
+// publication words and package table (72 bytes per package, so about
+// 14,000 packages).
+constexpr uint64_t kNoallocScratchBytes = 1ull << 20;
+
 // Per-run GPU queue state in HBM (device-scope atomics only). The last
 // workgroup to leave a run resets it to zero for the next run. Contended
 // atomics on one cache line serialise at the memory side, so the ticket

@@ -148,6 +148,13 @@ struct ce_engine {
   DevBuf pkgs_dev;
   DevBuf pub_dev;  // publication words of the GPU's packages, zero between runs
   uint32_t pkgs_dev_cap = 0;
+  // The allocation-free run keeps the queue state, publication words and
+  // package table in this device's static scratch array instead.
+  void* noalloc_base = nullptr;      // device address of the scratch (null: unavailable)
+  hipError_t noalloc_err = hipSuccess;
+  bool noalloc = false;              // the current run may not allocate
+  PkgSlot* trace_pkgs = nullptr;     // package table of the last run
+  uint32_t trace_pkgs_cap = 0;
   double clock_offset_ns = 0.0;  // host_ns = tick * period + offset
   double clock_latency_ns = 0.0; // one-way GPU -> host visibility latency (half the best round trip)
   bool clock_ok = false;
@@ -781,11 +788,36 @@ struct ce_engine {
 
   // ------------------------------------------------------------ run
   ce_status run() {
+    const ce_status st = run_impl();
+    noalloc = false;
+    return st;
+  }
+
+  // Scratch layout of the allocation-free run: the queue state, then the
+  // publication words, then the package table. Packages that fit:
+  static uint64_t noalloc_max_pkgs() {
+    return (kNoallocScratchBytes - sizeof(L2State)) / (sizeof(uint64_t) + sizeof(PkgSlot));
+  }
+
+  ce_status run_impl() {
     if (kernel_id == 0) return fail(CE_E_STATE, "run: no kernel bound");
     if (!sched_set) return fail(CE_E_STATE, "run: no scheduler set");
     if (ndim == 0) return fail(CE_E_STATE, "run: work_items not set");
     if (n_devices() == 0) return fail(CE_E_STATE, "run: empty device set");
     if (use_host() && !hp && kernel_id != CE_KERNEL_RUNTIME) return fail(CE_E_UNSUPPORTED, "run: host CPU lacks AVX2/FMA");
+    if (noalloc) {
+      if (!noalloc_base)
+        return fail(CE_E_DEVICE, "run_noalloc: no device scratch (%s)", hipGetErrorString(noalloc_err));
+      if (use_host() || !use_gpu()) return fail(CE_E_UNSUPPORTED, "run_noalloc: the device set must be the GPU alone");
+      for (int s = 0; s < n_in_slots(); ++s)
+        if (in[s].bound && !in[s].dev) return fail(CE_E_UNSUPPORTED, "run_noalloc: input slot %d has no device pointer", s);
+      for (int s = 0; s < n_out_slots(); ++s)
+        if (out[s].bound && !out[s].dev_out)
+          return fail(CE_E_UNSUPPORTED, "run_noalloc: output slot %d has no device pointer", s);
+      for (int s = 0; s < n_out_slots(); ++s)
+        if (out[s].bound && out[s].host_out)
+          return fail(CE_E_UNSUPPORTED, "run_noalloc: output slot %d also has a host pointer (it would need a copy)", s);
+    }
     // index space must match the kernel
     if (is_nbody()) {
       if (ndim != 1 || gws[0] != n_bodies() || lws0 != kNbodyGranule)
@@ -947,7 +979,23 @@ struct ce_engine {
     if (st != CE_OK) return st;
     host_args = hs;
     if (use_gpu()) {
-      if (gmax > pkgs_dev_cap) {
+      if (noalloc) {
+        const uint64_t cap = noalloc_max_pkgs();
+        if (gmax > cap)
+          return fail(CE_E_INVALID, "run_noalloc: the schedule needs up to %llu packages; the scratch holds %llu",
+                      (unsigned long long)gmax, (unsigned long long)cap);
+        char* base = (char*)noalloc_base;
+        gs.l2 = (L2State*)base;
+        gs.pub = (uint64_t*)(base + sizeof(L2State));
+        gs.pkgs = (PkgSlot*)(base + sizeof(L2State) + gmax * sizeof(uint64_t));
+        gs.max_pkgs = (uint32_t)gmax;
+        // Another caller's run may have ended early and left the state dirty:
+        // clear the queue state and the publication words (not the table,
+        // which each run writes before reading) with a fill kernel.
+        static_assert(sizeof(L2State) % sizeof(uint64_t) == 0, "queue state is whole words");
+        if ((he = launch_zero_words(base, sizeof(L2State) / sizeof(uint64_t) + gmax, stream)) != hipSuccess)
+          return hip_fail(he, "run_noalloc: clearing the scratch");
+      } else if (gmax > pkgs_dev_cap) {
         if (!pkgs_dev.ensure(gmax * sizeof(PkgSlot)) || !pub_dev.ensure(gmax * sizeof(uint64_t)))
           return fail(CE_E_NOMEM, "run: package table");
         if ((he = hipMemset(pub_dev.p, 0, gmax * sizeof(uint64_t))) != hipSuccess ||
@@ -955,9 +1003,13 @@ struct ce_engine {
           return hip_fail(he, "run: package table");
         pkgs_dev_cap = (uint32_t)gmax;
       }
-      gs.pkgs = (PkgSlot*)pkgs_dev.p;
-      gs.pub = (uint64_t*)pub_dev.p;
-      gs.max_pkgs = pkgs_dev_cap;
+      if (!noalloc) {
+        gs.pkgs = (PkgSlot*)pkgs_dev.p;
+        gs.pub = (uint64_t*)pub_dev.p;
+        gs.max_pkgs = pkgs_dev_cap;
+      }
+      trace_pkgs = gs.pkgs;
+      trace_pkgs_cap = gs.max_pkgs;
       // Claim the next package while half a round of tiles is still to be
       // handed out: with the host in the set its output copies share PCIe
       // with the claim's atomics, which can then take tens of microseconds.
@@ -1226,8 +1278,8 @@ struct ce_engine {
     trace.clear();
     const int gi = gpu_index(), hi = host_index();
     if (gi >= 0 && gpu_pkgs_last) {
-      std::vector<PkgSlot> v(std::min<uint64_t>(gpu_pkgs_last, pkgs_dev_cap));
-      if (hipMemcpy(v.data(), pkgs_dev.p, v.size() * sizeof(PkgSlot), hipMemcpyDeviceToHost) == hipSuccess) {
+      std::vector<PkgSlot> v(std::min<uint64_t>(gpu_pkgs_last, trace_pkgs_cap));
+      if (hipMemcpy(v.data(), trace_pkgs, v.size() * sizeof(PkgSlot), hipMemcpyDeviceToHost) == hipSuccess) {
         for (auto& p : v)
           trace.push_back(ce_package_rec{(uint32_t)gi, 0, p.g0, p.g1, tick_to_host_s(p.t_claim), tick_to_host_s(p.t_end)});
       }
@@ -1270,6 +1322,8 @@ struct ce_engine {
       return hip_fail(he, "create: device view of host memory");
     if ((he = hipMalloc((void**)&l2, sizeof(L2State))) != hipSuccess) return hip_fail(he, "create: queue state");
     if ((he = hipMemset(l2, 0, sizeof(L2State))) != hipSuccess) return hip_fail(he, "create: queue state");
+    // the allocation-free run's scratch on this GPU (a failure only disables that run)
+    noalloc_err = noalloc_scratch_address(gpu, &noalloc_base);
     hp = host_payloads();
     host_threads = (int)std::max(1u, std::thread::hardware_concurrency());
     calibrate_clock();
@@ -1607,6 +1661,20 @@ ce_status ce_engine_bare_run_source(ce_engine* e, uint64_t gws, uint32_t lws, co
   if ((he = launch_bare(a, st)) != hipSuccess) return e->hip_fail(he, "bare: launch");
   if (sync && (he = hipStreamSynchronize(st)) != hipSuccess) return e->hip_fail(he, "bare: sync");
   return CE_OK;
+}
+
+ce_status ce_engine_run_noalloc(ce_engine* e) {
+  if (!e) return CE_E_INVALID;
+  try {
+    e->noalloc = true;
+    return e->run();
+  } catch (const std::exception& ex) {
+    e->noalloc = false;
+    return e->fail(CE_E_NOMEM, "run_noalloc: %s", ex.what());
+  } catch (...) {
+    e->noalloc = false;
+    return e->fail(CE_E_NOMEM, "run_noalloc: unknown exception");
+  }
 }
 
 ce_status ce_engine_run(ce_engine* e) {

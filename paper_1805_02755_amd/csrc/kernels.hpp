@@ -50,6 +50,11 @@ int rt_compile(const char* source, const char* entry, std::string* code, std::st
 int rt_build(const char* source, const char* entry, void** module, void** fn_persistent, void** fn_bare,
              std::string* log);
 void rt_release(void* module);
+// Allocation-free runs (noalloc.hip): the address of this device's static
+// scratch array (kNoallocScratchBytes), looked up once per device; and a
+// zero fill of n 64-bit words on a stream.
+hipError_t noalloc_scratch_address(int device, void** out);
+hipError_t launch_zero_words(void* p, uint64_t n_words, hipStream_t st);
 // Clock calibration: one thread answers `rounds` pings through the mailbox.
 hipError_t launch_calibrate(L1State* l1, uint32_t rounds, uint64_t spin_limit, hipStream_t st);
 

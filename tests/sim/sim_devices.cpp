@@ -308,6 +308,18 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, 
   return hipSuccess;
 }
 
+// the allocation-free run's static scratch: a static host array here
+alignas(256) static unsigned char g_noalloc_scratch[kNoallocScratchBytes];
+hipError_t noalloc_scratch_address(int, void** out) {
+  *out = g_noalloc_scratch;
+  return hipSuccess;
+}
+hipError_t launch_zero_words(void* p, uint64_t n_words, hipStream_t) {
+  join_gpu();
+  memset(p, 0, n_words * sizeof(uint64_t));
+  return hipSuccess;
+}
+
 hipError_t launch_bare(const KernelArgs& a, hipStream_t) {
   const uint64_t G = gpu_granules(a);
   mark((uint32_t*)a.out, 0, items_of(a, 0, G), item_words(a));

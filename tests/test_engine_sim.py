@@ -46,7 +46,7 @@ def _coverage(L, n):
     return cov
 
 
-def _run(L, kind, size, devs, sched, host_threads=4, rates=(0.0, 0.0, 0.0), merge=ce.CE_MERGE_DMA):
+def _run(L, kind, size, devs, sched, host_threads=4, rates=(0.0, 0.0, 0.0), merge=ce.CE_MERGE_DMA, noalloc=False):
     L.sim_set_rates(*rates)
     eng = ce.Engine(L)
     eng.output_merge(merge)
@@ -79,7 +79,10 @@ def _run(L, kind, size, devs, sched, host_threads=4, rates=(0.0, 0.0, 0.0), merg
     eng.program_out(0, dev=out)
     n_items = out.shape[0] if kind == "nbody" else out.size
     L.sim_reset(n_items)
-    eng.run()
+    if noalloc:
+        eng.run_noalloc()
+    else:
+        eng.run()
     st = eng.stats()
     tr = eng.trace()
     eng.close()
@@ -489,4 +492,41 @@ def test_runtime_payload_refusals(simlib):
         eng.program_out(1, host=out)
     with pytest.raises(ce.CoexecError):
         eng.program_out_pattern(1, 10)
+    eng.close()
+
+
+@pytest.mark.parametrize("kind,size", [("escape", (37, 53)), ("blur", (1000, 61)), ("nbody", 3000)])
+@pytest.mark.parametrize("sched", list(SCHEDS))
+def test_noalloc_run_covers_every_item_once(simlib, kind, size, sched):
+    """The allocation-free run uses the static scratch for its package table
+    and still covers the space exactly once, twice in a row."""
+    for _ in range(2):
+        cnt, st, tr, G = _run(simlib, kind, size, ce.CE_DEV_GPU, _one_dev(SCHEDS[sched]), noalloc=True)
+        assert np.all(cnt == 1)
+        cov = np.zeros(G, np.int32)
+        for d, b, e, _, _ in tr:
+            cov[b:e] += 1
+        assert np.all(cov == 1)
+
+
+def test_noalloc_run_refusals(simlib):
+    eng = ce.Engine(simlib)
+    eng.work_items([16, 20000])
+    eng.program_kernel(ce.CE_KERNEL_ESCAPE, ce.ce_escape_params(16, 20000, -2.0, -1.5, 0.01, 0.01, 10))
+    out = np.zeros((20000, 16), np.uint32)
+    eng.program_out(0, dev=out)
+    eng.use(ce.CE_DEV_GPU, 0, 0)
+    eng.scheduler(kind=ce.CE_SCHED_DYNAMIC, package_granules=1)
+    assert eng.run_noalloc_status() == ce.CE_E_INVALID  # 20,001 packages > the scratch's table
+    eng.clear_errors()
+    eng.use(ce.CE_DEV_GPU | ce.CE_DEV_HOST, 0, 2)
+    eng.scheduler(kind=ce.CE_SCHED_STATIC, props=[0.5])
+    assert eng.run_noalloc_status() == ce.CE_E_UNSUPPORTED
+    eng.clear_errors()
+    eng.use(ce.CE_DEV_GPU, 0, 0)
+    eng.program_out(0, host=out)
+    assert eng.run_noalloc_status() == ce.CE_E_UNSUPPORTED  # host-only output: would need device scratch
+    eng.clear_errors()
+    eng.program_out(0, host=out, dev=out)
+    assert eng.run_noalloc_status() == ce.CE_E_UNSUPPORTED  # host copy: would need a copy
     eng.close()
