@@ -246,8 +246,12 @@ typedef struct {
   void* buf[CE_RT_MAX_BUFS];
   unsigned char scalars[CE_RT_SCALAR_BYTES];
 } ce_rt_args;
-/* Host version: computes work-items [i0, i1). */
-typedef void (*ce_rt_host_fn)(uint64_t i0, uint64_t i1, const ce_rt_args* a);
+/* Host version: computes work-items [i0, i1) and returns 0, or a nonzero
+ * code if it could not. A failure is collected, not thrown (section 6.1):
+ * the host device claims no further package, the other devices go on, and
+ * the run returns CE_E_DEVICE with an error naming the items and the code
+ * (the failed items' outputs are unspecified). */
+typedef int32_t (*ce_rt_host_fn)(uint64_t i0, uint64_t i1, const ce_rt_args* a);
 typedef struct {
   const char* source;         /* HIP C++ source; must define `entry` as
                                *   __device__ void entry(uint64_t i, const ce_rt_args* a)
@@ -305,6 +309,18 @@ ce_status ce_engine_bare_run_source(ce_engine* e, uint64_t gws, uint32_t lws, co
 #define CE_MERGE_DMA 0
 #define CE_MERGE_GPU_GATHER 1
 ce_status ce_engine_output_merge(ce_engine* e, int mode);
+
+/* Bounds, in seconds, on the waits inside the GPU kernel for the following
+ * runs (0 keeps the default): dispenser_s for a workgroup waiting on the
+ * dispenser (a claim, a package to appear; default 5 s, far above the
+ * microseconds these take), gather_s for a gather workgroup waiting for the
+ * host's next finished tile (CE_MERGE_GPU_GATHER; default 60 s; it must
+ * exceed the host's longest package). A wait that runs out ends the GPU's
+ * part of the run early and the run returns CE_E_TIMEOUT, the other devices
+ * having finished theirs; the kernel still ends normally and the engine is
+ * ready for the next run. Errors: CE_E_INVALID for a negative value or one
+ * above 3600. */
+ce_status ce_engine_wait_bounds(ce_engine* e, double dispenser_s, double gather_s);
 
 /* Number of workgroups of the GPU's persistent kernel for the following
  * runs; 0 (the default) lets the engine choose: the resident workgroups

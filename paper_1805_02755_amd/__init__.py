@@ -53,7 +53,7 @@ CE_MERGE_GPU_GATHER = 1
 
 EXPORTED_SYMBOLS = (
     "ce_engine_create", "ce_engine_destroy", "ce_engine_use", "ce_engine_work_items", "ce_engine_scheduler",
-    "ce_engine_stream", "ce_engine_output_merge", "ce_engine_gpu_workgroups", "ce_engine_kernel_events", "ce_program_kernel", "ce_program_in", "ce_program_out", "ce_program_out_pattern",
+    "ce_engine_stream", "ce_engine_output_merge", "ce_engine_gpu_workgroups", "ce_engine_wait_bounds", "ce_engine_kernel_events", "ce_program_kernel", "ce_program_in", "ce_program_out", "ce_program_out_pattern",
     "ce_engine_run", "ce_engine_run_noalloc", "ce_engine_stats", "ce_engine_trace", "ce_engine_has_errors", "ce_engine_error_count",
     "ce_engine_error", "ce_engine_clear_errors", "ce_bare_run", "ce_bare_run_outs", "ce_sched_static_plan", "ce_sched_hguided_size",
     "ce_gauss5_weights", "ce_binomial_table", "ce_version", "ce_batch_create", "ce_batch_destroy", "ce_batch_add_escape",
@@ -97,7 +97,7 @@ class ce_rt_args(C.Structure):
 
 
 # host version of a runtime payload: (i0, i1, const ce_rt_args*)
-CE_RT_HOST_FN = C.CFUNCTYPE(None, C.c_uint64, C.c_uint64, C.POINTER(ce_rt_args))
+CE_RT_HOST_FN = C.CFUNCTYPE(C.c_int32, C.c_uint64, C.c_uint64, C.POINTER(ce_rt_args))
 
 
 class ce_rt_desc(C.Structure):
@@ -184,6 +184,7 @@ def load(path: str):
         "ce_engine_kernel_events": (i32, [vp, vp, vp]),
         "ce_engine_output_merge": (i32, [vp, C.c_int]),
         "ce_engine_gpu_workgroups": (i32, [vp, u32]),
+        "ce_engine_wait_bounds": (i32, [vp, C.c_double, C.c_double]),
         "ce_program_kernel": (i32, [vp, C.c_int, vp, sz]),
         "ce_program_in": (i32, [vp, u32, vp, vp, sz]),
         "ce_program_out": (i32, [vp, u32, vp, vp, sz]),
@@ -437,6 +438,9 @@ class Engine:
 
     def output_merge(self, mode: int):
         return self._check(self._L.ce_engine_output_merge(self._h, mode), "ce_engine_output_merge")
+
+    def wait_bounds(self, dispenser_s: float = 0.0, gather_s: float = 0.0):
+        return self._check(self._L.ce_engine_wait_bounds(self._h, dispenser_s, gather_s), "ce_engine_wait_bounds")
 
     def gpu_workgroups(self, workgroups: int):
         return self._check(self._L.ce_engine_gpu_workgroups(self._h, workgroups), "ce_engine_gpu_workgroups")

@@ -238,6 +238,8 @@ struct ce_engine {
   uint64_t gpu_pkgs_last = 0;
   uint32_t gpu_grid_last = 0;
   uint32_t grid_override = 0;  // persistent workgroups chosen by the caller (0: the engine chooses)
+  double dispenser_wait_s = (double)kDispenserWaitSeconds;  // bounds on the kernel's waits
+  double gather_wait_s = (double)kGatherWaitSeconds;
 
   std::vector<std::string> errors;
 
@@ -478,7 +480,8 @@ struct ce_engine {
     }
   }
 
-  void host_tile(const HostPkg& p, uint32_t ti) {
+  // Computes host tile ti of package p; 0, or the host function's failure code.
+  int32_t host_tile(const HostPkg& p, uint32_t ti) {
     switch (kernel_id) {
       case CE_KERNEL_ESCAPE: hp->escape_rows(esc, p.g0 + ti, p.g0 + ti + 1, (uint32_t*)host_out); break;
       case CE_KERNEL_BLUR5:
@@ -507,8 +510,22 @@ struct ce_engine {
         binomial_groups((const float*)host_in0, (const float*)host_in1, bin.steps, bin.strike, bin.pu, bin.pd,
                         p.g0 + ti, p.g0 + ti + 1, (float*)host_out);
         break;
-      case CE_KERNEL_RUNTIME: rt_host(rt_item(p.g0 + ti), rt_item(p.g0 + ti + 1), &rt_host_args); break;
+      case CE_KERNEL_RUNTIME: return rt_host(rt_item(p.g0 + ti), rt_item(p.g0 + ti + 1), &rt_host_args);
     }
+    return 0;
+  }
+
+  // The first host tile that failed in this run (host_fail_code 0: none).
+  std::atomic<int32_t> host_fail_code{0};
+  uint64_t host_fail_i0 = 0, host_fail_i1 = 0;
+  void host_tile_failed(const HostPkg& p, uint32_t ti, int32_t code) {
+    int32_t none = 0;
+    if (host_fail_code.compare_exchange_strong(none, code)) {
+      host_fail_i0 = kernel_id == CE_KERNEL_RUNTIME ? rt_item(p.g0 + ti) : p.g0 + ti;
+      host_fail_i1 = kernel_id == CE_KERNEL_RUNTIME ? rt_item(p.g0 + ti + 1) : p.g0 + ti + 1;
+    }
+    // the host device claims nothing more; its claimed tiles still run
+    hq.done.store(1, std::memory_order_release);
   }
 
   // Byte range of the output written by host tile ti of package p.
@@ -657,7 +674,8 @@ struct ce_engine {
       while (t >= hq.pkgs[p].base + hq.pkgs[p].ntiles) ++p;
       p_cache = p;
       HostPkg& pk = hq.pkgs[p];
-      host_tile(pk, (uint32_t)(t - pk.base));
+      const int32_t rc = host_tile(pk, (uint32_t)(t - pk.base));
+      if (rc != 0) host_tile_failed(pk, (uint32_t)(t - pk.base), rc);
       if (gather) publish_host_tile(pk, (uint32_t)(t - pk.base));
       if (pk.tiles_done.fetch_add(1, std::memory_order_acq_rel) + 1 == pk.ntiles) {
         pk.t_end.store(now_ns(), std::memory_order_release);
@@ -690,7 +708,7 @@ struct ce_engine {
     // not running claims itself after milliseconds. Five seconds is thus only
     // reached when something is broken, and is well inside the host's own
     // deadline for the kernel.
-    base.wait_ticks = (uint64_t)wallclock_hz * kDispenserWaitSeconds;
+    base.wait_ticks = std::max<uint64_t>(1, (uint64_t)((double)wallclock_hz * dispenser_wait_s));
     base.l1 = l1_dev;
     base.l2 = l2;
     *gpu_s = base;
@@ -1045,7 +1063,7 @@ struct ce_engine {
       if (long_tiles) gs.chunk = 1;
       gs.stride = (kernel_id == CE_KERNEL_RUNTIME || gather || long_tiles) ? 0u : 1u;
       // the gatherers wait for the host's packages, whose length depends on the problem
-      gs.gather_wait_ticks = (uint64_t)wallclock_hz * kGatherWaitSeconds;
+      gs.gather_wait_ticks = std::max<uint64_t>(1, (uint64_t)((double)wallclock_hz * gather_wait_s));
       if (gather) {
         const uint64_t max_host_tiles =
             is_nbody() ? ceil_div(n_bodies(), kHostNbodyTile) : G;
@@ -1073,6 +1091,7 @@ struct ce_engine {
     }
     hq.reset();
     host_error.store(0);
+    host_fail_code.store(0);
 
     // arm the level-1 dispenser
     __atomic_store_n(&l1->next, 0, __ATOMIC_RELAXED);
@@ -1140,6 +1159,9 @@ struct ce_engine {
       if (push_error.load()) return fail(CE_E_DEVICE, "run: host output copy to the device failed");
     }
     if (host_error.load()) return fail(CE_E_DEVICE, "run: host package table overflow");
+    if (const int32_t code = host_fail_code.load())
+      return fail(CE_E_DEVICE, "run: the host version failed with code %d on work-items [%llu, %llu)", (int)code,
+                  (unsigned long long)host_fail_i0, (unsigned long long)host_fail_i1);
 
     // merge outputs so each bound pointer holds the whole result
     st = merge_outputs(gpu_out);
@@ -1453,6 +1475,15 @@ ce_status ce_engine_output_merge(ce_engine* e, int mode) {
   if (mode == CE_MERGE_DMA && !e->sdma.ready())
     return e->fail(CE_E_UNSUPPORTED, "output_merge: no DMA engine (%s)", e->sdma_why);
   e->merge_mode = mode;
+  return CE_OK;
+}
+
+ce_status ce_engine_wait_bounds(ce_engine* e, double dispenser_s, double gather_s) {
+  if (!e) return CE_E_INVALID;
+  if (!(dispenser_s >= 0.0 && dispenser_s <= 3600.0) || !(gather_s >= 0.0 && gather_s <= 3600.0))
+    return e->fail(CE_E_INVALID, "wait_bounds: each bound must lie in [0, 3600] s");
+  e->dispenser_wait_s = dispenser_s > 0.0 ? dispenser_s : (double)kDispenserWaitSeconds;
+  e->gather_wait_s = gather_s > 0.0 ? gather_s : (double)kGatherWaitSeconds;
   return CE_OK;
 }
 

@@ -10,7 +10,7 @@ typedef struct {
   unsigned char scalars[128];
 } rt_args;
 
-void escape_host(uint64_t i0, uint64_t i1, const rt_args* a) {
+int32_t escape_host(uint64_t i0, uint64_t i1, const rt_args* a) {
   float f[4];
   uint32_t u[2];
   memcpy(f, a->scalars, sizeof f);
@@ -32,10 +32,11 @@ void escape_host(uint64_t i0, uint64_t i1, const rt_args* a) {
     }
     out[i] = n;
   }
+  return 0;
 }
 
 /* Two inputs, two outputs: z0 = alpha * x + y and z1 = x - y (float32). */
-void axpy2_host(uint64_t i0, uint64_t i1, const rt_args* a) {
+int32_t axpy2_host(uint64_t i0, uint64_t i1, const rt_args* a) {
   float alpha;
   memcpy(&alpha, a->scalars, sizeof alpha);
   const float* x = (const float*)a->buf[0];
@@ -47,4 +48,5 @@ void axpy2_host(uint64_t i0, uint64_t i1, const rt_args* a) {
     z0[i] = p + y[i];
     z1[i] = x[i] - y[i];
   }
+  return 0;
 }

@@ -28,6 +28,11 @@ std::thread g_gpu;
 double g_gpu_ns_per_item = 1.0;
 double g_host_ns_per_item = 10.0;
 double g_gpu_claim_ns = 1000.0;
+// faults: the fake GPU's first claim waits this long, then gives up as the
+// kernel's bounded dispenser wait does (0: no stall); the runtime payload's
+// host version fails on the tile holding this item (~0: never)
+double g_gpu_stall_ms = 0.0;
+uint64_t g_host_fail_item = ~0ull;
 std::atomic<uint32_t>* g_cov = nullptr;
 size_t g_cov_n = 0;
 
@@ -53,6 +58,11 @@ extern "C" void sim_reset(size_t n_items) {
 
 extern "C" void sim_coverage(uint32_t* dst, size_t n) {
   for (size_t i = 0; i < n && i < g_cov_n; ++i) dst[i] = g_cov[i].load();
+}
+
+extern "C" void sim_set_faults(double gpu_stall_ms, uint64_t host_fail_item) {
+  g_gpu_stall_ms = gpu_stall_ms;
+  g_host_fail_item = host_fail_item;
 }
 
 extern "C" void sim_set_rates(double gpu_ns_per_item, double host_ns_per_item, double gpu_claim_ns) {
@@ -170,10 +180,13 @@ const HostPayloadFns* host_payloads() { return &kSim; }
 
 // Host version of a simulated runtime payload: scalars[0] is the index of
 // the output buffer, scalars[1] its 32-bit words per work-item.
-extern "C" void sim_rt_host(uint64_t i0, uint64_t i1, const ce_rt_args* a) {
+extern "C" int32_t sim_rt_host(uint64_t i0, uint64_t i1, const ce_rt_args* a) {
+  // 2^63: every call fails
+  if ((g_host_fail_item >= i0 && g_host_fail_item < i1) || g_host_fail_item == (1ull << 63)) return 42;
   const int64_t until = now_ns() + (int64_t)(g_host_ns_per_item * (double)(i1 - i0));
   mark((uint32_t*)a->buf[a->scalars[0]], i0, i1, a->scalars[1]);
   spin_until(until);
+  return 0;
 }
 
 // The step's update after the (coverage-counting) force payload: the
@@ -220,6 +233,13 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, 
     for (;;) {
       uint64_t g0 = 0, g1 = 0;
       spin_until(now_ns() + (int64_t)g_gpu_claim_ns);
+      if (!pre && g_gpu_stall_ms > 0.0) {
+        // a claim that never comes back: the bounded wait runs out and the
+        // GPU's part ends after the package it already had, flagged
+        spin_until(now_ns() + (int64_t)(g_gpu_stall_ms * 1e6));
+        __atomic_store_n(&s.l1->gpu_flags, 1, __ATOMIC_RELEASE);
+        break;
+      }
       if (pre) {
         g0 = s.pre_g0;
         g1 = s.pre_g1;

@@ -11,6 +11,8 @@ import ctypes as C
 import os
 import subprocess
 
+import time
+
 import numpy as np
 import pytest
 
@@ -35,6 +37,8 @@ def simlib(tmp_path_factory):
     L.sim_set_rates.argtypes = [C.c_double, C.c_double, C.c_double]
     L.sim_reset.restype = None
     L.sim_reset.argtypes = [C.c_size_t]
+    L.sim_set_faults.restype = None
+    L.sim_set_faults.argtypes = [C.c_double, C.c_uint64]
     L.sim_coverage.restype = None
     L.sim_coverage.argtypes = [C.c_void_p, C.c_size_t]
     return L
@@ -529,4 +533,110 @@ def test_noalloc_run_refusals(simlib):
     eng.clear_errors()
     eng.program_out(0, host=out, dev=out)
     assert eng.run_noalloc_status() == ce.CE_E_UNSUPPORTED  # host copy: would need a copy
+    eng.close()
+
+
+# ------------------------------------------------------ failure paths
+# Errors are collected, not thrown (section 6.1): a device that fails ends
+# the run with an error status and an entry in the error list, never with
+# a silent hole in the output; the engine stays usable.
+
+def _rt_engine(L, n, lws, devs, sched, threads=4):
+    eng = ce.Engine(L)
+    eng.use(devs, 0, threads)
+    eng.work_items([n], [lws])
+    eng.program_source(SIM_RT_SRC, "sim_entry", host=C.cast(L.sim_rt_host, C.c_void_p).value, n_in=1, n_out=1,
+                       in_bytes=[16], out_item_bytes=4, scalars=bytes([1, 1]))
+    x = np.zeros(4, np.float32)
+    eng.program_in(0, host=x, dev=x)
+    out = np.zeros(n, np.uint32)
+    eng.program_out(0, dev=out)
+    eng.scheduler(**sched)
+    return eng, out, x
+
+
+@pytest.mark.parametrize("devs", ["host", "both"])
+@pytest.mark.parametrize("sched", ["static", "dynamic", "hguided"])
+def test_failing_host_package_is_reported(simlib, devs, sched):
+    n, lws = 4000, 10
+    d = {"host": ce.CE_DEV_HOST, "both": BOTH}[devs]
+    s = SCHEDS[sched] if devs == "both" else _one_dev(SCHEDS[sched])
+    simlib.sim_set_rates(20.0, 50.0, 1000.0)
+    eng, out, keep = _rt_engine(simlib, n, lws, d, s)
+    # the host version fails on every call: on the first tile the host runs
+    simlib.sim_set_faults(0.0, 1 << 63)
+    simlib.sim_reset(n)
+    try:
+        st = eng.run_status()
+        errs = eng.errors()
+    finally:
+        simlib.sim_set_faults(0.0, ~0 & (2**64 - 1))
+    assert st == ce.CE_E_DEVICE, (st, errs)
+    assert any("host version failed with code 42" in m for m in errs), errs
+    cov = _coverage(simlib, n)
+    assert cov.max() <= 1  # nothing twice
+    assert (cov == 0).any()  # the failed tile's items: reported, not hidden
+    # the engine is usable again
+    eng.clear_errors()
+    simlib.sim_reset(n)
+    eng.run()
+    assert np.all(_coverage(simlib, n) == 1)
+    assert np.array_equal(out, np.arange(n, dtype=np.uint32))
+    eng.close()
+
+
+@pytest.mark.parametrize("kind,size", [("escape", (64, 300)), ("nbody", 6000)])
+@pytest.mark.parametrize("sched", ["dynamic", "hguided"])
+def test_stalled_gpu_claim_is_reported(simlib, kind, size, sched):
+    """The fake GPU's claim stalls until the bounded wait runs out: the run
+    returns CE_E_TIMEOUT within the bound, names the dispenser, and the host
+    still finishes everything the GPU did not take."""
+    simlib.sim_set_rates(1.0, 5.0, 1000.0)
+    simlib.sim_set_faults(50.0, ~0 & (2**64 - 1))
+    eng = ce.Engine(simlib)
+    try:
+        eng.use(BOTH, 0, 4)
+        if kind == "escape":
+            w, h = size
+            eng.work_items([w, h])
+            eng.program_kernel(ce.CE_KERNEL_ESCAPE, ce.ce_escape_params(w, h, -2.0, -1.5, 0.01, 0.01, 10))
+            out = np.zeros((h, w), np.uint32)
+            n_items = w * h
+        else:
+            n = size
+            eng.work_items([n], [256])
+            eng.program_kernel(ce.CE_KERNEL_NBODY_ACC, ce.ce_nbody_params(n, 1e-6, 1))
+            pos = np.zeros((n, 4), np.float32)
+            eng.program_in(0, host=pos, dev=pos)
+            out = np.zeros((n, 4), np.uint32)
+            n_items = n
+        eng.program_out(0, dev=out)
+        eng.scheduler(**SCHEDS[sched])
+        simlib.sim_reset(n_items)
+        t0 = time.perf_counter()
+        st = eng.run_status()
+        dt = time.perf_counter() - t0
+        errs = eng.errors()
+    finally:
+        simlib.sim_set_faults(0.0, ~0 & (2**64 - 1))
+    assert st == ce.CE_E_TIMEOUT, (st, errs)
+    assert any("dispenser wait" in m for m in errs), errs
+    assert dt < 5.0
+    # every item exactly once: the GPU ran only its first package, the host the rest
+    assert np.all(_coverage(simlib, n_items) == 1)
+    eng.clear_errors()
+    simlib.sim_reset(n_items)
+    eng.run()
+    assert np.all(_coverage(simlib, n_items) == 1)
+    eng.close()
+
+
+def test_wait_bounds_validation(simlib):
+    eng = ce.Engine(simlib)
+    for bad in ((-1.0, 0.0), (0.0, 4000.0), (float("nan"), 1.0)):
+        with pytest.raises(ce.CoexecError):
+            eng.wait_bounds(*bad)
+    eng.clear_errors()
+    eng.wait_bounds(0.5, 10.0)
+    eng.wait_bounds(0.0, 0.0)  # defaults
     eng.close()
