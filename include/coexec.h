@@ -429,9 +429,13 @@ const char* ce_batch_error(const ce_batch* b);
  * interleaves the tiles of every admitted job. A job's inputs may instead be
  * device pointers the caller keeps resident. Latency is measured from
  * ce_server_submit to the server thread seeing the job's completion word.
- * A session starts at the first submit and ends at ce_server_drain; while it
- * lasts the serving kernel occupies the GPU's compute units. The per-item
- * arithmetic is that of the CE_KERNEL_* payloads. GPU only. */
+ * A session starts at the first submit and ends at ce_server_drain, when
+ * the kernel has been idle for session_timeout_s, or when it has taken
+ * max_jobs jobs; jobs submitted after that go to a new session, started by
+ * the server thread (a job published just as a session ended is published
+ * again in the next). While a session lasts the serving kernel occupies the
+ * GPU's compute units. The per-item arithmetic is that of the CE_KERNEL_*
+ * payloads. GPU only. */
 #define CE_JOB_QUEUED 0
 #define CE_JOB_ADMITTED 1
 #define CE_JOB_DONE 2
@@ -445,7 +449,8 @@ typedef struct {
   uint32_t workgroups_per_cu; /* serving workgroups per CU; 0 = the occupancy
                                * limit minus one, which leaves room for copies
                                * and the caller's own kernels during a session */
-  double session_timeout_s; /* the kernel leaves after this long; 0 = 300 s  */
+  double session_timeout_s; /* the kernel leaves after this long with no new
+                             * job; 0 = 300 s                                  */
 } ce_server_config;
 typedef struct {
   int32_t kernel_id;        /* CE_KERNEL_*                                    */
@@ -467,6 +472,12 @@ typedef struct {
   uint64_t max_inflight_seen;
 } ce_server_report;
 ce_status ce_server_create(const ce_server_config* cfg, void* hip_stream, ce_server** out);
+/* When a finished job ran on the GPU, in the GPU's s_memrealtime ticks (the
+ * rate is hipDeviceAttributeWallClockRate kHz): the start of its first tile
+ * and the end of its last. Ticks of jobs of one session compare directly, so
+ * overlapping intervals show jobs sharing the device. CE_E_STATE if the job
+ * is not done. */
+ce_status ce_server_job_ticks(ce_server* s, uint64_t ticket, uint64_t* first_tile_tick, uint64_t* done_tick);
 /* Ends the session (waits up to 30 s) and frees everything. NULL-safe. */
 void ce_server_destroy(ce_server* s);
 /* CE_E_BUDGET if the job alone needs more than the HBM budget. */
@@ -483,6 +494,15 @@ ce_status ce_server_release(ce_server* s, uint64_t ticket);
 ce_status ce_server_drain(ce_server* s, double timeout_s);
 ce_status ce_server_stats(const ce_server* s, ce_server_report* r);
 const char* ce_server_error(const ce_server* s);
+
+/* ---- bandwidth reference (not part of the method): copies `bytes` (a
+ * multiple of 16; both pointers 16-byte aligned device pointers, or device
+ * views of pinned host memory) with one non-temporal 16-byte load and store
+ * per thread, on `hip_stream` (NULL = default stream). It is the achievable
+ * streaming rate the HBM-bound payloads are compared with. sync != 0 waits.
+ * Errors: CE_E_INVALID for a size or alignment that does not fit,
+ * CE_E_DEVICE for a launch failure. */
+ce_status ce_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream, int sync);
 
 /* ---- plain single-GPU launch (the "native" side of the overhead metric,
  * section 7.3): one grid launch of the same payload over the whole index

@@ -55,11 +55,11 @@ EXPORTED_SYMBOLS = (
     "ce_engine_create", "ce_engine_destroy", "ce_engine_use", "ce_engine_work_items", "ce_engine_scheduler",
     "ce_engine_stream", "ce_engine_output_merge", "ce_engine_gpu_workgroups", "ce_engine_wait_bounds", "ce_engine_kernel_events", "ce_program_kernel", "ce_program_in", "ce_program_out", "ce_program_out_pattern",
     "ce_engine_run", "ce_engine_run_noalloc", "ce_engine_stats", "ce_engine_trace", "ce_engine_has_errors", "ce_engine_error_count",
-    "ce_engine_error", "ce_engine_clear_errors", "ce_bare_run", "ce_bare_run_outs", "ce_sched_static_plan", "ce_sched_hguided_size",
+    "ce_engine_error", "ce_engine_clear_errors", "ce_stream_copy", "ce_bare_run", "ce_bare_run_outs", "ce_sched_static_plan", "ce_sched_hguided_size",
     "ce_gauss5_weights", "ce_binomial_table", "ce_version", "ce_batch_create", "ce_batch_destroy", "ce_batch_add_escape",
     "ce_batch_clear", "ce_batch_set_config", "ce_batch_get_config", "ce_batch_tune", "ce_batch_run",
     "ce_batch_run_separate", "ce_batch_stats", "ce_batch_error", "ce_server_create", "ce_server_destroy",
-    "ce_server_submit", "ce_server_poll", "ce_server_wait", "ce_server_output", "ce_server_copy_output",
+    "ce_server_submit", "ce_server_job_ticks", "ce_server_poll", "ce_server_wait", "ce_server_output", "ce_server_copy_output",
     "ce_server_release", "ce_server_drain", "ce_server_stats", "ce_server_error", "ce_program_source",
     "ce_rt_compile_check", "ce_rt_code_object", "ce_engine_bare_run_source",
 )
@@ -198,6 +198,7 @@ def load(path: str):
         "ce_engine_error": (C.c_char_p, [vp, C.c_int]),
         "ce_engine_clear_errors": (None, [vp]),
         "ce_bare_run": (i32, [C.c_int, vp, sz, C.POINTER(vp), vp, vp, C.c_int]),
+        "ce_stream_copy": (i32, [vp, vp, sz, vp, C.c_int]),
         "ce_bare_run_outs": (i32, [C.c_int, vp, sz, C.POINTER(vp), C.POINTER(vp), C.c_uint32, vp, C.c_int]),
         "ce_program_source": (i32, [vp, C.POINTER(ce_rt_desc), C.c_char_p, sz]),
         "ce_rt_compile_check": (i32, [C.c_char_p, C.c_char_p, C.c_char_p, sz]),
@@ -224,6 +225,7 @@ def load(path: str):
         "ce_server_create": (i32, [C.POINTER(ce_server_config), vp, C.POINTER(vp)]),
         "ce_server_destroy": (None, [vp]),
         "ce_server_submit": (i32, [vp, C.POINTER(ce_job), C.POINTER(u64)]),
+        "ce_server_job_ticks": (i32, [vp, u64, C.POINTER(u64), C.POINTER(u64)]),
         "ce_server_poll": (i32, [vp, u64, C.POINTER(i32)]),
         "ce_server_wait": (i32, [vp, u64, C.c_double]),
         "ce_server_output": (i32, [vp, u64, C.POINTER(vp), C.POINTER(sz)]),
@@ -330,6 +332,13 @@ def ce_bare_run(kernel_id: int, params, ins, out, stream=None, sync: bool = True
                            _ptr(stream) if stream is not None else None, int(sync))
     if st != CE_OK:
         raise CoexecError(st, "ce_bare_run")
+
+
+def ce_stream_copy(dst, src, nbytes: int, stream=None, sync: bool = True) -> None:
+    """The streaming-copy bandwidth reference (device pointers)."""
+    st = lib().ce_stream_copy(_ptr(dst), _ptr(src), nbytes, _ptr(stream) if stream is not None else None, int(sync))
+    if st != CE_OK:
+        raise CoexecError(st, "ce_stream_copy")
 
 
 def ce_bare_run_outs(kernel_id: int, params, ins, outs, stream=None, sync: bool = True) -> None:
@@ -663,6 +672,12 @@ class Server:
         if keep:
             self._keep[int(t.value)] = keep
         return int(t.value)
+
+    def job_ticks(self, ticket: int):
+        """(first tile start, last tile end) of a finished job, in GPU ticks."""
+        a, b = C.c_uint64(), C.c_uint64()
+        self._check(self._L.ce_server_job_ticks(self._h, ticket, C.byref(a), C.byref(b)), "ce_server_job_ticks")
+        return int(a.value), int(b.value)
 
     def poll(self, ticket: int) -> int:
         v = C.c_int32()

@@ -57,7 +57,28 @@ struct Binding {
   void* dev_out = nullptr;
   size_t bytes = 0;
   bool bound = false;
+  // The GPU's view of the host pointer when the caller's host memory is
+  // pinned (hipHostMalloc, e.g. a pinned torch tensor): the kernel can then
+  // read or write it over PCIe with no copy. Null for pageable memory.
+  void* host_dev = nullptr;
 };
+
+// The device address of pinned host memory at p, or null if p is pageable.
+void* pinned_device_view(const void* p) {
+  if (!p) return nullptr;
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();  // pageable memory: not an error worth keeping
+    return nullptr;
+  }
+  if (a.type != hipMemoryTypeHost) return nullptr;
+  void* d = nullptr;
+  if (hipHostGetDevicePointer(&d, const_cast<void*>(p), 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return d;
+}
 
 // Engine-owned scratch memory that grows on demand.
 struct DevBuf {
@@ -155,9 +176,28 @@ struct ce_engine {
   bool noalloc = false;              // the current run may not allocate
   PkgSlot* trace_pkgs = nullptr;     // package table of the last run
   uint32_t trace_pkgs_cap = 0;
-  double clock_offset_ns = 0.0;  // host_ns = tick * period + offset
+  // GPU tick -> host ns: host_ns = anchor_ns + (tick - anchor_tick) * ns_per_tick.
+  // The anchor is the GPU's latest completion seen as it happened; the rate
+  // is measured between the calibration at creation and that anchor, since
+  // the two clocks drift apart by a few parts per million (tens of
+  // microseconds over a few seconds, as much as a whole blur run).
+  uint64_t anchor0_tick = 0, anchor_tick = 0;
+  double anchor0_ns = 0.0, anchor_ns = 0.0;
+  double ns_per_tick = 10.0;
   double clock_latency_ns = 0.0; // one-way GPU -> host visibility latency (half the best round trip)
   bool clock_ok = false;
+  double tick_to_host_ns(uint64_t tick) const {
+    return anchor_ns + (tick >= anchor_tick ? (double)(tick - anchor_tick) : -(double)(anchor_tick - tick)) * ns_per_tick;
+  }
+  void re_anchor(uint64_t tick, double host_ns) {
+    anchor_tick = tick;
+    anchor_ns = host_ns;
+    const double nominal = 1e9 / (double)wallclock_hz;
+    if (tick > anchor0_tick + (uint64_t)wallclock_hz) {  // at least a second apart
+      const double r = (host_ns - anchor0_ns) / (double)(tick - anchor0_tick);
+      if (r > nominal * 0.999 && r < nominal * 1.001) ns_per_tick = r;
+    }
+  }
   const HostPayloadFns* hp = nullptr;
 
   // ---- configuration
@@ -238,6 +278,7 @@ struct ce_engine {
   uint64_t gpu_pkgs_last = 0;
   uint32_t gpu_grid_last = 0;
   uint32_t grid_override = 0;  // persistent workgroups chosen by the caller (0: the engine chooses)
+  bool pcie_stream = false;    // this run's kernel reads or writes pinned host memory directly
   double dispenser_wait_s = (double)kDispenserWaitSeconds;  // bounds on the kernel's waits
   double gather_wait_s = (double)kGatherWaitSeconds;
 
@@ -266,7 +307,7 @@ struct ce_engine {
   // host_ns under the current mapping (the mapping is off by far less than
   // the 2^40-tick wrap).
   uint64_t unwrap_tick40(uint64_t t40, double host_ns) const {
-    const double est = (host_ns - clock_offset_ns) * ((double)wallclock_hz * 1e-9);
+    const double est = (double)anchor_tick + (host_ns - anchor_ns) / ns_per_tick;
     const uint64_t e = est > 0.0 ? (uint64_t)est : 0;
     const uint64_t half = 1ull << 39;
     uint64_t t = (e & ~kTick40) | t40;
@@ -276,8 +317,7 @@ struct ce_engine {
   }
 
   double tick_to_host_s(uint64_t tick) const {
-    const double ns = (double)tick * (1e9 / (double)wallclock_hz) + clock_offset_ns;
-    return (ns - (double)t0_ns) * 1e-9;
+    return (tick_to_host_ns(tick) - (double)t0_ns) * 1e-9;
   }
 
   // ------------------------------------------------------------ geometry
@@ -296,6 +336,11 @@ struct ce_engine {
   uint64_t rt_item(uint64_t g) const { return std::min<uint64_t>(g * lws0, gws[0]); }
   uint32_t n_bodies() const { return kernel_id == CE_KERNEL_NBODY_STEP ? nbs.n : nb.n; }
   bool is_nbody() const { return kernel_id == CE_KERNEL_NBODY_ACC || kernel_id == CE_KERNEL_NBODY_STEP; }
+  // Whether the GPU kernel reads each input byte about once (streaming), so a
+  // pinned host input is better read over PCIe than copied first. N-body
+  // reads every position once per body block; a runtime payload may read
+  // its inputs any number of times.
+  bool reads_input_once() const { return kernel_id == CE_KERNEL_BLUR5 || kernel_id == CE_KERNEL_BINOMIAL; }
   uint64_t items_in(uint64_t g0, uint64_t g1) const {
     switch (kernel_id) {
       case CE_KERNEL_ESCAPE: return (g1 - g0) * esc.w;
@@ -787,6 +832,9 @@ struct ce_engine {
         uint64_t rows_per_tile = 1;
         while (rows_per_tile < G && gpu_tiles(kargs, 0, rows_per_tile + 1) == tiles_per_g) ++rows_per_tile;
         uint64_t def = std::max<uint64_t>(1, ceil_div((uint64_t)grid, tiles_per_g) * rows_per_tile);
+        // streaming over PCIe, a few workgroups already saturate the link: an
+        // eighth of a round keeps the GPU's last package short
+        if (pcie_stream) def = std::max<uint64_t>(rows_per_tile, ceil_div((uint64_t)grid / 8, tiles_per_g) * rows_per_tile);
         // ... but never more than the GPU's proportional share of the space
         // (where the host is the faster device the GPU must leave it work)
         def = std::min<uint64_t>(def, std::max<uint64_t>(1, G * P[gi] / sumP));
@@ -881,6 +929,8 @@ struct ce_engine {
       for (int s = 0; s < n_in_slots(); ++s) {
         if (in[s].dev) {
           gin[s] = in[s].dev;
+        } else if (in[s].host_dev && reads_input_once()) {
+          gin[s] = in[s].host_dev;  // pinned: the kernel streams it over PCIe
         } else {
           if (!in_dev[s].ensure(in[s].bytes)) return fail(CE_E_NOMEM, "run: device staging for input %d", s);
           if ((he = hipMemcpyAsync(in_dev[s].p, in[s].host, in[s].bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
@@ -891,9 +941,14 @@ struct ce_engine {
     }
     kargs.in0 = gin[0];
     kargs.in1 = gin[1];
+    // the kernel reads or writes host memory over PCIe: its tiles are long
+    pcie_stream = false;
+    for (int s = 0; s < n_in_slots(); ++s) pcie_stream |= use_gpu() && gin[s] && gin[s] == in[s].host_dev;
     void* gpu_out[kMaxSlots] = {nullptr, nullptr};
     for (int s = 0; s < n_out_slots(); ++s) {
       gpu_out[s] = out[s].dev_out;
+      // pinned host output alone: the kernel writes its rows straight into it
+      if (use_gpu() && !gpu_out[s] && out[s].host_dev) gpu_out[s] = out[s].host_dev;
       if (use_gpu() && !gpu_out[s]) {
         if (!out_dev_scratch[s].ensure(out[s].bytes)) return fail(CE_E_NOMEM, "run: device output scratch");
         gpu_out[s] = out_dev_scratch[s].p;
@@ -901,6 +956,7 @@ struct ce_engine {
     }
     kargs.out = gpu_out[0];
     kargs.out1 = gpu_out[1];
+    for (int s = 0; s < n_out_slots(); ++s) pcie_stream |= use_gpu() && gpu_out[s] && gpu_out[s] == out[s].host_dev;
     if (kernel_id == CE_KERNEL_RUNTIME) {
       // generic arguments: inputs, then outputs, then the scalar block
       for (uint32_t k = 0; k < rt_n_in; ++k) kargs.rt.buf[k] = const_cast<void*>(gin[k]);
@@ -1031,7 +1087,11 @@ struct ce_engine {
       // Claim the next package while half a round of tiles is still to be
       // handed out: with the host in the set its output copies share PCIe
       // with the claim's atomics, which can then take tens of microseconds.
-      gs.lookahead = std::max<uint32_t>(1, (grid - gather_wgs) / 2);
+      // When the kernel streams host memory its tiles take milliseconds, a
+      // claim's round trip is negligible beside them, and claiming early
+      // would take work the host could still do: the GPU then claims only
+      // when a workgroup runs out, as the paper's devices do.
+      gs.lookahead = pcie_stream ? 0u : std::max<uint32_t>(1, (grid - gather_wgs) / 2);
       // A Dynamic claim takes as many packages as half a round of tiles holds:
       // the GPU's workgroups are that many requesters, and one PCIe atomic
       // per package would serialise them (about 1 us each).
@@ -1143,7 +1203,7 @@ struct ce_engine {
         // accumulate into the device times.
         const double seen = (double)now_ns() - clock_latency_ns;
         const uint64_t tl = unwrap_tick40(dw & kTick40, seen);
-        clock_offset_ns = seen - (double)tl * (1e9 / (double)wallclock_hz);
+        re_anchor(tl, seen);
       }
       if ((he = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(he, "run: kernel");
       if (!done_is(__atomic_load_n(&l1->gpu_done, __ATOMIC_ACQUIRE), run_id))
@@ -1211,8 +1271,10 @@ struct ce_engine {
         }
       }
     }
-    // GPU-computed ranges (the complement of the host's) into the host output
+    // GPU-computed ranges (the complement of the host's) into the host output,
+    // unless the kernel wrote them there itself
     for (int slot = 0; slot < n_out_slots() && use_gpu() && out[slot].host_out; ++slot) {
+      if (gpu_out[slot] == out[slot].host_dev) continue;
       uint64_t cur = 0;
       auto copy = [&](uint64_t a, uint64_t b) -> ce_status {
         size_t off, len;
@@ -1359,7 +1421,8 @@ struct ce_engine {
     __atomic_store_n(&l1->ping, 0, __ATOMIC_RELEASE);
     __atomic_store_n(&l1->pong, 0, __ATOMIC_RELEASE);
     if (launch_calibrate(l1_dev, rounds, 1ull << 24, stream) != hipSuccess) return;
-    double best_rt = 1e300, best_off = 0.0;
+    double best_rt = 1e300, best_ns = 0.0;
+    uint64_t best_tick = 0;
     bool ok = true;
     for (uint32_t i = 1; i <= rounds && ok; ++i) {
       const int64_t ta = now_ns();
@@ -1378,7 +1441,8 @@ struct ce_engine {
       const double rt = (double)(tb - ta);
       if (rt < best_rt) {
         best_rt = rt;
-        best_off = 0.5 * (double)(ta + tb) - (double)tick * (1e9 / (double)wallclock_hz);
+        best_ns = 0.5 * (double)(ta + tb);
+        best_tick = tick;
       }
     }
     // unblock the kernel if the host gave up early
@@ -1386,7 +1450,9 @@ struct ce_engine {
     (void)hipStreamSynchronize(stream);
     clock_ok = ok;
     if (ok) {
-      clock_offset_ns = best_off;
+      ns_per_tick = 1e9 / (double)wallclock_hz;
+      anchor0_tick = anchor_tick = best_tick;
+      anchor0_ns = anchor_ns = best_ns;
       clock_latency_ns = 0.5 * best_rt;
     }
     else errors.emplace_back("create: GPU clock calibration failed; GPU times are unmapped");
@@ -1571,7 +1637,7 @@ ce_status ce_program_in(ce_engine* e, uint32_t slot, const void* host_ptr, const
   if (!host_ptr && !dev_ptr) return e->fail(CE_E_INVALID, "in: slot %u needs a host or device pointer", slot);
   if (bytes != e->in_bytes((int)slot))
     return e->fail(CE_E_INVALID, "in: slot %u expects %zu bytes, got %zu", slot, e->in_bytes((int)slot), bytes);
-  e->in[slot] = Binding{host_ptr, dev_ptr, nullptr, nullptr, bytes, true};
+  e->in[slot] = Binding{host_ptr, dev_ptr, nullptr, nullptr, bytes, true, dev_ptr ? nullptr : pinned_device_view(host_ptr)};
   return CE_OK;
 }
 
@@ -1581,7 +1647,7 @@ ce_status ce_program_out(ce_engine* e, uint32_t slot, void* host_ptr, void* dev_
   if ((int)slot >= e->n_out_slots()) return e->fail(CE_E_INVALID, "out: kernel has no output slot %u", slot);
   if (!host_ptr && !dev_ptr) return e->fail(CE_E_INVALID, "out: needs a host or device pointer");
   if (bytes != e->out_bytes()) return e->fail(CE_E_INVALID, "out: expects %zu bytes, got %zu", e->out_bytes(), bytes);
-  e->out[slot] = Binding{nullptr, nullptr, host_ptr, dev_ptr, bytes, true};
+  e->out[slot] = Binding{nullptr, nullptr, host_ptr, dev_ptr, bytes, true, dev_ptr ? nullptr : pinned_device_view(host_ptr)};
   return CE_OK;
 }
 
@@ -1749,6 +1815,15 @@ const char* ce_engine_error(const ce_engine* e, int i) {
 }
 void ce_engine_clear_errors(ce_engine* e) {
   if (e) e->errors.clear();
+}
+
+ce_status ce_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream, int sync) {
+  if (!dst || !src || (bytes % 16) != 0 || ((uintptr_t)dst % 16) != 0 || ((uintptr_t)src % 16) != 0)
+    return CE_E_INVALID;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (launch_stream_copy(dst, src, bytes / 16, st) != hipSuccess) return CE_E_DEVICE;
+  if (sync && hipStreamSynchronize(st) != hipSuccess) return CE_E_DEVICE;
+  return CE_OK;
 }
 
 ce_status ce_bare_run(int kernel_id, const void* params, size_t params_size, const void* const* ins, void* out,

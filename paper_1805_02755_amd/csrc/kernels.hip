@@ -174,6 +174,25 @@ hipError_t launch_bare(const KernelArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Streaming copy, the achievable-bandwidth reference for the HBM-bound
+// payloads: one 16-byte non-temporal load and store per thread, one
+// workgroup per 4 KiB (the fastest of the shapes measured on this GPU:
+// 1, 2, 4 or 8 vectors per thread, temporal or not, one-shot or grid-stride).
+__global__ __launch_bounds__(kBlockThreads) void k_stream_copy(f32x4* __restrict__ dst, const f32x4* __restrict__ src,
+                                                               uint64_t n16) {
+  const uint64_t i = (uint64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+  if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+hipError_t launch_stream_copy(void* dst, const void* src, uint64_t n16, hipStream_t st) {
+  if (n16 == 0) return hipSuccess;
+  const uint64_t blocks = (n16 + kBlockThreads - 1) / kBlockThreads;
+  if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_stream_copy, dim3((uint32_t)blocks), dim3(kBlockThreads), 0, st, (f32x4*)dst,
+                     (const f32x4*)src, n16);
+  return hipGetLastError();
+}
+
 hipError_t launch_calibrate(L1State* l1, uint32_t rounds, uint64_t spin_limit, hipStream_t st) {
   hipLaunchKernelGGL(k_calibrate, dim3(1), dim3(64), 0, st, l1, rounds, spin_limit);
   return hipGetLastError();

@@ -55,6 +55,8 @@ void rt_release(void* module);
 // zero fill of n 64-bit words on a stream.
 hipError_t noalloc_scratch_address(int device, void** out);
 hipError_t launch_zero_words(void* p, uint64_t n_words, hipStream_t st);
+// Streaming copy of n16 16-byte vectors (the bandwidth reference).
+hipError_t launch_stream_copy(void* dst, const void* src, uint64_t n16, hipStream_t st);
 // Clock calibration: one thread answers `rounds` pings through the mailbox.
 hipError_t launch_calibrate(L1State* l1, uint32_t rounds, uint64_t spin_limit, hipStream_t st);
 

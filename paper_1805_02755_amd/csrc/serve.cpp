@@ -140,6 +140,8 @@ struct JobRec {
   ServeDesc desc{};
   int32_t state = CE_JOB_QUEUED;
   int64_t t_submit = 0, t_admit = 0, t_done = 0;
+  uint64_t tick_first = 0, tick_done = 0;  // GPU ticks: first tile start, last tile end
+  std::string why;                        // why the job failed
   uint64_t mem_off = 0, mem_bytes = 0, out_bytes = 0;
   bool has_mem = false;
   uint64_t items = 0;
@@ -186,9 +188,11 @@ struct ce_server {
   ServeDesc* ring = nullptr;
   ServeCtl* ctl = nullptr;
   uint64_t* done_words = nullptr;
+  uint64_t* first_words = nullptr;
   ServeDesc* ring_dev = nullptr;
   ServeCtl* ctl_dev = nullptr;
   uint64_t* done_dev = nullptr;
+  uint64_t* first_dev = nullptr;
 
   std::mutex mu;
   std::mutex copy_mu;                // serialises use of copy_stream and staging
@@ -260,14 +264,17 @@ struct ce_server {
     const unsigned fl = hipHostMallocCoherent | hipHostMallocMapped;
     if ((he = hipHostMalloc((void**)&ring, cap * sizeof(ServeDesc), fl)) != hipSuccess ||
         (he = hipHostMalloc((void**)&ctl, sizeof(ServeCtl), fl)) != hipSuccess ||
-        (he = hipHostMalloc((void**)&done_words, cap * sizeof(uint64_t), fl)) != hipSuccess)
+        (he = hipHostMalloc((void**)&done_words, cap * sizeof(uint64_t), fl)) != hipSuccess ||
+        (he = hipHostMalloc((void**)&first_words, cap * sizeof(uint64_t), fl)) != hipSuccess)
       return fail(CE_E_NOMEM, "host-coherent rings: %s", hipGetErrorString(he));
     memset(ring, 0, cap * sizeof(ServeDesc));
     memset(ctl, 0, sizeof(ServeCtl));
     memset(done_words, 0, cap * sizeof(uint64_t));
+    memset(first_words, 0, cap * sizeof(uint64_t));
     if ((he = hipHostGetDevicePointer((void**)&ring_dev, ring, 0)) != hipSuccess ||
         (he = hipHostGetDevicePointer((void**)&ctl_dev, ctl, 0)) != hipSuccess ||
-        (he = hipHostGetDevicePointer((void**)&done_dev, done_words, 0)) != hipSuccess)
+        (he = hipHostGetDevicePointer((void**)&done_dev, done_words, 0)) != hipSuccess ||
+        (he = hipHostGetDevicePointer((void**)&first_dev, first_words, 0)) != hipSuccess)
       return fail(CE_E_DEVICE, "device views: %s", hipGetErrorString(he));
     worker = std::thread([this] { loop(); });
     return CE_OK;
@@ -290,6 +297,7 @@ struct ce_server {
     if (ring) (void)hipHostFree(ring);
     if (ctl) (void)hipHostFree(ctl);
     if (done_words) (void)hipHostFree(done_words);
+    if (first_words) (void)hipHostFree(first_words);
   }
 
   // Starts a serving session: clears the kernel's state and launches it.
@@ -304,7 +312,9 @@ struct ce_server {
     __atomic_store_n(&ctl->head, 0, __ATOMIC_RELEASE);
     __atomic_store_n(&ctl->stop, 0, __ATOMIC_RELEASE);
     __atomic_store_n(&ctl->flags, 0, __ATOMIC_RELEASE);
+    __atomic_store_n(&ctl->consumed, 0, __ATOMIC_RELEASE);
     memset(done_words, 0, cap * sizeof(uint64_t));
+    memset(first_words, 0, cap * sizeof(uint64_t));
     if ((he = hipMemsetAsync(state, 0, sizeof(ServeState), stream)) != hipSuccess ||
         (he = hipMemsetAsync(pub, 0, cap * sizeof(uint64_t), stream)) != hipSuccess ||
         (he = hipMemsetAsync(tiles_done, 0, cap * sizeof(uint32_t), stream)) != hipSuccess)
@@ -319,9 +329,10 @@ struct ce_server {
     a.q = state;
     a.ctl = ctl_dev;
     a.done_words = done_dev;
+    a.first_words = first_dev;
     a.cap = (uint32_t)cap;
     a.session = session;
-    a.deadline = (uint64_t)(cfg.session_timeout_s * (double)wallclock_hz);
+    a.idle_ticks = (uint64_t)(cfg.session_timeout_s * (double)wallclock_hz);
     const uint32_t per_cu = cfg.workgroups_per_cu ? std::min<uint32_t>(cfg.workgroups_per_cu, (uint32_t)std::max(1, bpc))
                                                   : (uint32_t)std::max(1, bpc - 1);
     const uint32_t grid = per_cu * (uint32_t)n_cu;
@@ -375,11 +386,11 @@ struct ce_server {
     d.seq = head;
     lk.unlock();
     std::unique_lock<std::mutex> ck(copy_mu);
-    bool ok = true;
-    if (copy0 && staging.to_device((void*)d.in0, r.job.in0_host, in_bytes_of(r.job, 0), copy_stream) != hipSuccess)
-      ok = false;
-    if (ok && copy1 && staging.to_device((void*)d.in1, r.job.in1_host, in_bytes_of(r.job, 1), copy_stream) != hipSuccess)
-      ok = false;
+    hipError_t ce_ = hipSuccess;
+    if (copy0) ce_ = staging.to_device((void*)d.in0, r.job.in0_host, in_bytes_of(r.job, 0), copy_stream);
+    if (ce_ == hipSuccess && copy1)
+      ce_ = staging.to_device((void*)d.in1, r.job.in1_host, in_bytes_of(r.job, 1), copy_stream);
+    const bool ok = ce_ == hipSuccess;
     ck.unlock();
     lk.lock();
     if (ok && !session_on) {  // the session ended while the inputs were copied: retry in the next one
@@ -390,6 +401,7 @@ struct ce_server {
     }
     if (!ok) {
       r.state = CE_JOB_FAILED;
+      r.why = std::string("copying its inputs into HBM failed: ") + hipGetErrorString(ce_);
       arena.release(r.mem_off, r.mem_bytes);
       r.has_mem = false;
       cv.notify_all();
@@ -398,11 +410,7 @@ struct ce_server {
     r.desc = d;
     r.t_admit = now_ns();
     r.state = CE_JOB_ADMITTED;
-    session_tiles += d.ntiles;
-    ring[head] = d;  // the descriptor is complete before head moves
-    seq_ticket.push_back(tk);
-    ++head;
-    __atomic_store_n(&ctl->head, head, __ATOMIC_RELEASE);
+    publish(tk);
     inflight.push_back(tk);
     max_inflight_seen = std::max<uint64_t>(max_inflight_seen, inflight.size());
     return true;
@@ -413,8 +421,11 @@ struct ce_server {
     for (size_t i = 0; i < inflight.size();) {
       const uint64_t tk = inflight[i];
       JobRec& r = jobs[tk];
-      if (__atomic_load_n(&done_words[r.desc.seq], __ATOMIC_ACQUIRE) != 0) {
+      const uint64_t dw = __atomic_load_n(&done_words[r.desc.seq], __ATOMIC_ACQUIRE);
+      if (dw != 0) {
         r.t_done = now_ns();
+        r.tick_done = dw & ~1ull;
+        r.tick_first = __atomic_load_n(&first_words[r.desc.seq], __ATOMIC_ACQUIRE);
         t_last_done = r.t_done;
         r.state = CE_JOB_DONE;
         if (!cfg.keep_outputs && r.has_mem) {
@@ -432,10 +443,99 @@ struct ce_server {
     return any;
   }
 
+  // Publishes an admitted job in the current session (mu held).
+  void publish(uint64_t tk) {
+    JobRec& r = jobs[tk];
+    r.desc.seq = head;
+    session_tiles += r.desc.ntiles;
+    ring[head] = r.desc;  // the descriptor is complete before head moves
+    seq_ticket.push_back(tk);
+    ++head;
+    __atomic_store_n(&ctl->head, head, __ATOMIC_RELEASE);
+  }
+
+  // The session can take no more jobs (its kernel left when idle, or the
+  // ring or the tile space is full): end it, and start the next one for the
+  // jobs waiting, publishing first any admitted job the kernel never took.
+  // Called with mu held, by the server thread only.
+  void roll_over(std::unique_lock<std::mutex>& lk, bool ended) {
+    if (!ended) __atomic_store_n(&ctl->stop, 1, __ATOMIC_SEQ_CST);
+    const uint64_t sess = session;
+    lk.unlock();
+    const int64_t limit = now_ns() + 10'000'000'000LL;
+    while (__atomic_load_n(&ctl->exited, __ATOMIC_ACQUIRE) != sess && now_ns() < limit) _mm_pause();
+    const hipError_t he = hipStreamSynchronize(stream);
+    lk.lock();
+    if (he != hipSuccess || __atomic_load_n(&ctl->exited, __ATOMIC_ACQUIRE) != sess) {
+      fail(CE_E_DEVICE, "serving kernel did not end: %s", hipGetErrorString(he));
+      return;
+    }
+    collect(lk);
+    const uint64_t consumed = __atomic_load_n(&ctl->consumed, __ATOMIC_ACQUIRE);
+    std::vector<uint64_t> again;
+    for (size_t i = 0; i < inflight.size();) {
+      JobRec& r = jobs[inflight[i]];
+      if (r.desc.seq >= consumed) {
+        again.push_back(inflight[i]);
+      } else {
+        // taken by the kernel but never finished (it gave up on an invisible job)
+        r.state = CE_JOB_FAILED;
+        r.why = "the serving kernel took it but ended before finishing it";
+        if (r.has_mem) {
+          arena.release(r.mem_off, r.mem_bytes);
+          r.has_mem = false;
+        }
+        fail(CE_E_DEVICE, "serving kernel dropped job %llu", (unsigned long long)inflight[i]);
+      }
+      inflight[i] = inflight.back();
+      inflight.pop_back();
+    }
+    std::sort(again.begin(), again.end(), [&](uint64_t a, uint64_t b) { return jobs[a].desc.seq < jobs[b].desc.seq; });
+    session_on = false;
+    if (again.empty() && pending.empty()) return;
+    if (start_session() != CE_OK) {
+      for (uint64_t tk : again) {
+        jobs[tk].state = CE_JOB_FAILED;
+        jobs[tk].why = "no new session could be started for it";
+        if (jobs[tk].has_mem) {
+          arena.release(jobs[tk].mem_off, jobs[tk].mem_bytes);
+          jobs[tk].has_mem = false;
+        }
+      }
+      cv.notify_all();
+      return;
+    }
+    for (uint64_t tk : again) {
+      publish(tk);
+      inflight.push_back(tk);
+    }
+    cv.notify_all();
+  }
+
+  // Whether the oldest pending job would fit this session's tile space.
+  bool next_fits_tiles() const {
+    if (pending.empty()) return true;
+    const JobRec& r = jobs[pending.front()];
+    ServeDesc probe{};
+    probe.kind = (uint32_t)r.job.kernel_id;
+    probe.esc = r.job.esc;
+    probe.blur = r.job.blur;
+    probe.nb = r.job.nb;
+    return session_tiles + serve_tiles(probe) <= kServeTotalMask;
+  }
+
   void loop() {
     std::unique_lock<std::mutex> lk(mu);
     while (!quit.load()) {
       bool progress = collect(lk);
+      if (session_on) {
+        const bool ended = __atomic_load_n(&ctl->exited, __ATOMIC_ACQUIRE) == session;
+        const bool full = !pending.empty() && (head >= cfg.max_jobs || !next_fits_tiles());
+        if (ended || (full && inflight.empty())) {
+          roll_over(lk, ended);
+          progress = true;
+        }
+      }
       while (admit_one(lk)) progress = true;
       if (!progress) {
         if (inflight.empty() && pending.empty()) {
@@ -491,7 +591,9 @@ struct ce_server {
       if (cv.wait_until(lk, until) == std::cv_status::timeout && std::chrono::steady_clock::now() >= until)
         return fail(CE_E_TIMEOUT, "wait: job %llu not done", (unsigned long long)tk);
     }
-    return jobs[tk].state == CE_JOB_DONE ? CE_OK : fail(CE_E_DEVICE, "job %llu failed", (unsigned long long)tk);
+    return jobs[tk].state == CE_JOB_DONE
+               ? CE_OK
+               : fail(CE_E_DEVICE, "job %llu failed: %s", (unsigned long long)tk, jobs[tk].why.c_str());
   }
 
   // Waits for every submitted job, then ends the session (the kernel leaves).
@@ -545,6 +647,17 @@ ce_status ce_server_submit(ce_server* s, const ce_job* job, uint64_t* ticket) {
   } catch (...) {
     return CE_E_NOMEM;
   }
+}
+
+ce_status ce_server_job_ticks(ce_server* s, uint64_t ticket, uint64_t* first_tile_tick, uint64_t* done_tick) {
+  if (!s || !first_tile_tick || !done_tick) return CE_E_INVALID;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (ticket >= s->jobs.size()) return s->fail(CE_E_INVALID, "job_ticks: unknown ticket");
+  const JobRec& r = s->jobs[ticket];
+  if (r.state != CE_JOB_DONE) return s->fail(CE_E_STATE, "job_ticks: job not done");
+  *first_tile_tick = r.tick_first;
+  *done_tick = r.tick_done;
+  return CE_OK;
 }
 
 ce_status ce_server_poll(ce_server* s, uint64_t ticket, int32_t* state) {

@@ -35,9 +35,10 @@ struct alignas(64) ServeState {
   uint64_t ct;          // done << 63 | jobs copied from the host ring << 40 | tiles of those jobs
   uint32_t pad_done;
   uint32_t exit_count;
-  uint32_t flags;       // bit 0: deadline reached
+  uint32_t flags;       // bit 0: a published job stayed invisible past the idle bound
   uint32_t pad0;
-  uint64_t pad[4];
+  uint64_t t_active;    // s_memrealtime when the last job was appended (0: none yet)
+  uint64_t pad[3];
 };
 constexpr uint32_t kServeTotalBits = 40;  // tiles per session < 2^40
 constexpr uint64_t kServeTotalMask = (1ull << kServeTotalBits) - 1;
@@ -50,7 +51,8 @@ struct alignas(64) ServeCtl {
   uint64_t stop;        // 1: no more jobs will be published (host writes)
   uint64_t exited;      // session id, written by the last workgroup out
   uint64_t flags;       // error bits from the kernel
-  uint64_t pad[4];
+  uint64_t consumed;    // jobs the kernel took from the ring (written before exited)
+  uint64_t pad[3];
 };
 
 struct ServeArgs {
@@ -61,10 +63,11 @@ struct ServeArgs {
   ServeState* q;          // HBM
   ServeCtl* ctl;          // device view of the host control block
   uint64_t* done_words;   // device view of host completion words, one per job
+  uint64_t* first_words;  // device view of host words: tick of each job's first tile
   uint32_t cap;           // jobs per session
   uint32_t pad;
   uint64_t session;
-  uint64_t deadline;      // s_memrealtime tick after which the kernel leaves
+  uint64_t idle_ticks;    // the kernel leaves after this many ticks with no new job
 };
 
 uint32_t serve_tiles(const ServeDesc& d);  // GPU tiles of a job

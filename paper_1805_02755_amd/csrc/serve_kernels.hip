@@ -22,8 +22,9 @@ constexpr uint32_t kDescWords = sizeof(ServeDesc) / 8;
 
 __device__ __forceinline__ uint64_t sys_load_c(const uint64_t* p) { return sys_load(const_cast<uint64_t*>(p)); }
 
-// Takes the next tile ticket; returns false when the session is over.
-__device__ bool serve_next(const ServeArgs& a, uint64_t deadline, uint32_t* p_cache, uint64_t* base_cache,
+// Takes the next tile ticket; returns false when the session is over (the
+// host said stop, the ring is full, or no job came for idle_ticks).
+__device__ bool serve_next(const ServeArgs& a, uint64_t t_start, uint32_t* p_cache, uint64_t* base_cache,
                            uint32_t* job, uint32_t* ti, uint32_t* nt) {
   ServeState* q = a.q;
   const uint64_t t = dev_add(&q->ticket, (uint64_t)1);
@@ -54,18 +55,22 @@ __device__ bool serve_next(const ServeArgs& a, uint64_t deadline, uint32_t* p_ca
         for (uint32_t k = 0; k < kDescWords; ++k) dev_store(dst + k, w[k]);
         const uint32_t ntl = (uint32_t)w[1];  // ntiles: low half of the second word
         __hip_atomic_store(&a.pub[c], (uint64_t)ntl, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        dev_store(&q->t_active, now_tick());
         dev_store(&q->ct, ((c + 1) << kServeTotalBits) | (tot + ntl));
         continue;
       }
-      if (stop || c >= a.cap) {
+      // Idle: no job appended for idle_ticks, a normal end of the session
+      // (the host publishes a job that comes too late in the next one). Only
+      // this workgroup appends jobs and writes ct, so the two decisions
+      // cannot cross. The tick of the last append may be later than this
+      // workgroup's clock read: compare, never subtract blindly.
+      const uint64_t now = now_tick();
+      uint64_t ta = dev_load(&q->t_active);
+      if (ta < t_start) ta = t_start;
+      if (stop || c >= a.cap || (now > ta && now - ta > a.idle_ticks)) {
         dev_store(&q->ct, ct | kServeDone);  // only this workgroup writes ct now
         return false;
       }
-    }
-    if (now_tick() > deadline) {
-      dev_store(&q->flags, 1u);
-      __hip_atomic_fetch_or(&q->ct, kServeDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
     }
     if (t == tot)
       __builtin_amdgcn_s_sleep(2);
@@ -74,10 +79,11 @@ __device__ bool serve_next(const ServeArgs& a, uint64_t deadline, uint32_t* p_ca
   }
   uint32_t p = *p_cache;
   uint64_t base = *base_cache;
-  for (;;) {
+  for (uint64_t t1 = 0;;) {
     const uint64_t n = dev_load(&a.pub[p]);
     if (n == 0) {  // published but not visible here yet
-      if (now_tick() > deadline) {
+      if (t1 == 0) t1 = now_tick();
+      if (now_tick() - t1 > a.idle_ticks) {
         dev_store(&q->flags, 1u);
         return false;
       }
@@ -122,7 +128,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_serve(ServeArgs a) {
   __shared__ uint32_t sh_go, sh_job, sh_ti, sh_nt;
   const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) == 0;
   const bool lane0 = threadIdx.x == 0;
-  const uint64_t deadline = now_tick() + a.deadline;
+  const uint64_t t_start = now_tick();
   uint32_t p_cache = 0, cur_job = 0xFFFFFFFFu, prev_job = 0xFFFFFFFFu, prev_nt = 0;
   uint64_t base_cache = 0;
   for (;;) {
@@ -139,7 +145,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_serve(ServeArgs a) {
           }
         }
         uint32_t job = 0, ti = 0, nt = 0;
-        const bool go = serve_next(a, deadline, &p_cache, &base_cache, &job, &ti, &nt);
+        const bool go = serve_next(a, t_start, &p_cache, &base_cache, &job, &ti, &nt);
+        // the job's first tile: its start is when the job reached the device
+        if (go && ti == 0) sys_store(&a.first_words[job], now_tick());
         if (go && job != cur_job) {
           // descriptor of a new job: coherent loads from its table entry
           const uint64_t* src = reinterpret_cast<const uint64_t*>(&a.table[job]);
@@ -170,6 +178,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_serve(ServeArgs a) {
       const uint32_t ex = dev_add(&a.q->exit_count, 1u);
       if (ex + 1 == gridDim.x) {
         if (dev_load(&a.q->flags)) sys_store(&a.ctl->flags, 1);
+        // jobs taken from the ring: the host publishes any later one again
+        sys_store(&a.ctl->consumed, (dev_load(&a.q->ct) & ~kServeDone) >> kServeTotalBits);
         sys_store_release(&a.ctl->exited, a.session);
       }
     }

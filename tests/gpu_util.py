@@ -34,8 +34,12 @@ def _sched_for(name, devs):
 def run_payload(eng, kernel_id, params, gws, lws, inputs, out_shape, out_dtype, devs, sched, mode="dev",
                 host_threads=0, merge=ce.CE_MERGE_DMA):
     """inputs: list of numpy arrays. mode: 'dev' (device-resident in and out,
-    host mirror of inputs), 'host' (host pointers only), 'both' (everything
-    bound on both sides). Returns (output ndarray, stats, trace)."""
+    host mirror of inputs), 'host' (host pointers only), 'pinned' (host
+    pointers only, into pinned host memory the GPU reads and writes over
+    PCIe), 'both' (everything bound on both sides). Returns (output ndarray,
+    stats, trace)."""
+    if mode == "pinned":
+        inputs = [pinned_copy(a) for a in inputs]
     eng.use(devs, 0, host_threads)
     eng.output_merge(merge)
     eng.work_items(gws, lws)
@@ -43,7 +47,7 @@ def run_payload(eng, kernel_id, params, gws, lws, inputs, out_shape, out_dtype, 
     eng.program_kernel(kernel_id, params)
     keep = []
     for slot, a in enumerate(inputs):
-        if mode == "host":
+        if mode in ("host", "pinned"):
             eng.program_in(slot, host=a)
         else:
             d = torch.from_numpy(a).to(DEV)
@@ -53,6 +57,8 @@ def run_payload(eng, kernel_id, params, gws, lws, inputs, out_shape, out_dtype, 
     nbytes_out = int(np.prod(out_shape)) * np.dtype(out_dtype).itemsize
     out_h = (np.full(nbytes_out, 0xFF, dtype=np.uint8).view(out_dtype).reshape(out_shape)
              if mode in ("host", "both") else None)
+    if mode == "pinned":
+        out_h = pinned_copy(np.full(nbytes_out, 0xFF, dtype=np.uint8)).view(out_dtype).reshape(out_shape)
     out_d = None
     if mode in ("dev", "both"):
         nbytes = int(np.prod(out_shape)) * np.dtype(out_dtype).itemsize
@@ -63,7 +69,7 @@ def run_payload(eng, kernel_id, params, gws, lws, inputs, out_shape, out_dtype, 
     eng.run()
     st = eng.stats()
     tr = eng.trace()
-    if mode == "host":
+    if mode in ("host", "pinned"):
         res = out_h
     else:
         res = out_d.cpu().numpy().view(out_dtype).reshape(out_shape)
@@ -71,6 +77,21 @@ def run_payload(eng, kernel_id, params, gws, lws, inputs, out_shape, out_dtype, 
             assert np.array_equal(res.view(np.uint8), out_h.view(np.uint8)), "host and device copies differ"
     del keep
     return res, st, tr
+
+
+_PINNED_KEEP = []
+
+
+def pinned_copy(a):
+    """A copy of a numpy array in pinned host memory (hipHostMalloc through
+    torch); the tensor is kept alive for the module's lifetime."""
+    t = torch.empty(a.nbytes, dtype=torch.uint8, pin_memory=True)
+    _PINNED_KEEP.append(t)
+    if len(_PINNED_KEEP) > 64:
+        del _PINNED_KEEP[:32]
+    v = t.numpy().view(a.dtype).reshape(a.shape)
+    v[...] = a
+    return v
 
 
 def diff_report(out, ref, tr=None):

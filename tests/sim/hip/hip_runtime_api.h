@@ -38,3 +38,14 @@ hipError_t hipEventDestroy(hipEvent_t);
 hipError_t hipEventQuery(hipEvent_t);
 hipError_t hipEventSynchronize(hipEvent_t);
 const char* hipGetErrorString(hipError_t);
+hipError_t hipGetLastError();
+enum hipMemoryType { hipMemoryTypeUnregistered = 0, hipMemoryTypeHost = 1, hipMemoryTypeDevice = 2 };
+typedef struct hipPointerAttribute_t {
+  enum hipMemoryType type;
+  int device;
+  void* devicePointer;
+  void* hostPointer;
+  int isManaged;
+  unsigned allocationFlags;
+} hipPointerAttribute_t;
+hipError_t hipPointerGetAttributes(hipPointerAttribute_t*, const void*);

@@ -18,7 +18,9 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <mutex>
 #include <thread>
+#include <vector>
 
 #include "../../paper_1805_02755_amd/csrc/host_payloads.hpp"
 #include "../../paper_1805_02755_amd/csrc/kernels.hpp"
@@ -116,6 +118,33 @@ hipError_t hipEventDestroy(hipEvent_t e) {
 hipError_t hipEventQuery(hipEvent_t) { return hipSuccess; }
 hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
 const char* hipGetErrorString(hipError_t) { return "sim"; }
+hipError_t hipGetLastError() { return hipSuccess; }
+
+// Memory a test marked as pinned (sim_pin) is "host memory" to the engine;
+// everything else is pageable.
+namespace {
+std::mutex g_pin_mu;
+std::vector<std::pair<uintptr_t, size_t>> g_pinned;
+}  // namespace
+extern "C" void sim_pin(void* p, size_t n) {
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pinned.emplace_back((uintptr_t)p, n);
+}
+extern "C" void sim_unpin_all() {
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pinned.clear();
+}
+hipError_t hipPointerGetAttributes(hipPointerAttribute_t* a, const void* p) {
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  for (auto& r : g_pinned) {
+    if ((uintptr_t)p >= r.first && (uintptr_t)p < r.first + r.second) {
+      a->type = hipMemoryTypeHost;
+      a->devicePointer = a->hostPointer = const_cast<void*>(p);
+      return hipSuccess;
+    }
+  }
+  return hipErrorInvalidValue;
+}
 
 namespace ce {
 
@@ -337,6 +366,11 @@ hipError_t noalloc_scratch_address(int, void** out) {
 hipError_t launch_zero_words(void* p, uint64_t n_words, hipStream_t) {
   join_gpu();
   memset(p, 0, n_words * sizeof(uint64_t));
+  return hipSuccess;
+}
+
+hipError_t launch_stream_copy(void* dst, const void* src, uint64_t n16, hipStream_t) {
+  memcpy(dst, src, n16 * 16);
   return hipSuccess;
 }
 

@@ -101,3 +101,24 @@ def test_nbody_dynamic_one_granule_65536_every_package(eng, mode, monkeypatch):
         for i in (g * 256, g * 256 + 255, g * 256 + int(inner[g])):
             want = O.nbody_acc_body(pos, 1e-6, i, True)
             assert np.array_equal(out[i].view(np.uint32), want.view(np.uint32)), (g, i, out[i], want)
+
+
+@pytest.mark.parametrize("host_threads", [1, 0])
+@pytest.mark.parametrize("sched", ["c1", "hguided", "dynamic"])
+def test_device_times_lie_inside_the_run(eng, escape_ref, monkeypatch, host_threads, sched):
+    """T_d (section 7.3) of each device, mapped from the GPU's clock to the
+    host's, ends before the run returns, and the GPU's own span fits it."""
+    p, ref = escape_ref
+    monkeypatch.setitem(SCHEDULES, "c1", STATIC8["gpu7_host1"])
+    for _ in range(5):
+        out, st, tr = run_payload(eng, ce.CE_KERNEL_ESCAPE, escape_params(p), [p.w, p.h], None, [], (p.h, p.w),
+                                  np.uint32, BOTH, sched, host_threads=host_threads)
+        assert np.array_equal(out, ref)
+        for d in range(st.n_devices):
+            if st.packages[d] == 0:  # a device that got no package has T_d = 0 (G-7)
+                assert st.t_device[d] == 0.0
+                continue
+            assert 0.0 < st.t_device[d] <= st.t_run + 10e-6, (d, st.t_device[d], st.t_run, st.t_gpu_kernel)
+        assert st.t_gpu_kernel <= st.t_device[0] + 10e-6, (st.t_gpu_kernel, st.t_device[0])
+        for d, b, e, tc, te in tr:
+            assert -10e-6 <= tc <= te <= st.t_run + 10e-6, (d, b, e, tc, te, st.t_run)

@@ -37,6 +37,9 @@ def simlib(tmp_path_factory):
     L.sim_set_rates.argtypes = [C.c_double, C.c_double, C.c_double]
     L.sim_reset.restype = None
     L.sim_reset.argtypes = [C.c_size_t]
+    L.sim_pin.restype = None
+    L.sim_pin.argtypes = [C.c_void_p, C.c_size_t]
+    L.sim_unpin_all.restype = None
     L.sim_set_faults.restype = None
     L.sim_set_faults.argtypes = [C.c_double, C.c_uint64]
     L.sim_coverage.restype = None
@@ -640,3 +643,60 @@ def test_wait_bounds_validation(simlib):
     eng.wait_bounds(0.5, 10.0)
     eng.wait_bounds(0.0, 0.0)  # defaults
     eng.close()
+
+
+# ------------------------------------------------------ pinned host buffers
+@pytest.mark.parametrize("kind,size", [("escape", (300, 77)), ("blur", (1000, 61)), ("nbody", 3000)])
+@pytest.mark.parametrize("sched", ["static", "dynamic", "hguided"])
+@pytest.mark.parametrize("devs", ["gpu", "both"])
+def test_pinned_host_buffers(simlib, kind, size, sched, devs):
+    """Host-resident run whose host buffers are pinned: the GPU reads the
+    streamed inputs and writes its rows in place over PCIe, so no merge copy
+    is needed; every item still lands once, in the caller's buffer."""
+    L = simlib
+    L.sim_set_rates(1.0, 5.0, 1000.0)
+    d = BOTH if devs == "both" else ce.CE_DEV_GPU
+    s = SCHEDS[sched] if devs == "both" else _one_dev(SCHEDS[sched])
+    eng = ce.Engine(L)
+    keep = []
+    try:
+        eng.use(d, 0, 4)
+        if kind == "escape":
+            w, h = size
+            eng.work_items([w, h])
+            eng.program_kernel(ce.CE_KERNEL_ESCAPE, ce.ce_escape_params(w, h, -2.0, -1.5, 0.01, 0.01, 10))
+            out = np.zeros((h, w), np.uint32)
+            n_items = w * h
+        elif kind == "blur":
+            w, h = size
+            eng.work_items([w, h])
+            eng.program_kernel(ce.CE_KERNEL_BLUR5, ce.ce_blur5_params(w, h))
+            img, wt = np.zeros((h, w), np.float32), np.zeros(25, np.float32)
+            keep += [img, wt]
+            for a in keep:
+                L.sim_pin(a.ctypes.data, a.nbytes)
+            eng.program_in(0, host=img)
+            eng.program_in(1, host=wt)
+            out = np.zeros((h, w), np.uint32)
+            n_items = w * h
+        else:
+            n = size
+            eng.work_items([n], [256])
+            eng.program_kernel(ce.CE_KERNEL_NBODY_ACC, ce.ce_nbody_params(n, 1e-6, 1))
+            pos = np.zeros((n, 4), np.float32)
+            keep.append(pos)
+            L.sim_pin(pos.ctypes.data, pos.nbytes)
+            eng.program_in(0, host=pos)
+            out = np.zeros((n, 4), np.uint32)
+            n_items = n
+        L.sim_pin(out.ctypes.data, out.nbytes)
+        eng.program_out(0, host=out)
+        eng.scheduler(**s)
+        L.sim_reset(n_items)
+        eng.run()
+        vals = out[:, 0] if kind == "nbody" else out.reshape(-1)
+        assert np.array_equal(vals, np.arange(n_items, dtype=np.uint32))
+        assert np.all(_coverage(L, n_items) == 1)
+    finally:
+        eng.close()
+        L.sim_unpin_all()

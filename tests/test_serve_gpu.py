@@ -1,7 +1,11 @@
 """Serving form (continuous batching on one persistent serving kernel):
 outputs of jobs admitted while others run are bit-identical to the oracle's
 and to the same job run alone; HBM-budget and in-flight admission limits
-hold; sessions restart; invalid and oversized jobs are refused."""
+hold; jobs submitted together run at the same time on the device; sessions
+restart, roll over when full and end when idle; invalid and oversized jobs
+are refused."""
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -13,7 +17,7 @@ from oracle import oracle as O
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
 MiB = 1 << 20
-SESSION_S = 60.0  # the serving kernel leaves by itself after this long
+SESSION_S = 60.0  # the serving kernel leaves by itself after this long without a new job
 
 
 def _esc(p):
@@ -201,3 +205,45 @@ def test_full_size_jobs_sampled():
         assert ob[y, x].view(np.uint32) == O.blur5_pixel(img, wt_ref, int(y), int(x)).view(np.uint32)
     for i in [0, 131071] + list(rng.integers(131072, size=6)):
         assert np.array_equal(on[i].view(np.uint32), O.nbody_acc_body(pos, 1e-6, int(i), True).view(np.uint32))
+
+
+def test_concurrent_jobs_overlap_on_the_device():
+    """Continuous batching: jobs admitted together share the GPU, so the
+    [first tile, last tile] intervals of at least two of them overlap, and
+    more than one job was in flight at once."""
+    jobs = [escape_job(1024, 512, 3000 + 100 * i) for i in range(4)] + [blur_job(4096, 1024), nbody_job(20000)]
+    with ce.Server(512 * MiB, keep_outputs=True, session_timeout_s=SESSION_S) as srv:
+        tickets = [j.submit(srv) for j in jobs]
+        for j, t in zip(jobs, tickets):
+            j.check(srv, t)
+        spans = [srv.job_ticks(t) for t in tickets]
+        srv.drain(60.0)
+        r = srv.stats()
+    assert all(0 < a <= b for a, b in spans), spans
+    overlaps = sum(1 for i in range(len(spans)) for k in range(i + 1, len(spans))
+                   if spans[i][0] < spans[k][1] and spans[k][0] < spans[i][1])
+    assert overlaps >= 1, spans
+    assert r.max_inflight_seen >= 2
+
+
+def test_sessions_roll_over_when_full():
+    """A session takes max_jobs jobs; the server thread ends it and starts the
+    next for the rest, so ten jobs through sessions of four all complete."""
+    jobs = [escape_job(200 + 11 * i, 90, 300 + 50 * i) for i in range(10)]
+    with ce.Server(64 * MiB, keep_outputs=True, max_jobs=4, session_timeout_s=SESSION_S) as srv:
+        tickets = [j.submit(srv) for j in jobs]
+        for j, t in zip(jobs, tickets):
+            j.check(srv, t)
+        srv.drain(60.0)
+        assert srv.stats().completed == 10
+
+
+def test_idle_session_ends_and_the_next_job_starts_another():
+    a, b = escape_job(300, 100, 400), blur_job(1001, 37)
+    with ce.Server(32 * MiB, keep_outputs=True, session_timeout_s=0.2) as srv:
+        a.check(srv, a.submit(srv))
+        time.sleep(0.6)  # the kernel has left: no job for 0.2 s
+        b.check(srv, b.submit(srv))
+        a.check(srv, a.submit(srv))
+        srv.drain(30.0)
+        assert srv.stats().completed == 3
