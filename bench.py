@@ -3,22 +3,30 @@
 
 Default workload: 5x5 Gaussian blur of an 8192 x 8192 FP32 image (pixels
 uniform in [0, 1), seed 0xB1), HGuided scheduler, GPU + every host core. A
-step is one ce_engine_run over the whole image. Inputs are resident before
-the timed region: in HBM for the GPU and mirrored in host memory for the host
-workers; the output ends in HBM (the host's rows copied by the SDMA engines
-during the run).
+step is one ce_engine_run over the whole image. `value` is K steps timed back
+to back with inputs resident in HBM (and mirrored in host memory for the host
+workers) and the output ending in HBM (the host's rows copied in by the SDMA
+engines during the run).
 
-The JSON line reports work-items/s of the co-executed run (value: K runs timed
-back to back, nothing else in the loop), the plain single-GPU launch of the
-same kernel, the engine's overhead over it, the balance and efficiency of
-section 7.3 (from per-run medians, measured alike for the plain launch, the
-engine alone and the co-execution), the roofline of the persistent GPU kernel
-(timed with HIP events on its stream, in a second, untimed pass of K runs) and
-the oracle timed on the host.
+Beside it, on the same line:
+- the measurement protocol of section 7.3: three sets of runs with the first
+  of each set discarded (20 runs per set; 100 for the overhead), median, p5
+  and p95 of the plain single-GPU launch, the engine with the GPU alone, the
+  host alone and the co-execution; speedup, S_max, efficiency and balance of
+  section 7.3 from those medians; the work each device took;
+- the host-resident run (section 7.3's T includes the transfers): the same
+  image in pinned host buffers, which the GPU streams over PCIe, against the
+  best plain single-GPU launch with its transfers;
+- the roofline of the persistent GPU kernel (HIP events on its stream) and a
+  streaming-copy reference, and the oracle timed on one host core.
 
-Other workloads: --workload escape (1024^2, max_iter 256, Static with 8
-packages, GPU + 1 host thread) and --workload nbody (65,536 bodies, Dynamic
-256-body packages, GPU + every host core).
+Other workloads (--workload): escape (1024^2, max_iter 256, Static split into
+8 packages over the GPU and ONE host thread, as configured; HGuided over every
+core beside it), nbody (65,536 bodies, Dynamic 256-body packages, GPU + every
+core; the hardware 1/sqrt beside the strict one), escape-roofline (8192^2,
+max_iter 4096, GPU), runtime, nbody-step, binomial, batch, serve, copy.
+--sched-grid adds the paper's scheduler grid (Static, Static rev, Dynamic 50
+and 150 packages, HGuided) and --sweep the overhead against problem size.
 """
 from __future__ import annotations
 
@@ -34,9 +42,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "work-items/s co-executed (GPU+host) vs plain 1-GPU launch; balance efficiency"
 HBM_PEAK_GBS = 8000.0
-# Non-packed FP32 VALU issue rate: 256 CUs x 64 lanes per clock x 2.4 GHz.
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-
+# Published dense FP32 vector peak (it counts packed FP32, two lanes' FMAs per
+# instruction); this build issues no packed FP32, so each lane retires at most
+# one FMA (two flops) per clock: half of it.
+FP32_PEAK_TFLOPS = 157.3
+FP32_NONPACKED_TFLOPS = 78.6
+# VALU issue rate without packed FP32: 256 CUs x 64 lanes per clock x 2.4 GHz.
+VALU_ISSUE_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Section 7.3's protocol: sets of runs, the first run of each set discarded.
+SETS, RUNS, OVERHEAD_RUNS = 3, 20, 100
 
 DEVICE_SOURCES = ("paper_1805_02755_amd/csrc/kernels.hip", "paper_1805_02755_amd/csrc/device_tiles.hpp",
                   "paper_1805_02755_amd/csrc/device_atomics.hpp", "paper_1805_02755_amd/csrc/device_payloads.hpp",
@@ -44,9 +58,9 @@ DEVICE_SOURCES = ("paper_1805_02755_amd/csrc/kernels.hip", "paper_1805_02755_amd
                   "paper_1805_02755_amd/csrc/rt_tile.hpp")
 
 
-def measured_traffic(name):
-    """HBM bytes per dispatch from the committed counter summary, or None if
-    the device sources changed since the counters were taken."""
+def measured(name):
+    """A committed counter summary (profiles/NAME, JSON) if the device sources
+    it was taken from are unchanged, else None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
@@ -59,7 +73,7 @@ def measured_traffic(name):
             h.update(f.read())
     if h.hexdigest() != rec.get("device_source_sha256"):
         return None
-    return rec.get("traffic_bytes_per_dispatch")
+    return rec
 
 
 def log(msg):
@@ -71,16 +85,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["blur", "escape", "runtime", "nbody", "nbody-step", "binomial", "batch", "serve",
-                                           "copy"],
-                    default="blur")
+    ap.add_argument("--workload", default="blur",
+                    choices=["blur", "escape", "escape-roofline", "runtime", "nbody", "nbody-step", "binomial",
+                             "batch", "serve", "copy"])
     ap.add_argument("--serve-jobs", type=int, default=2000)
-    ap.add_argument("--trace-out", default=None, help="write the last co-executed run's package trace (JSON) here")
-    ap.add_argument("--mode", choices=["device", "host"], default="device",
-                    help="device: inputs and output resident in HBM; host: host buffers, PCIe inside the step")
+    ap.add_argument("--trace-out", default=None,
+                    help="write the last co-executed run's package trace here (Chrome trace JSON)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-host-resident", action="store_true", help="skip the host-resident leg")
+    ap.add_argument("--sched-grid", action="store_true", help="add the scheduler grid of section 7.3")
+    ap.add_argument("--sweep", action="store_true", help="add the overhead against problem size")
     ap.add_argument("--merge", choices=["dma", "gpu"], default="dma",
-                    help="how the host's share reaches the device output: the GPU's copy engines (dma) or "
+                    help="how the host's share reaches a device output: the GPU's copy engines (dma) or "
                          "gather workgroups inside its kernel (gpu)")
     ap.add_argument("--host-threads", type=int, default=0)
     return ap.parse_args()
@@ -99,6 +115,7 @@ class HipEvents:
         self.L.hipEventSynchronize.argtypes = [C.c_void_p]
         self.L.hipEventDestroy.argtypes = [C.c_void_p]
         self.L.hipEventRecord.argtypes = [C.c_void_p, C.c_void_p]
+        self.L.hipHostGetDevicePointer.argtypes = [C.POINTER(C.c_void_p), C.c_void_p, C.c_uint]
 
     def create(self):
         ev = self.C.c_void_p()
@@ -119,6 +136,13 @@ class HipEvents:
     def destroy(self, ev):
         self.L.hipEventDestroy(ev)
 
+    def device_view(self, host_ptr):
+        """The GPU's address of pinned host memory."""
+        d = self.C.c_void_p()
+        if self.L.hipHostGetDevicePointer(self.C.byref(d), self.C.c_void_p(host_ptr), 0) != 0:
+            raise RuntimeError("hipHostGetDevicePointer failed")
+        return d.value
+
 
 def timed_runs(fn, warmup, steps, sync):
     for _ in range(warmup):
@@ -136,11 +160,465 @@ def med(v):
     return statistics.median(v) if v else float("nan")
 
 
+def pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, dtype=float), q)) if v else float("nan")
+
+
+def dist_ms(v):
+    """Median, p5 and p95 (ms) of run times in seconds."""
+    return {"median_ms": med(v) * 1e3, "p5_ms": pct(v, 5) * 1e3, "p95_ms": pct(v, 95) * 1e3, "runs": len(v)}
+
+
+def protocol(fn, sets=SETS, per_set=RUNS, after=None):
+    """Section 7.3: `sets` sets of per_set + 1 runs, the first of each set
+    discarded. Returns the kept run times (s) and after()'s value per kept run."""
+    times, extra = [], []
+    for _ in range(sets):
+        for i in range(per_set + 1):
+            t0 = time.perf_counter()
+            fn()
+            dt = time.perf_counter() - t0
+            if i == 0:
+                continue
+            times.append(dt)
+            if after is not None:
+                extra.append(after())
+    return times, extra
+
+
+def runs_for(t_one, budget_s, lo=2, hi=RUNS):
+    """Runs per set that fit three sets into budget_s, given one run's time."""
+    return int(max(lo, min(hi, budget_s / max(1e-9, 3.0 * t_one))))
+
+
+def chrome_trace(trace, stats, path, title):
+    """The package trace as Chrome trace events (chrome://tracing, Perfetto):
+    one row per device, one slice per package, times in microseconds from
+    the start of the run."""
+    names = {0: "GPU", 1: "host"}
+    ev = [{"ph": "M", "name": "process_name", "pid": 0, "args": {"name": title}}]
+    for d in sorted({r[0] for r in trace}):
+        ev.append({"ph": "M", "name": "thread_name", "pid": 0, "tid": int(d),
+                   "args": {"name": names.get(stats.device_kind[d] - 1, str(d)) if hasattr(stats, "device_kind")
+                            else str(d)}})
+    for d, b, e, tc, te in trace:
+        ev.append({"ph": "X", "pid": 0, "tid": int(d), "name": f"granules [{b}, {e})", "ts": tc * 1e6,
+                   "dur": max(0.0, (te - tc) * 1e6), "args": {"g0": int(b), "g1": int(e)}})
+    for d in range(stats.n_devices):
+        ev.append({"ph": "i", "pid": 0, "tid": d, "name": "device end", "ts": stats.t_device[d] * 1e6, "s": "t"})
+    with open(path, "w") as f:
+        json.dump({"traceEvents": ev, "displayTimeUnit": "ms"}, f)
+
+
+def work_distribution(trace, stats, items_of):
+    """Granules, items and package sizes per device of one run (section 8.4)."""
+    out = {}
+    for d in range(stats.n_devices):
+        sizes = sorted(int(e - b) for dd, b, e, _, _ in trace if dd == d)
+        kind = "gpu" if stats.device_kind[d] == 1 else "host"
+        out[kind] = {"packages": len(sizes), "granules": int(sum(sizes)),
+                     "items": int(sum(items_of(b, e) for dd, b, e, _, _ in trace if dd == d)),
+                     "package_granules": {"min": sizes[0] if sizes else 0, "median": med(sizes) if sizes else 0,
+                                          "max": sizes[-1] if sizes else 0, "first": [int(e - b) for dd, b, e, _, _
+                                                                                      in sorted(trace, key=lambda r: r[3])
+                                                                                      if dd == d][:8]}}
+    return out
+
+
+# ------------------------------------------------------------------ workloads
+class Spec:
+    """One workload: its kernel, inputs (host arrays and HBM copies), output,
+    index space, configured scheduler and host threads."""
+
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+
+def make_spec(wl, args, ce, synth, np, torch, dev, strict=1):
+    if wl == "blur":
+        w = h = 8192
+        log("generating 8192x8192 image")
+        img = synth.blur_image(w, h)
+        wt = ce.ce_gauss5_weights(1.0)
+        return Spec(kid=ce.CE_KERNEL_BLUR5, params=ce.ce_blur5_params(w, h), gws=[w, h], lws=None,
+                    ins=[img, wt], out_shape=(h, w), out_dtype=np.float32, n_items=w * h, G=h,
+                    items_of=lambda b, e: (e - b) * w, host_threads=args.host_threads,
+                    sched=dict(kind=ce.CE_SCHED_HGUIDED, k=2), dtype="f32", bound="hbm",
+                    config={"workload": "blur5x5 8192x8192 fp32, sigma 1, clamp-to-edge", "scheduler": "hguided",
+                            "devices": "gpu+host", "output_merge": args.merge})
+    if wl in ("escape", "runtime"):
+        p = synth.escape_small()
+        s = Spec(kid=ce.CE_KERNEL_ESCAPE, params=ce.ce_escape_params(p.w, p.h, *p.as_f32(), p.max_iter),
+                 gws=[p.w, p.h], lws=None, ins=[], out_shape=(p.h, p.w), out_dtype=np.uint32, n_items=p.w * p.h,
+                 G=p.h, items_of=lambda b, e: (e - b) * p.w, host_threads=1,
+                 sched=dict(kind=ce.CE_SCHED_STATIC, n_packages=8), dtype="u32", bound="alu", esc=p,
+                 config={"workload": "escape-time 1024x1024 over [-2,1]x[-1.5,1.5], max_iter 256",
+                         "scheduler": "static, 8 packages", "devices": "gpu+1 host thread"})
+        if wl == "runtime":
+            s.rt_lws = 64
+            s.G = s.n_items // 64
+            s.items_of = lambda b, e: (e - b) * 64
+            s.host_threads = args.host_threads
+            s.sched = dict(kind=ce.CE_SCHED_HGUIDED, k=2)
+            s.config = {"workload": s.config["workload"] + ", supplied as HIP source at run time (hipRTC) with a C "
+                                    "host version", "granule": "64 pixels", "scheduler": "hguided",
+                        "devices": "gpu+host"}
+        return s
+    n = 65536
+    bodies = synth.nbody_bodies(n)
+    return Spec(kid=ce.CE_KERNEL_NBODY_ACC, params=ce.ce_nbody_params(n, 1e-6, strict), gws=[n], lws=[256],
+                ins=[bodies], out_shape=(n, 4), out_dtype=np.float32, n_items=n, G=n // 256,
+                items_of=lambda b, e: (min(e * 256, n) - b * 256), host_threads=args.host_threads,
+                sched=dict(kind=ce.CE_SCHED_DYNAMIC, package_granules=1), dtype="f32", bound="alu", exact=bool(strict),
+                config={"workload": "nbody acceleration 65536 bodies fp32, eps2 1e-6, "
+                                    + ("strict (Lomont) rsqrt" if strict else "hardware rsqrt"),
+                        "scheduler": "dynamic 256-body packages", "devices": "gpu+host"})
+
+
+def coexec_leg(ce, sp, mode, args, stream, hev, torch, np, sched=None, host_threads=None, K=None, events=True):
+    """Measures one workload in one residency mode: plain launch, engine
+    with the GPU alone, the host alone, the co-execution (section 7.3
+    protocol), K timed co-executed steps and the GPU kernel's events.
+    mode 'device': inputs and output in HBM (host mirrors of the inputs);
+    mode 'host': inputs and output in pinned host buffers only."""
+    dev = torch.device("cuda:0")
+    sync = torch.cuda.synchronize
+    K = K or args.steps
+    W = args.warmup
+    sched = dict(sched or sp.sched)
+    host_threads = sp.host_threads if host_threads is None else host_threads
+    nbytes_out = int(np.prod(sp.out_shape)) * np.dtype(sp.out_dtype).itemsize
+    keep = []
+    if mode == "device":
+        ins_dev = [torch.from_numpy(a).to(dev) for a in sp.ins]
+        out_dev = torch.empty(nbytes_out, dtype=torch.uint8, device=dev)
+        ins_host, out_host = sp.ins, None
+        bare_ins, bare_out = ins_dev, out_dev
+    else:
+        def pinned(a):
+            t = torch.empty(a.nbytes, dtype=torch.uint8, pin_memory=True)
+            keep.append(t)
+            v = t.numpy().view(a.dtype).reshape(a.shape)
+            v[...] = a
+            return v
+        ins_host = [pinned(a) for a in sp.ins]
+        out_host = pinned(np.zeros(nbytes_out, np.uint8))
+        ins_dev, out_dev = None, None
+        # plain launches over the same pinned buffers (read and written over PCIe)
+        bare_ins = [hev.device_view(a.ctypes.data) for a in ins_host]
+        bare_out = hev.device_view(out_host.ctypes.data)
+        # and the plain launch with explicit copies through HBM
+        ins_stage = [torch.empty(a.nbytes, dtype=torch.uint8, device=dev) for a in sp.ins]
+        out_stage = torch.empty(nbytes_out, dtype=torch.uint8, device=dev)
+        ins_pin_t = [torch.from_numpy(a.view(np.uint8).reshape(-1)) for a in ins_host]
+        out_pin_t = torch.from_numpy(out_host.view(np.uint8).reshape(-1))
+    sync()
+    res = {"mode": mode}
+
+    # ------------------------------------------------ plain single-GPU launch
+    log(f"[{mode}] plain launch")
+    rt = getattr(sp, "rt_lws", None)
+    eng = ce.Engine()
+    eng.stream(stream.cuda_stream)
+    eng.output_merge(ce.CE_MERGE_DMA if args.merge == "dma" else ce.CE_MERGE_GPU_GATHER)
+    if rt:
+        from paper_1805_02755_amd import rt_examples
+        p = sp.esc
+        eng.work_items([sp.n_items], [rt])
+        t_c = time.perf_counter()
+        eng.program_source(rt_examples.source("escape.hiprtc"), "escape_item",
+                           host=rt_examples.host_fn("escape_host"), n_in=0, n_out=1, out_item_bytes=4,
+                           scalars=rt_examples.escape_scalars(p.w, *p.as_f32(), p.max_iter))
+        res["compile_s"] = time.perf_counter() - t_c
+    else:
+        eng.work_items(sp.gws, sp.lws)
+        eng.program_kernel(sp.kid, sp.params)
+
+    def bare_once(sync_=True):
+        if rt:
+            eng.bare_run_source(sp.n_items, rt, [], [bare_out], stream=stream.cuda_stream, sync=sync_)
+        else:
+            ce.ce_bare_run(sp.kid, sp.params, bare_ins, bare_out, stream=stream.cuda_stream, sync=sync_)
+
+    for _ in range(W):
+        bare_once()
+    t_bare, _ = protocol(bare_once, per_set=OVERHEAD_RUNS)
+    res["t_bare"] = dist_ms(t_bare)
+    T_bare = med(t_bare)
+    if mode == "host":
+        def bare_copies():
+            with torch.cuda.stream(stream):
+                for s_, d_ in zip(ins_stage, ins_pin_t):
+                    s_.copy_(d_, non_blocking=True)
+                ce.ce_bare_run(sp.kid, sp.params, ins_stage, out_stage, stream=stream.cuda_stream, sync=False)
+                out_pin_t.copy_(out_stage, non_blocking=True)
+            stream.synchronize()
+        for _ in range(W):
+            bare_copies()
+        t_bc, _ = protocol(bare_copies)
+        res["t_bare_zero_copy"] = res["t_bare"]
+        res["t_bare_with_copies"] = dist_ms(t_bc)
+        # the faster plain launch is the baseline
+        if med(t_bc) < T_bare:
+            T_bare = med(t_bc)
+            res["t_bare"] = res["t_bare_with_copies"]
+        res["bare_form"] = "copies" if T_bare == med(t_bc) else "zero-copy"
+    k_bare = []
+    if events and mode == "device":
+        ev = [(hev.create(), hev.create()) for _ in range(K)]
+        for a, b in ev:
+            hev.record(a, stream.cuda_stream)
+            bare_once(False)
+            hev.record(b, stream.cuda_stream)
+        sync()
+        k_bare = [hev.elapsed_ms(a, b) for a, b in ev]
+        for a, b in ev:
+            hev.destroy(a)
+            hev.destroy(b)
+        res["t_bare_kernel_ms"] = med(k_bare)
+
+    # ------------------------------------------------ bind the engine
+    for slot in range(len(sp.ins)):
+        if mode == "device":
+            eng.program_in(slot, host=ins_host[slot], dev=ins_dev[slot], nbytes=ins_host[slot].nbytes)
+        else:
+            eng.program_in(slot, host=ins_host[slot])
+    if mode == "device":
+        eng.program_out(0, dev=out_dev, nbytes=nbytes_out)
+    else:
+        eng.program_out(0, host=out_host)
+
+    # ------------------------------------------------ engine, GPU alone
+    log(f"[{mode}] engine GPU only")
+    eng.use(ce.CE_DEV_GPU, 0, 0)
+    eng.scheduler(ce.CE_SCHED_STATIC)
+    for _ in range(W):
+        eng.run()
+    t_gpu, _ = protocol(eng.run, per_set=OVERHEAD_RUNS)
+    res["t_engine_gpu"] = dist_ms(t_gpu)
+    T_gpu = med(t_gpu)
+    res["gpu_workgroups"] = eng.stats().gpu_workgroups
+    if events:
+        ev = [(hev.create(), hev.create()) for _ in range(K)]
+        kg = []
+        for a, b in ev:
+            eng.kernel_events(a, b)
+            eng.run()
+            kg.append(hev.elapsed_ms(a, b))
+        eng.kernel_events(None, None)
+        for a, b in ev:
+            hev.destroy(a)
+            hev.destroy(b)
+        res["t_engine_gpu_kernel_ms"] = med(kg)
+    if mode == "device":
+        ref = out_dev.clone()
+
+    # ------------------------------------------------ engine, host alone
+    log(f"[{mode}] engine host only")
+    eng.use(ce.CE_DEV_HOST, 0, host_threads)
+    eng.scheduler(ce.CE_SCHED_STATIC)
+    t0 = time.perf_counter()
+    eng.run()
+    t_one = time.perf_counter() - t0
+    t_host, _ = protocol(eng.run, per_set=runs_for(t_one, 6.0))
+    res["t_engine_host"] = dist_ms(t_host)
+    T_host = med(t_host)
+    res["host_threads"] = eng.stats().host_threads
+
+    # ------------------------------------------------ co-execution
+    if sched["kind"] == ce.CE_SCHED_HGUIDED and "power" not in sched:
+        # computing powers (G-3): integers proportional to the standalone
+        # throughputs, the faster device at 4096
+        t_min = min(T_gpu, T_host)
+        sched["power"] = [max(1, int(round(4096 * t_min / T_gpu))), max(1, int(round(4096 * t_min / T_host)))]
+    elif sched["kind"] == ce.CE_SCHED_STATIC and "props" not in sched:
+        # the GPU's share from the standalone times (G-9: default props from calibration)
+        sched["props"] = [max(0.0, min(1.0, T_host / (T_gpu + T_host)))]
+    log(f"[{mode}] co-execution {sched}")
+    eng.use(ce.CE_DEV_GPU | ce.CE_DEV_HOST, 0, host_threads)
+    eng.scheduler(**sched)
+    for _ in range(W):
+        eng.run()
+    t0 = time.perf_counter()
+    eng.run()
+    t_one = time.perf_counter() - t0
+    t_co, st_co = protocol(eng.run, per_set=runs_for(t_one, 6.0), after=eng.stats)
+    res["t_coexec"] = dist_ms(t_co)
+    T_co = med(t_co)
+    # K steps back to back, nothing else in the loop: the line's value
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        eng.run()
+    sync()
+    T_total = time.perf_counter() - t0
+    kern = []
+    if events:
+        ev = [(hev.create(), hev.create()) for _ in range(K)]
+        for a, b in ev:
+            eng.kernel_events(a, b)
+            eng.run()
+            kern.append(hev.elapsed_ms(a, b))
+        eng.kernel_events(None, None)
+        for a, b in ev:
+            hev.destroy(a)
+            hev.destroy(b)
+        res["t_coexec_kernel_ms"] = med(kern)
+    st = eng.stats()
+    trace = eng.trace()
+    if mode == "device":
+        if getattr(sp, "exact", True):
+            assert torch.equal(out_dev, ref), "co-executed output differs from the GPU alone"
+        res["_out"] = out_dev
+    else:
+        res["_out"] = out_host
+    if args.trace_out and mode == "device":
+        chrome_trace(trace, st, args.trace_out, sp.config["workload"])
+    s_real = T_bare / T_co
+    s_max = min(T_bare, T_host) * (1.0 / T_bare + 1.0 / T_host)
+    gpu_items = [s_.items[0] for s_ in st_co]
+    res.update({
+        "value": sp.n_items * K / T_total, "ms_per_step": T_total / K * 1e3, "steps": K,
+        "plain_gpu_items_per_s": sp.n_items / T_bare,
+        "s_real": s_real, "s_max": s_max, "efficiency": s_real / s_max,
+        "balance": med([s_.balance for s_ in st_co]),
+        "balance_p5_p95": [pct([s_.balance for s_ in st_co], 5), pct([s_.balance for s_ in st_co], 95)],
+        "overhead_pct_gpu_only": (T_gpu - T_bare) / T_bare * 100.0,
+        "gpu_share": med(gpu_items) / sp.n_items,
+        "packages": {"gpu": med([s_.packages[0] for s_ in st_co]), "host": med([s_.packages[1] for s_ in st_co])},
+        "t_device_ms": [med([s_.t_device[0] for s_ in st_co]) * 1e3, med([s_.t_device[1] for s_ in st_co]) * 1e3],
+        "scheduler": {k: (list(v) if isinstance(v, (list, tuple)) else v) for k, v in sched.items()},
+        "work_distribution": work_distribution(trace, st, sp.items_of),
+        "_kern_ms": kern, "_gpu_items": gpu_items,
+    })
+    eng.close()
+    del keep
+    return res
+
+
+def public(d):
+    return {k: v for k, v in d.items() if not k.startswith("_")}
+
+
+def escape_iterations(out_u32, np):
+    """Iterations of an escape-time output and the lane efficiency of the
+    row-strip tiles: each wave runs 64 consecutive pixels of a row for as many
+    iterations as the longest of them, so efficiency = sum of counts /
+    sum over 64-pixel strips of 64 x their largest count."""
+    c = out_u32.astype(np.int64)
+    h, w = c.shape
+    pad = (-w) % 64
+    cp = np.pad(c, ((0, 0), (0, pad)))
+    strips = cp.reshape(h, -1, 64)
+    used = int(c.sum())
+    issued = int((strips.max(axis=2) * 64).sum())
+    # padding lanes of a ragged strip are idle lanes of that wave
+    return used, used / issued if issued else 1.0
+
+
+def alu_roofline(flops, lane_ops, kern_ms, kernel, counters_name=None):
+    achieved = flops / (kern_ms * 1e-3) / 1e12
+    r = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+         "frac": achieved / FP32_PEAK_TFLOPS, "frac_of_nonpacked_peak": achieved / FP32_NONPACKED_TFLOPS,
+         "traffic": None, "kernel": kernel, "kernel_ms": kern_ms,
+         "issue": {"lane_ops": lane_ops, "achieved_T_lane_ops_per_s": lane_ops / (kern_ms * 1e-3) / 1e12,
+                   "peak_T_lane_ops_per_s": VALU_ISSUE_TOPS,
+                   "frac": lane_ops / (kern_ms * 1e-3) / 1e12 / VALU_ISSUE_TOPS}}
+    if counters_name:
+        rec = measured(counters_name)
+        r["counters"] = {k: rec[k] for k in ("valu_busy", "valu_utilization", "valu_insts_per_dispatch",
+                                             "command") if k in rec} if rec else None
+    return r
+
+
+def cpu_baseline_for(wl, sp, np, budget=10.0):
+    from oracle import oracle as O
+    log("oracle CPU baseline")
+    t0 = time.perf_counter()
+    done = 0
+    if wl == "blur":
+        wt_o = O.gauss5_weights(1.0)
+        passes = 0
+        while passes < 4 and time.perf_counter() - t0 < budget:
+            O.blur5(sp.ins[0], wt_o)
+            passes += 1
+        done = passes * sp.n_items
+        sample = f"{passes} full passes over the 8192x8192 image"
+    elif wl in ("escape", "runtime"):
+        p = sp.esc
+        passes = 0
+        while passes < 40 and time.perf_counter() - t0 < budget:
+            O.escape(p.w, p.h, *[float(v) for v in p.as_f32()], p.max_iter)
+            passes += 1
+        done = passes * sp.n_items
+        sample = f"{passes} full passes over the 1024x1024 grid"
+    else:
+        i = 0
+        while time.perf_counter() - t0 < budget:
+            O.nbody_acc_body(sp.ins[0], 1e-6, i, True)
+            i += 1
+        done = i
+        sample = f"{i} bodies (each against all 65536)"
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "work-items/s", "cores": 1, "kind": "oracle", "sample": sample,
+            "seconds": dt}
+
+
+def copy_reference(ce, torch, stream, hev, nbytes, K):
+    """The streaming-copy kernel over nbytes: achievable bandwidth (GB/s)."""
+    dev = torch.device("cuda:0")
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).uniform_()
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        ce.ce_stream_copy(b, a, nbytes, stream=stream.cuda_stream)
+    ms = []
+    s0, s1 = hev.create(), hev.create()
+    for _ in range(K):
+        hev.record(s0, stream.cuda_stream)
+        ce.ce_stream_copy(b, a, nbytes, stream=stream.cuda_stream, sync=False)
+        hev.record(s1, stream.cuda_stream)
+        ms.append(hev.elapsed_ms(s0, s1))
+    hev.destroy(s0)
+    hev.destroy(s1)
+    assert torch.equal(a, b)
+    return {"kernel": "k_stream_copy (one non-temporal 16-byte load and store per thread)", "bytes": 2 * nbytes,
+            "ms_median": med(ms), "GBps": 2 * nbytes / (med(ms) * 1e-3) / 1e9}
+
+
+def roofline_for(wl, sp, leg, ce, torch, np, stream, hev, K):
+    kern = med(leg["_kern_ms"])
+    share = med(leg["_gpu_items"]) / sp.n_items
+    if wl == "blur":
+        bytes_launch = 8.0 * med(leg["_gpu_items"])
+        achieved = bytes_launch / (kern * 1e-3) / 1e9
+        rec = measured("blur5_8192_hbm_traffic.json")
+        ref = copy_reference(ce, torch, stream, hev, 256 << 20, K)
+        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": rec.get("traffic_bytes_per_dispatch") if rec else None,
+                "traffic_unit": "bytes per launch", "kernel": "k_persistent<Blur5Tile>", "kernel_ms": kern,
+                "algorithmic_bytes_per_item": 8.0, "algorithmic_bytes_per_launch": bytes_launch,
+                "copy_reference": ref, "frac_of_copy": achieved / ref["GBps"]}
+    if wl in ("escape", "runtime"):
+        out = leg["_out"].cpu().numpy().view(np.uint32).reshape(sp.out_shape)
+        iters, eff = escape_iterations(out, np)
+        r = alu_roofline(8.0 * iters * share, 8.0 * iters * share, kern,
+                         "k_persistent<RtTile> (hipRTC)" if wl == "runtime" else "k_persistent<EscapeTile>",
+                         None if wl == "runtime" else "escape_1024_valu.json")
+        r.update({"iterations": iters, "flops_per_iteration": 8, "lane_efficiency": eff})
+        return r
+    n = sp.n_items
+    r = alu_roofline(20.0 * n * n * share, 24.0 * n * n * share, kern, "k_persistent<NbodyTile<true>>",
+                     "nbody_65536_valu.json")
+    r.update({"flops_per_interaction": 20, "lane_ops_per_interaction": 24})
+    return r
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
-                          "n_gpus": args.gpus}), flush=True)
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
     import numpy as np
     import torch
@@ -151,319 +629,205 @@ def main():
     ce.lib()  # fail loudly if the HIP library is missing
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream()
-    sync = torch.cuda.synchronize
-    host_cores = os.cpu_count() or 1
-    if args.workload == "batch":
+    wl = args.workload
+    if wl == "batch":
         return bench_batch(args, ce, synth, torch, np, stream)
-    if args.workload == "serve":
+    if wl == "serve":
         return bench_serve(args, ce, synth, torch, np, stream)
-    if args.workload == "copy":
-        return bench_copy(args, torch, stream)
-    if args.workload == "nbody-step":
+    if wl == "copy":
+        return bench_copy(args, ce, torch, stream)
+    if wl == "nbody-step":
         return bench_nbody_step(args, ce, synth, torch, np, stream)
-    if args.workload == "binomial":
+    if wl == "binomial":
         return bench_binomial(args, ce, synth, torch, np, stream)
+    if wl == "escape-roofline":
+        return bench_escape_roofline(args, ce, synth, torch, np, stream)
 
+    hev = HipEvents()
+    sp = make_spec(wl, args, ce, synth, np, torch, dev)
+    leg = coexec_leg(ce, sp, "device", args, stream, hev, torch, np)
+    roof = roofline_for(wl, sp, leg, ce, torch, np, stream, hev, args.steps)
+    res = {
+        "metric": METRIC, "value": leg["value"], "unit": "work-items/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": leg["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": sp.dtype,
+        "data": "synthetic (seeded SplitMix64 inputs, paper_1805_02755_amd/synth.py)",
+        "config": dict(sp.config, residency="device"),
+        "roofline": roof,
+        "cpu_baseline": None,
+        "protocol": {"sets": SETS, "runs_per_set": RUNS, "overhead_runs_per_set": OVERHEAD_RUNS,
+                     "first_run_of_each_set_discarded": True, "host_cores": os.cpu_count()},
+        "coexec": public(leg),
+    }
+    if wl == "blur" and not args.no_host_resident:
+        hl = coexec_leg(ce, sp, "host", args, stream, hev, torch, np, K=max(3, args.steps // 4))
+        res["host_resident"] = dict(public(hl), note="inputs and output in pinned host buffers; the GPU streams its "
+                                    "rows over PCIe; T includes every transfer (section 7.3)")
+    if wl == "escape":
+        hg = coexec_leg(ce, sp, "device", args, stream, hev, torch, np, sched=dict(kind=ce.CE_SCHED_HGUIDED, k=2),
+                        host_threads=args.host_threads)
+        res["hguided_all_cores"] = public(hg)
+    if wl == "nbody":
+        fsp = make_spec("nbody", args, ce, synth, np, torch, dev, strict=0)
+        fl = coexec_leg(ce, fsp, "device", args, stream, hev, torch, np, K=max(3, args.steps // 2))
+        out_fast = fl["_out"].cpu().numpy().view(np.float32).reshape(-1, 4)
+        fr = roofline_for("nbody", fsp, fl, ce, torch, np, stream, hev, args.steps)
+        fr["kernel"] = "k_persistent<NbodyTile<false>>"
+        res["fast_rsqrt"] = dict(public(fl), roofline=fr, note="v_rsq_f32 on the GPU, 1/sqrtf on the host")
+        del out_fast
+    if args.sched_grid:
+        res["sched_grid"] = sched_grid(ce, sp, args, stream, hev, torch, np)
+    if args.sweep:
+        res["overhead_sweep"] = overhead_sweep(wl, ce, synth, args, stream, torch, np)
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline_for(wl, sp, np)
+    print(json.dumps(res), flush=True)
+
+
+def sched_grid(ce, sp, args, stream, hev, torch, np):
+    """Section 7.3's scheduler configurations on this workload: Static
+    (proportions from the standalone times), Static rev, Dynamic with 50 and
+    150 packages, HGuided."""
+    grid = {"static": dict(kind=ce.CE_SCHED_STATIC, order=ce.CE_ORDER_HOST_FIRST),
+            "static_rev": dict(kind=ce.CE_SCHED_STATIC, order=ce.CE_ORDER_GPU_FIRST),
+            "dynamic_50": dict(kind=ce.CE_SCHED_DYNAMIC, n_packages=50),
+            "dynamic_150": dict(kind=ce.CE_SCHED_DYNAMIC, n_packages=150),
+            "hguided": dict(kind=ce.CE_SCHED_HGUIDED, k=2)}
+    out = {}
+    for name, s in grid.items():
+        log(f"scheduler grid: {name}")
+        leg = coexec_leg(ce, sp, "device", args, stream, hev, torch, np, sched=s, host_threads=args.host_threads,
+                         K=3, events=False)
+        out[name] = {k: leg[k] for k in ("s_real", "s_max", "efficiency", "balance", "balance_p5_p95",
+                                         "t_coexec", "t_bare", "t_engine_host", "gpu_share", "packages",
+                                         "scheduler")}
+    return out
+
+
+def overhead_sweep(wl, ce, synth, args, stream, torch, np):
+    """Engine with the GPU alone against the plain launch, across problem
+    sizes (section 8.2): 3 sets of 100 runs each."""
+    import numpy as _np
+    dev = torch.device("cuda:0")
+    rows = []
+    if wl == "blur":
+        cases = [(s, s) for s in (1024, 2048, 4096, 8192, 16384)]
+    elif wl in ("escape", "runtime"):
+        cases = [(s, s) for s in (256, 512, 1024, 2048, 4096)]
+    else:
+        cases = [(n,) for n in (4096, 8192, 16384, 32768, 65536)]
+    for c in cases:
+        if wl == "blur":
+            w, h = c
+            img = synth.blur_image(w, h, seed=w)
+            ins = [torch.from_numpy(img).to(dev), torch.from_numpy(ce.ce_gauss5_weights(1.0)).to(dev)]
+            out = torch.empty_like(ins[0])
+            kid, prm, gws, lws, items = ce.CE_KERNEL_BLUR5, ce.ce_blur5_params(w, h), [w, h], None, w * h
+        elif wl in ("escape", "runtime"):
+            w, h = c
+            p = synth.escape_region(w, h, -2.0, 1.0, -1.5, 1.5, 256)
+            ins, out = [], torch.empty((h, w), dtype=torch.int32, device=dev)
+            kid, prm, gws, lws, items = (ce.CE_KERNEL_ESCAPE, ce.ce_escape_params(w, h, *p.as_f32(), 256), [w, h],
+                                         None, w * h)
+        else:
+            n = c[0]
+            ins = [torch.from_numpy(synth.nbody_bodies(n)).to(dev)]
+            out = torch.empty_like(ins[0])
+            kid, prm, gws, lws, items = ce.CE_KERNEL_NBODY_ACC, ce.ce_nbody_params(n, 1e-6, 1), [n], [256], n
+        torch.cuda.synchronize()
+        bare = lambda: ce.ce_bare_run(kid, prm, ins, out, stream=stream.cuda_stream, sync=True)
+        for _ in range(3):
+            bare()
+        t0 = time.perf_counter()
+        bare()
+        per = runs_for(time.perf_counter() - t0, 4.0, lo=5, hi=OVERHEAD_RUNS)
+        tb, _ = protocol(bare, per_set=per)
+        eng = ce.Engine()
+        eng.stream(stream.cuda_stream)
+        eng.use(ce.CE_DEV_GPU, 0, 0)
+        eng.work_items(gws, lws)
+        eng.program_kernel(kid, prm)
+        for s_, d_ in enumerate(ins):
+            eng.program_in(s_, dev=d_, nbytes=d_.numel() * d_.element_size())
+        eng.program_out(0, dev=out, nbytes=out.numel() * out.element_size())
+        eng.scheduler(ce.CE_SCHED_STATIC)
+        for _ in range(3):
+            eng.run()
+        tg, _ = protocol(eng.run, per_set=per)
+        eng.close()
+        rows.append({"size": list(c), "items": items, "t_bare": dist_ms(tb), "t_engine_gpu": dist_ms(tg),
+                     "overhead_pct": (med(tg) - med(tb)) / med(tb) * 100.0})
+        del ins, out
+    del _np
+    return rows
+
+
+def bench_escape_roofline(args, ce, synth, torch, np, stream):
+    """The escape-time kernel where it is compute-bound: 8192 x 8192 over
+    [-2,1]x[-1.5,1.5], max_iter 4096, on the GPU (plain launch and the engine
+    with the GPU alone): FP32 flops and lane efficiency from the iteration
+    counts."""
+    hev = HipEvents()
+    K, W = args.steps, args.warmup
+    w = h = 8192
+    p = synth.escape_region(w, h, -2.0, 1.0, -1.5, 1.5, 4096)
+    prm = ce.ce_escape_params(w, h, *p.as_f32(), p.max_iter)
+    dev = torch.device("cuda:0")
+    out = torch.empty((h, w), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    ev = [(hev.create(), hev.create()) for _ in range(K)]
+
+    def timed(fn):
+        for _ in range(W):
+            fn(True)
+        ms = []
+        for a, b in ev:
+            hev.record(a, stream.cuda_stream)
+            fn(False)
+            hev.record(b, stream.cuda_stream)
+            ms.append(hev.elapsed_ms(a, b))
+        return ms
+
+    log("escape roofline: plain launch")
+    kb = timed(lambda s: ce.ce_bare_run(ce.CE_KERNEL_ESCAPE, prm, [], out, stream=stream.cuda_stream, sync=s))
+    ref = out.clone()
     eng = ce.Engine()
     eng.stream(stream.cuda_stream)
-    eng.output_merge(ce.CE_MERGE_DMA if args.merge == "dma" else ce.CE_MERGE_GPU_GATHER)
-
-    # ---------------------------------------------------------------- payload
-    wl = args.workload
-    if wl == "blur":
-        w = h = 8192
-        log("generating 8192x8192 image")
-        img = synth.blur_image(w, h)
-        wt = ce.ce_gauss5_weights(1.0)
-        img_d = torch.from_numpy(img).to(dev)
-        wt_d = torch.from_numpy(wt).to(dev)
-        out_d = torch.empty_like(img_d)
-        out_h = np.empty_like(img) if args.mode == "host" else None
-        params = ce.ce_blur5_params(w, h)
-        kid = ce.CE_KERNEL_BLUR5
-        gws, lws = [w, h], None
-        ins_host, ins_dev = [img, wt], [img_d, wt_d]
-        n_items = w * h
-        G = h
-        bytes_per_item = 8.0  # 4 B read + 4 B written; halo re-reads are not algorithmic
-        host_threads = args.host_threads
-        coexec = dict(kind=ce.CE_SCHED_HGUIDED, k=2)
-        config = {"workload": "blur5x5 8192x8192 fp32, sigma 1, clamp-to-edge", "scheduler": "hguided",
-                  "devices": "gpu+host", "residency": args.mode, "output_merge": args.merge}
-        bound = "hbm"
-    elif wl in ("escape", "runtime"):
-        p = synth.escape_small()
-        params = ce.ce_escape_params(p.w, p.h, *p.as_f32(), p.max_iter)
-        kid = ce.CE_KERNEL_ESCAPE
-        gws, lws = [p.w, p.h], None
-        out_d = torch.empty((p.h, p.w), dtype=torch.int32, device=dev)
-        out_h = np.empty((p.h, p.w), np.uint32) if args.mode == "host" else None
-        ins_host, ins_dev = [], []
-        n_items = p.w * p.h
-        G = p.h
-        host_threads = args.host_threads
-        coexec = dict(kind=ce.CE_SCHED_HGUIDED, k=2)
-        config = {"workload": "escape-time 1024x1024 over [-2,1]x[-1.5,1.5], max_iter 256", "scheduler": "hguided",
-                  "devices": "gpu+host", "residency": args.mode}
-        bound = "alu"
-        if wl == "runtime":
-            if args.mode != "device":
-                raise SystemExit("--workload runtime runs with device residency only")
-            from paper_1805_02755_amd import rt_examples
-            config["workload"] += ", supplied as HIP source at run time (hipRTC) with a C host version"
-            # The plain C host version needs about 0.16 ms per 1024-pixel row,
-            # more than the GPU's whole run: 64-pixel granules and HGuided let
-            # the host take only what it finishes in time.
-            rt_lws = 64
-            G = n_items // rt_lws
-            config["granule"] = "64 pixels"
-    else:
-        n = 65536
-        bodies = synth.nbody_bodies(n)
-        b_d = torch.from_numpy(bodies).to(dev)
-        out_d = torch.empty_like(b_d)
-        out_h = np.empty_like(bodies) if args.mode == "host" else None
-        params = ce.ce_nbody_params(n, 1e-6, 1)
-        kid = ce.CE_KERNEL_NBODY_ACC
-        gws, lws = [n], [256]
-        ins_host, ins_dev = [bodies], [b_d]
-        n_items = n
-        G = n // 256
-        host_threads = args.host_threads
-        coexec = dict(kind=ce.CE_SCHED_DYNAMIC, package_granules=1)
-        config = {"workload": "nbody acceleration 65536 bodies fp32, eps2 1e-6, strict rsqrt",
-                  "scheduler": "dynamic 256-body packages", "devices": "gpu+host", "residency": args.mode}
-        bound = "alu"
-    sync()
-
-    eng.work_items(gws, lws)
-    if wl == "runtime":
-        eng.work_items([n_items], [rt_lws])
-        t_c = time.perf_counter()
-        eng.program_source(rt_examples.source("escape.hiprtc"), "escape_item",
-                           host=rt_examples.host_fn("escape_host"), n_in=0, n_out=1, out_item_bytes=4,
-                           scalars=rt_examples.escape_scalars(p.w, *p.as_f32(), p.max_iter))
-        config["compile_s"] = time.perf_counter() - t_c
-    else:
-        eng.program_kernel(kid, params)
-    for slot in range(len(ins_host)):
-        if args.mode == "host":
-            eng.program_in(slot, host=ins_host[slot])
-        else:
-            eng.program_in(slot, host=ins_host[slot], dev=ins_dev[slot], nbytes=ins_host[slot].nbytes)
-    if args.mode == "host":
-        eng.program_out(0, host=out_h)
-    else:
-        eng.program_out(0, dev=out_d, nbytes=out_d.numel() * out_d.element_size())
-
-    K, W = args.steps, args.warmup
-
-    # ---------------------------------------------- plain single-GPU launch
-    log("bare launch")
-    def bare_launch(do_sync):
-        if wl == "runtime":
-            eng.bare_run_source(n_items, rt_lws, [], [out_d], stream=stream.cuda_stream, sync=do_sync)
-        else:
-            ce.ce_bare_run(kid, params, ins_dev if args.mode != "host" else ins_dev_b, out_d,
-                           stream=stream.cuda_stream, sync=do_sync)
-
-    def bare():
-        if args.mode == "host":
-            for i, a in enumerate(ins_host):
-                ins_dev_b[i].copy_(torch.from_numpy(a), non_blocking=False)
-            ce.ce_bare_run(kid, params, ins_dev_b, out_d, stream=stream.cuda_stream, sync=True)
-            out_h_b[...] = out_d.cpu().numpy().view(out_h_b.dtype).reshape(out_h_b.shape)
-        else:
-            bare_launch(True)
-    if args.mode == "host":
-        ins_dev_b = [torch.empty(a.shape, dtype=torch.from_numpy(a).dtype, device=dev) for a in ins_host]
-        out_h_b = np.empty_like(out_h)
-    t_bare = timed_runs(bare, W, K, sync)
-    hev = HipEvents()
-    ev_s = [hev.create() for _ in range(K)]
-    ev_e = [hev.create() for _ in range(K)]
-    # kernel time of the plain launch, from events on its stream
-    for i in range(K):
-        hev.record(ev_s[i], stream.cuda_stream)
-        bare_launch(False)
-        hev.record(ev_e[i], stream.cuda_stream)
-    sync()
-    k_bare_ms = med([hev.elapsed_ms(ev_s[i], ev_e[i]) for i in range(K)])
-
-    # ------------------------------------------------- engine, GPU alone
-    log("engine GPU only")
     eng.use(ce.CE_DEV_GPU, 0, 0)
+    eng.work_items([w, h])
+    eng.program_kernel(ce.CE_KERNEL_ESCAPE, prm)
+    eng.program_out(0, dev=out, nbytes=out.numel() * 4)
     eng.scheduler(ce.CE_SCHED_STATIC)
-    t_gpu = timed_runs(eng.run, W, K, sync)
-    k_gpu = []
-    for i in range(K):
-        eng.kernel_events(ev_s[i], ev_e[i])
-        eng.run()
-        k_gpu.append(hev.elapsed_ms(ev_s[i], ev_e[i]))
-    eng.kernel_events(None, None)
-    k_gpu_ms = med(k_gpu)
-
-    # ------------------------------------------------- engine, host alone
-    log("engine host only")
-    eng.use(ce.CE_DEV_HOST, 0, host_threads)
-    eng.scheduler(ce.CE_SCHED_STATIC)
-    t_host = timed_runs(eng.run, 1, min(K, 5), sync)
-    host_threads_used = eng.stats().host_threads
-
-    # ------------------------------------------------- co-execution
-    T_bare, T_gpu, T_host = med(t_bare), med(t_gpu), med(t_host)
-    if coexec["kind"] == ce.CE_SCHED_HGUIDED:
-        # computing powers from the standalone throughputs, the slower device at 1
-        if T_host >= T_gpu:
-            coexec["power"] = [max(1, min(1 << 20, int(round(T_host / T_gpu)))), 1]
-        else:
-            coexec["power"] = [1, max(1, min(1 << 20, int(round(T_gpu / T_host))))]
-    elif coexec["kind"] == ce.CE_SCHED_STATIC:
-        coexec["props"] = [max(0.0, 1.0 - T_gpu / (T_gpu + T_host))]
-    eng.use(ce.CE_DEV_GPU | ce.CE_DEV_HOST, 0, host_threads)
-    eng.scheduler(**coexec)
-    log(f"co-execution {coexec}")
+    log("escape roofline: engine, GPU alone")
     for _ in range(W):
         eng.run()
-    # the timed steps: nothing but the runs (and a clock read) in the loop
-    per_run = []
-    sync()
-    t0 = time.perf_counter()
-    for i in range(K):
-        a = time.perf_counter()
+    kg = []
+    for a, b in ev:
+        eng.kernel_events(a, b)
         eng.run()
-        per_run.append(time.perf_counter() - a)
-    sync()
-    T_total = time.perf_counter() - t0
-    # the same runs again, untimed, for kernel events and per-run statistics
-    stats = []
-    for i in range(K):
-        eng.kernel_events(ev_s[i], ev_e[i])
-        eng.run()
-        stats.append(eng.stats())
+        kg.append(hev.elapsed_ms(a, b))
     eng.kernel_events(None, None)
-    trace = eng.trace()
-    if args.trace_out:
-        with open(args.trace_out, "w") as f:
-            json.dump({"stats": {"t_device": list(stats[-1].t_device[:2]), "t_run": stats[-1].t_run,
-                                 "t_gather": stats[-1].t_gather, "gathered_bytes": stats[-1].gathered_bytes},
-                       "packages": [list(r) for r in trace]}, f)
-
-    kern_ms = [hev.elapsed_ms(ev_s[i], ev_e[i]) for i in range(K)]
-    for ev in ev_s + ev_e:
-        hev.destroy(ev)
-    gpu_items = [s.items[0] for s in stats]
-    host_items = [s.items[1] for s in stats]
-    T_co = T_total / K
-    value = n_items * K / T_total
-    # speedup and efficiency compare per-run medians, measured the same way
-    # for the plain launch, the engine alone and the co-execution
-    s_real = T_bare / med(per_run)
-    s_max = min(T_bare, T_host) * (1.0 / T_bare + 1.0 / T_host)
-    balance = med([s.balance for s in stats])
-
-    # --------------------------------------------------------- roofline
-    if wl == "blur":
-        achieved = sum(bytes_per_item * g for g in gpu_items) / (sum(kern_ms) * 1e-3) / 1e9
-        traffic = measured_traffic("blur5_8192_hbm_traffic.json") if args.mode == "device" else None
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes per launch",
-                "kernel": "k_persistent<Blur5Tile>", "kernel_ms": med(kern_ms),
-                "algorithmic_bytes_per_item": bytes_per_item}
-    elif wl in ("escape", "runtime"):
-        cnt = out_d.cpu().numpy().view(np.uint32).astype(np.int64)
-        iters = int(cnt.sum())
-        ops = 8.0 * iters * (sum(gpu_items) / (K * n_items))
-        achieved = ops / (med(kern_ms) * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (FP32 VALU lane-ops)",
-                "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                "kernel": "k_persistent<RtTile> (hipRTC)" if wl == "runtime" else "k_persistent<EscapeTile>",
-                "kernel_ms": med(kern_ms), "iterations": iters}
-    else:
-        n = n_items
-        ops = 24.0 * n * n * (sum(gpu_items) / (K * n_items))
-        achieved = ops / (med(kern_ms) * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (FP32 VALU lane-ops)",
-                "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "k_persistent<NbodyTile<true>>",
-                "kernel_ms": med(kern_ms), "ops_per_interaction": 24}
-
-    # ------------------------------------------------------ CPU baseline
-    cpu_base = None
-    if not args.no_cpu_baseline:
-        log("oracle CPU baseline")
-        from oracle import oracle as O
-        t0 = time.perf_counter()
-        done_items = 0
-        if wl == "blur":
-            wt_o = O.gauss5_weights(1.0)
-            passes = 0
-            while passes < 4 and (time.perf_counter() - t0 < 10.0):
-                O.blur5(img, wt_o)
-                passes += 1
-                done_items += n_items
-            sample = f"{passes} full passes over the 8192x8192 image"
-        elif wl in ("escape", "runtime"):
-            passes = 0
-            while passes < 40 and (time.perf_counter() - t0 < 10.0):
-                O.escape(p.w, p.h, *[float(v) for v in p.as_f32()], p.max_iter)
-                passes += 1
-                done_items += n_items
-            sample = f"{passes} full passes over the 1024x1024 grid"
-        else:
-            i = 0
-            while time.perf_counter() - t0 < 10.0:
-                O.nbody_acc_body(bodies, 1e-6, i, True)
-                i += 1
-            done_items = i
-            sample = f"{i} bodies (each against all 65536)"
-        dt = time.perf_counter() - t0
-        cpu_base = {"value": done_items / dt, "unit": "work-items/s", "cores": 1, "kind": "oracle",
-                    "sample": sample, "seconds": dt}
-
-    res = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "work-items/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": W,
-        "ms_per_step": T_co * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32" if wl in ("escape", "runtime") else "f32",
-        "data": "synthetic (seeded SplitMix64 inputs, paper_1805_02755_amd/synth.py)",
-        "config": config,
-        "roofline": roof,
-        "cpu_baseline": cpu_base,
-        "coexec": {
-            "plain_gpu_items_per_s": n_items / T_bare,
-            "vs_plain_gpu": s_real,
-            "balance": balance,
-            "s_real": s_real,
-            "s_max": s_max,
-            "efficiency": s_real / s_max,
-            "overhead_pct_gpu_only": (T_gpu - T_bare) / T_bare * 100.0,
-            "t_bare_ms": T_bare * 1e3,
-            "t_bare_kernel_ms": k_bare_ms,
-            "t_engine_gpu_ms": T_gpu * 1e3,
-            "t_engine_gpu_kernel_ms": k_gpu_ms,
-            "t_engine_host_ms": T_host * 1e3,
-            "t_coexec_ms_median": med(per_run) * 1e3,
-            "host_threads": host_threads_used,
-            "host_cores": host_cores,
-            "gpu_share": sum(gpu_items) / (K * n_items),
-            "packages_gpu": med([s.packages[0] for s in stats]),
-            "packages_host": med([s.packages[1] for s in stats]),
-            "scheduler": {k: (list(v) if isinstance(v, (list, tuple)) else v) for k, v in coexec.items()},
-            "t_device_ms": [med([s.t_device[0] for s in stats]) * 1e3, med([s.t_device[1] for s in stats]) * 1e3],
-            "t_gather_ms": med([s.t_gather for s in stats]) * 1e3,
-            "gathered_MiB": med([s.gathered_bytes for s in stats]) / 2**20,
-            "trace_packages": len(trace),
-        },
-    }
-    print(json.dumps(res), flush=True)
+    assert torch.equal(out, ref)
     eng.close()
+    iters, eff = escape_iterations(out.cpu().numpy().view(np.uint32), np)
+    r = alu_roofline(8.0 * iters, 8.0 * iters, med(kg), "k_persistent<EscapeTile>", "escape_8192_4096_valu.json")
+    r.update({"iterations": iters, "lane_efficiency": eff, "flops_per_iteration": 8})
+    rb = alu_roofline(8.0 * iters, 8.0 * iters, med(kb), "k_bare<EscapeTile>")
+    res = {"metric": METRIC, "value": w * h / (med(kg) * 1e-3), "unit": "work-items/s", "n_gpus": 1, "steps": K,
+           "warmup": W, "ms_per_step": med(kg), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u32", "data": "synthetic (no random input)",
+           "config": {"workload": "escape-time 8192x8192 over [-2,1]x[-1.5,1.5], max_iter 4096", "devices": "gpu",
+                      "scheduler": "static"},
+           "roofline": r, "plain_launch": {"kernel_ms": med(kb), "roofline": rb}, "cpu_baseline": None}
+    print(json.dumps(res), flush=True)
+
+
+def bench_copy(args, ce, torch, stream):
+    """The streaming-copy reference over 256 MiB and 1 GiB, timed with HIP
+    events."""
+    hev = HipEvents()
+    res = [copy_reference(ce, torch, stream, hev, nb, args.steps) for nb in (256 << 20, 1 << 30)]
+    print(json.dumps({"workload": "streaming copy", "copies": res}), flush=True)
 
 
 def bench_nbody_step(args, ce, synth, torch, np, stream):
@@ -550,8 +914,6 @@ def bench_nbody_step(args, ce, synth, torch, np, stream):
     s_real = T_bare / med(per_run)
     s_max = min(T_bare, T_host) * (1.0 / T_bare + 1.0 / T_host)
     gpu_share = sum(s_.items[0] for s_ in stats) / (K * n)
-    ops = 24.0 * n * n * gpu_share
-    achieved = ops / (med(kern_ms) * 1e-3) / 1e12
     cpu_base = None
     if not args.no_cpu_baseline:
         log("oracle CPU baseline")
@@ -571,10 +933,9 @@ def bench_nbody_step(args, ce, synth, torch, np, stream):
         "config": {"workload": "nbody integration step, 65536 bodies fp32, eps2 1e-6, dt 1e-3, strict rsqrt, "
                                "resident ping-pong buffers", "scheduler": "dynamic 256-body packages",
                    "devices": "gpu+host", "residency": "device"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "TOP/s (FP32 VALU lane-ops)", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                     "kernel": "k_persistent<NbodyStepTile<true>>", "kernel_ms": med(kern_ms),
-                     "ops_per_interaction": 24},
+        "roofline": dict(alu_roofline(20.0 * n * n * gpu_share, 24.0 * n * n * gpu_share, med(kern_ms),
+                                      "k_persistent<NbodyStepTile<true>>", "nbody_step_65536_valu.json"),
+                         flops_per_interaction=20, lane_ops_per_interaction=24),
         "cpu_baseline": cpu_base,
         "coexec": {
             "plain_gpu_items_per_s": n / T_bare, "vs_plain_gpu": s_real, "s_real": s_real, "s_max": s_max,
@@ -677,9 +1038,11 @@ def bench_binomial(args, ce, synth, torch, np, stream):
     s_real = T_bare / med(per_run)
     s_max = min(T_bare, T_host) * (1.0 / T_bare + 1.0 / T_host)
     gpu_share = sum(s_.items[0] for s_ in stats) / (K * items)
-    # per call: 255 leaves (mul, sub, max) and steps*(steps+1)/2 node updates (two muls and an add)
-    ops = 4.0 * n_groups * (3.0 * (steps + 1) + 3.0 * steps * (steps + 1) / 2) * gpu_share
-    achieved = ops / (med(kern_ms) * 1e-3) / 1e12
+    # per call: steps+1 leaves (a mul, a sub and a max: two flops, three lane-ops) and
+    # steps*(steps+1)/2 node updates (two muls and an add)
+    nodes = steps * (steps + 1) / 2
+    flops = 4.0 * n_groups * (2.0 * (steps + 1) + 3.0 * nodes) * gpu_share
+    lane_ops = 4.0 * n_groups * (3.0 * (steps + 1) + 3.0 * nodes) * gpu_share
     cpu_base = None
     if not args.no_cpu_baseline:
         log("oracle CPU baseline")
@@ -701,9 +1064,8 @@ def bench_binomial(args, ce, synth, torch, np, stream):
         "config": {"workload": "binomial options: 16777216 European calls, 254 steps, 4194304 work-groups of 255, "
                                "out pattern 1:255", "scheduler": "hguided", "devices": "gpu+host",
                    "residency": "device", "options_per_s": 4 * n_groups * K / T_total},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "TOP/s (FP32 VALU lane-ops)", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                     "kernel": "k_persistent<BinomialTile>", "kernel_ms": med(kern_ms)},
+        "roofline": alu_roofline(flops, lane_ops, med(kern_ms), "k_persistent<BinomialTile>",
+                                 "binomial_4194304x254_valu.json"),
         "cpu_baseline": cpu_base,
         "coexec": {
             "plain_gpu_items_per_s": items / T_bare, "vs_plain_gpu": s_real, "s_real": s_real, "s_max": s_max,
@@ -757,7 +1119,6 @@ def bench_batch(args, ce, synth, torch, np, stream):
         kern.append(st.t_gpu_ms)
     T = time.perf_counter() - t0
     iters = int(sum(int(o.to(torch.int64).sum().item()) for o in outs))
-    achieved = 8.0 * iters / (med(kern) * 1e-3) / 1e12
     cpu_base = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -780,9 +1141,8 @@ def bench_batch(args, ce, synth, torch, np, stream):
         "config": {"workload": "batched escape-time: 256 jobs, side log-uniform [64,2048], max_iter U[64,4096]",
                    "form": "one persistent hipGraph launch", "tile_rows": chosen[0], "tile_cols": chosen[1],
                    "package_tiles": chosen[2]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "TOP/s (FP32 VALU lane-ops)", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                     "kernel": "k_batch_escape", "kernel_ms": med(kern), "iterations": iters},
+        "roofline": dict(alu_roofline(8.0 * iters, 8.0 * iters, med(kern), "k_batch_escape",
+                                      "batch_escape_256jobs_valu.json"), iterations=iters),
         "cpu_baseline": cpu_base,
         "batch": {"separate_launch_ms": med(t_sep) * 1e3, "separate_gpu_ms": med(g_sep),
                   "graph_launch_ms": med(per_run) * 1e3, "graph_gpu_ms": med(kern),
@@ -792,38 +1152,20 @@ def bench_batch(args, ce, synth, torch, np, stream):
     b.close()
 
 
-def bench_copy(args, torch, stream):
-    """Reference for the HBM counters and the achievable stream rate: a plain
-    device copy of 256 MiB (the blur image's size), timed with HIP events."""
-    dev = torch.device("cuda:0")
-    a = torch.rand(8192 * 8192, device=dev)
-    b = torch.empty_like(a)
-    hev = HipEvents()
-    s0, s1 = hev.create(), hev.create()
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        ms = []
-        for _ in range(args.steps):
-            hev.record(s0, stream.cuda_stream)
-            b.copy_(a)
-            hev.record(s1, stream.cuda_stream)
-            ms.append(hev.elapsed_ms(s0, s1))
-    nbytes = 2 * a.numel() * 4
-    print(json.dumps({"workload": "device copy 256 MiB fp32", "bytes_per_copy": nbytes, "steps": args.steps,
-                      "ms_median": med(ms), "GBps": nbytes / (med(ms) * 1e-3) / 1e9}), flush=True)
-
-
 def bench_serve(args, ce, synth, torch, np, stream):
-    """Serving: a Poisson trace of escape, blur and n-body jobs (200 jobs/s,
-    sizes log-uniform; seed 0x5E2E) replayed in real time against the
-    persistent serving kernel, and against one plain launch per job in
-    arrival order. Inputs come from resident pools in HBM (a job of side s
-    reads the first s*s pixels of one 16384^2 image; a job of n bodies the
-    first n of 131,072); outputs are allocated per job from the HBM budget."""
+    """Serving (continuous batching) under calibrated load. A trace of escape,
+    blur and n-body jobs (sizes log-uniform, kinds in thirds; seed 0x5E2E) is
+    first run saturated, all jobs submitted at once, which measures the
+    serving kernel's capacity (jobs/s) and one plain launch per job back to
+    back. The trace's Poisson arrivals are then replayed at rate
+    rho x capacity for rho in 0.5, 0.7, 0.9, against the serving kernel and
+    against one plain launch per job in arrival order; latency is arrival to
+    completion. Inputs come from resident pools in HBM (a job of side s reads
+    the first s*s pixels of one 16384^2 image; a job of n bodies the first n
+    of 131,072); outputs are allocated per job from the HBM budget."""
     import threading
-    trace = synth.serve_trace(args.serve_jobs)
+    n_jobs = args.serve_jobs
+    trace = synth.serve_trace(n_jobs)
     dev = torch.device("cuda:0")
     img = torch.from_numpy(synth.blur_image(16384, 16384, seed=0x5E21)).to(dev)
     bodies = torch.from_numpy(synth.nbody_bodies(131072, seed=0x5E22)).to(dev)
@@ -841,52 +1183,82 @@ def bench_serve(args, ce, synth, torch, np, stream):
     specs = [job_args(j) for j in trace]
     n_items = sum(s[3] for s in specs)
     out_bytes = max(s[3] for s in specs) * 16
+    budget = max(4 << 30, 8 * out_bytes)
     torch.cuda.synchronize()
-
-    # --- one plain launch per job, in arrival order (FIFO, no overlap)
-    log(f"serving trace: {len(trace)} jobs over {trace[-1].arrival_s:.1f} s; plain launches first")
     scratch = torch.empty(out_bytes, dtype=torch.uint8, device=dev)
-    lat_plain = []
-    t0 = time.perf_counter()
-    for j, (kid, prm, ins, _) in zip(trace, specs):
-        now = time.perf_counter() - t0
-        if now < j.arrival_s:
-            time.sleep(j.arrival_s - now)
-        ce.ce_bare_run(kid, prm, ins, scratch, stream=stream.cuda_stream, sync=True)
-        lat_plain.append(time.perf_counter() - t0 - j.arrival_s)
-    wall_plain = time.perf_counter() - t0
-    del scratch
-    torch.cuda.synchronize()
 
-    # --- the serving kernel
-    log("serving kernel")
-    srv = ce.Server(max(4 << 30, 8 * out_bytes), keep_outputs=False, session_timeout_s=600.0)
-    warm = [srv.submit(*specs[i][:2], *specs[i][2]) for i in range(min(8, len(specs)))]
-    for t in warm:
+    def plain(kid, prm, ins):
+        ce.ce_bare_run(kid, prm, ins, scratch, stream=stream.cuda_stream, sync=True)
+
+    # warm both paths
+    for kid, prm, ins, _ in specs[:8]:
+        plain(kid, prm, ins)
+    srv = ce.Server(budget, keep_outputs=False, session_timeout_s=30.0)
+    for t in [srv.submit(*s_[:2], *s_[2]) for s_ in specs[:8]]:
         srv.wait(t, 120.0)
     srv.drain(120.0)
     srv.close()
-    srv = ce.Server(max(4 << 30, 8 * out_bytes), keep_outputs=False, session_timeout_s=600.0)
-    tickets = []
 
-    def client():
-        c0 = time.perf_counter()
-        for j, (kid, prm, ins, _) in zip(trace, specs):
-            now = time.perf_counter() - c0
-            if now < j.arrival_s:
-                time.sleep(j.arrival_s - now)
-            tickets.append(srv.submit(kid, prm, *ins))
-
-    th = threading.Thread(target=client)
-    th.start()
-    th.join()
+    # ------------------------------------------------ saturated: capacity
+    log(f"serving: {n_jobs} jobs saturated (capacity)")
+    t0 = time.perf_counter()
+    for kid, prm, ins, _ in specs:
+        plain(kid, prm, ins)
+    plain_wall = time.perf_counter() - t0
+    srv = ce.Server(budget, keep_outputs=False, session_timeout_s=30.0)
+    tickets = [srv.submit(*s_[:2], *s_[2]) for s_ in specs]
     for t in tickets:
         srv.wait(t, 600.0)
     srv.drain(120.0)
-    r = srv.stats()
+    sat = srv.stats()
     srv.close()
-    lat_plain.sort()
-    pct = lambda v, q: float(np.percentile(np.asarray(v), q))
+    capacity = sat.completed / sat.wall_s
+    plain_capacity = n_jobs / plain_wall
+
+    def replay_server(arrivals):
+        srv = ce.Server(budget, keep_outputs=False, session_timeout_s=30.0)
+        tks = []
+
+        def client():
+            c0 = time.perf_counter()
+            for a, s_ in zip(arrivals, specs):
+                now = time.perf_counter() - c0
+                if now < a:
+                    time.sleep(a - now)
+                tks.append(srv.submit(*s_[:2], *s_[2]))
+        th = threading.Thread(target=client)
+        th.start()
+        th.join()
+        for t in tks:
+            srv.wait(t, 600.0)
+        srv.drain(120.0)
+        r = srv.stats()
+        srv.close()
+        return {"p50_ms": r.p50_s * 1e3, "p99_ms": r.p99_s * 1e3, "mean_ms": r.mean_s * 1e3, "max_ms": r.max_s * 1e3,
+                "items_per_s": r.items_per_s, "jobs_per_s": r.jobs_per_s, "wall_s": r.wall_s,
+                "max_inflight": int(r.max_inflight_seen), "peak_hbm_bytes": int(r.peak_hbm)}
+
+    def replay_plain(arrivals):
+        lat = []
+        t0 = time.perf_counter()
+        for a, (kid, prm, ins, _) in zip(arrivals, specs):
+            now = time.perf_counter() - t0
+            if now < a:
+                time.sleep(a - now)
+            plain(kid, prm, ins)
+            lat.append(time.perf_counter() - t0 - a)
+        wall = time.perf_counter() - t0
+        return {"p50_ms": pct(lat, 50) * 1e3, "p99_ms": pct(lat, 99) * 1e3, "mean_ms": sum(lat) / len(lat) * 1e3,
+                "max_ms": max(lat) * 1e3, "items_per_s": n_items / wall, "jobs_per_s": n_jobs / wall, "wall_s": wall}
+
+    loads = {}
+    base_rate = n_jobs / trace[-1].arrival_s  # the trace's own rate
+    for rho in (0.5, 0.7, 0.9):
+        lam = rho * capacity
+        arrivals = [j.arrival_s * base_rate / lam for j in trace]
+        log(f"serving: rho {rho}, {lam:.0f} jobs/s over {arrivals[-1]:.1f} s")
+        loads[str(rho)] = {"rate_jobs_per_s": lam, "serving": replay_server(arrivals), "plain": replay_plain(arrivals)}
+    del scratch
     cpu_base = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -905,19 +1277,19 @@ def bench_serve(args, ce, synth, torch, np, stream):
         cpu_base = {"value": done / dt, "unit": "work-items/s", "cores": 1, "kind": "oracle",
                     "sample": f"the first {nj} escape-time jobs of the trace", "seconds": dt}
     res = {
-        "metric": METRIC, "value": r.items_per_s, "unit": "work-items/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": r.wall_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "mixed (u32 escape, f32 blur and n-body)", "data": "synthetic (seeded SplitMix64 trace, paper_1805_02755_amd/synth.py)",
-        "config": {"workload": f"serving trace: {len(trace)} Poisson arrivals at 200/s, escape side [256,4096], "
-                               "blur side [1024,16384], n-body [4096,131072]", "form": "persistent serving kernel"},
+        "metric": METRIC, "value": sat.items_per_s, "unit": "work-items/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": sat.wall_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "mixed (u32 escape, f32 blur and n-body)",
+        "data": "synthetic (seeded SplitMix64 trace, paper_1805_02755_amd/synth.py)",
+        "config": {"workload": f"serving trace: {n_jobs} jobs, escape side [256,4096] max_iter U[64,4096], "
+                               "blur side [1024,16384], n-body [4096,131072] (hardware rsqrt)",
+                   "form": "persistent serving kernel, continuous batching"},
         "roofline": None,
         "cpu_baseline": cpu_base,
-        "serve": {"jobs": int(r.completed), "items": int(r.items), "p50_ms": r.p50_s * 1e3, "p99_ms": r.p99_s * 1e3,
-                  "mean_ms": r.mean_s * 1e3, "max_ms": r.max_s * 1e3, "wall_s": r.wall_s,
-                  "jobs_per_s": r.jobs_per_s, "peak_hbm_bytes": int(r.peak_hbm),
-                  "max_inflight": int(r.max_inflight_seen),
-                  "plain_p50_ms": pct(lat_plain, 50) * 1e3, "plain_p99_ms": pct(lat_plain, 99) * 1e3,
-                  "plain_wall_s": wall_plain, "plain_items_per_s": n_items / wall_plain},
+        "serve": {"capacity_jobs_per_s": capacity, "saturated_items_per_s": sat.items_per_s,
+                  "saturated_p50_ms": sat.p50_s * 1e3, "saturated_p99_ms": sat.p99_s * 1e3,
+                  "plain_capacity_jobs_per_s": plain_capacity, "plain_items_per_s": n_items / plain_wall,
+                  "loads": loads},
     }
     print(json.dumps(res), flush=True)
 
