@@ -1121,7 +1121,12 @@ struct ce_engine {
       // dynamically too.
       const bool long_tiles = kernel_id == CE_KERNEL_BINOMIAL;
       if (long_tiles) gs.chunk = 1;
-      gs.stride = (kernel_id == CE_KERNEL_RUNTIME || gather || long_tiles) ? 0u : 1u;
+      // Escape-time tiles of one column block over many rounds differ by
+      // orders of magnitude (8192^2: workgroup w would run every 128th row of
+      // one 512-pixel column, 64 tiles, the busiest columns all on the same
+      // workgroups): beyond one round they are dealt by atomic tickets.
+      const bool uneven = kernel_id == CE_KERNEL_ESCAPE && gpu_tiles(kargs, 0, G) > (uint64_t)(grid - gather_wgs);
+      gs.stride = (kernel_id == CE_KERNEL_RUNTIME || gather || long_tiles || uneven) ? 0u : 1u;
       // the gatherers wait for the host's packages, whose length depends on the problem
       gs.gather_wait_ticks = std::max<uint64_t>(1, (uint64_t)((double)wallclock_hz * gather_wait_s));
       if (gather) {
