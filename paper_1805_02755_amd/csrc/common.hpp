@@ -169,7 +169,14 @@ struct SchedArgs {
   uint32_t gather_wgs;  // workgroups 0 .. gather_wgs-1 only gather
   uint32_t ring_cap;    // entries in the ring
   uint64_t gather_wait_ticks;  // longest wait for the host's next finished tile
+  // Fast exit (pre_only with one ticket sequence per workgroup and no
+  // gatherers): no workgroup counts itself out; each stores the tick at
+  // which it left into wg_end[blockIdx.x] (host-coherent) and the host takes
+  // the GPU's end from them after the kernel. Null: the regular exit.
+  uint64_t* wg_end;
 };
+
+constexpr uint32_t kFastExitMaxWgs = 16384;  // entries of the host's wg_end array
 
 // HGuided package size (section 5.3 equation), integer only. Callers keep
 // G_r < 2^40 and P <= 2^20 so the products fit in 64 bits.

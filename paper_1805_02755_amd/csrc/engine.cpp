@@ -279,6 +279,10 @@ struct ce_engine {
   uint32_t gpu_grid_last = 0;
   uint32_t grid_override = 0;  // persistent workgroups chosen by the caller (0: the engine chooses)
   bool pcie_stream = false;    // this run's kernel reads or writes pinned host memory directly
+  uint64_t* wg_end = nullptr;      // host-coherent, kFastExitMaxWgs entries (fast exit)
+  uint64_t* wg_end_dev = nullptr;
+  bool fast_exit = false;          // this run's kernel uses the fast exit
+  uint64_t fast_g0 = 0, fast_g1 = 0;  // its one package
   double dispenser_wait_s = (double)kDispenserWaitSeconds;  // bounds on the kernel's waits
   double gather_wait_s = (double)kGatherWaitSeconds;
 
@@ -1164,8 +1168,17 @@ struct ce_engine {
     __atomic_thread_fence(__ATOMIC_SEQ_CST);
 
     t0_ns = now_ns();
+    fast_exit = false;
     if (use_gpu()) {
       gpu_preclaim(gs);
+      // The GPU's whole share was claimed before the launch and every
+      // workgroup walks its own tickets: no claim, no shared counter, so no
+      // workgroup needs to count out (the overhead of a single-device run
+      // is then that of a plain launch plus the dispenser's first ticket).
+      fast_exit = gs.pre_only && gs.stride && !gather && grid <= kFastExitMaxWgs;
+      gs.wg_end = fast_exit ? wg_end_dev : nullptr;
+      fast_g0 = gs.pre_g0;
+      fast_g1 = gs.pre_g1;
       if (ev_start && (he = hipEventRecord(ev_start, stream)) != hipSuccess) return hip_fail(he, "run: event");
       if ((he = launch_persistent(kargs, gs, grid, stream)) != hipSuccess) return hip_fail(he, "run: kernel launch");
       if (ev_stop && (he = hipEventRecord(ev_stop, stream)) != hipSuccess) return hip_fail(he, "run: event");
@@ -1191,7 +1204,9 @@ struct ce_engine {
       const uint32_t want = (uint32_t)pool.size();
       while (pool_done.load(std::memory_order_acquire) < want) cpu_relax();
     }
-    if (use_gpu()) {
+    if (use_gpu() && fast_exit) {
+      if ((he = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(he, "run: kernel");
+    } else if (use_gpu()) {
       // the last workgroup out writes the done word; poll it, then sync
       const int64_t deadline = now_ns() + kGpuDeadlineNs;
       bool waited = false;
@@ -1322,10 +1337,17 @@ struct ce_engine {
     uint64_t host_items = 0;
     if (gi >= 0) {
       s.device_kind[gi] = CE_DEV_GPU;
-      const uint64_t np = __atomic_load_n(&l1->gpu_packages, __ATOMIC_ACQUIRE);
-      const uint64_t gr = __atomic_load_n(&l1->gpu_granules, __ATOMIC_ACQUIRE);
+      uint64_t np = __atomic_load_n(&l1->gpu_packages, __ATOMIC_ACQUIRE);
+      uint64_t gr = __atomic_load_n(&l1->gpu_granules, __ATOMIC_ACQUIRE);
       const uint64_t tf = __atomic_load_n(&l1->gpu_t_first, __ATOMIC_ACQUIRE);
-      const uint64_t tl = __atomic_load_n(&l1->gpu_t_last, __ATOMIC_ACQUIRE);
+      uint64_t tl = __atomic_load_n(&l1->gpu_t_last, __ATOMIC_ACQUIRE);
+      if (fast_exit) {
+        // the one pre-claimed package; the GPU ended when its last workgroup left
+        np = 1;
+        gr = fast_g1 - fast_g0;
+        tl = 0;
+        for (uint32_t i = 0; i < gpu_grid_last; ++i) tl = std::max(tl, __atomic_load_n(&wg_end[i], __ATOMIC_ACQUIRE));
+      }
       s.packages[gi] = np;
       s.granules[gi] = gr;
       s.t_device[gi] = np ? std::max(0.0, tick_to_host_s(tl)) : 0.0;
@@ -1409,6 +1431,13 @@ struct ce_engine {
     memset(l1, 0, sizeof(L1State));
     if ((he = hipHostGetDevicePointer((void**)&l1_dev, l1, 0)) != hipSuccess)
       return hip_fail(he, "create: device view of host memory");
+    if ((he = hipHostMalloc(&p, kFastExitMaxWgs * sizeof(uint64_t), hipHostMallocCoherent | hipHostMallocMapped)) !=
+        hipSuccess)
+      return hip_fail(he, "create: coherent host memory");
+    wg_end = (uint64_t*)p;
+    memset(wg_end, 0, kFastExitMaxWgs * sizeof(uint64_t));
+    if ((he = hipHostGetDevicePointer((void**)&wg_end_dev, wg_end, 0)) != hipSuccess)
+      return hip_fail(he, "create: device view of host memory");
     if ((he = hipMalloc((void**)&l2, sizeof(L2State))) != hipSuccess) return hip_fail(he, "create: queue state");
     if ((he = hipMemset(l2, 0, sizeof(L2State))) != hipSuccess) return hip_fail(he, "create: queue state");
     // the allocation-free run's scratch on this GPU (a failure only disables that run)
@@ -1471,6 +1500,7 @@ struct ce_engine {
     if (own_stream) (void)hipStreamDestroy(own_stream);
     if (l2) (void)hipFree(l2);
     if (l1) (void)hipHostFree(l1);
+    if (wg_end) (void)hipHostFree(wg_end);
   }
 };
 

@@ -496,6 +496,14 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
         const uint64_t tp = now_tick();
         dev_store(&s.pkgs[0].t_claim, tp);
         sys_store(&s.l1->gpu_t_first, tp);
+        if (s.wg_end) {
+          // no last workgroup will write the rest of its trace record
+          PkgSlot* ps = &s.pkgs[0];
+          ps->g0 = s.pre_g0;
+          ps->g1 = s.pre_g1;
+          ps->base = 0;
+          ps->ntiles = s.pre_nt;
+        }
       }
     }
   }
@@ -570,6 +578,11 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
   }
   if (wave0) {
     if (lane0) {
+      if (sa.wg_end) {
+        // fast exit: nothing to count or reset, the host reads the ticks
+        sys_store(&sa.wg_end[blockIdx.x], now_tick());
+        return;
+      }
       // the last computing workgroup out marks the end of the GPU's work
       // (gather workgroups may still be copying the host's output)
       if (sa.gather_wgs && dev_add(&sa.l2->exit_compute, 1u) + 1 == gridDim.x - sa.gather_wgs)

@@ -352,6 +352,9 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, 
     __atomic_store_n(&s.l1->gpu_t_last, t_last, __ATOMIC_RELEASE);
     __atomic_store_n(&s.l1->gpu_granules, gr, __ATOMIC_RELEASE);
     __atomic_store_n(&s.l1->gpu_packages, np, __ATOMIC_RELEASE);
+    if (s.wg_end) {
+      __atomic_store_n(&s.wg_end[0], t_last, __ATOMIC_RELEASE);  // fast exit: one workgroup's end
+    }
     __atomic_store_n(&s.l1->gpu_done, done_word(s.run_id, (uint64_t)(now_ns() / 10)), __ATOMIC_RELEASE);
   });
   return hipSuccess;
