@@ -99,6 +99,8 @@ def parse():
                     help="how the host's share reaches a device output: the GPU's copy engines (dma) or "
                          "gather workgroups inside its kernel (gpu)")
     ap.add_argument("--host-threads", type=int, default=0)
+    ap.add_argument("--quick", action="store_true",
+                    help="one set of two runs per quantity (for profilers; not the protocol of section 7.3)")
     return ap.parse_args()
 
 
@@ -170,9 +172,11 @@ def dist_ms(v):
     return {"median_ms": med(v) * 1e3, "p5_ms": pct(v, 5) * 1e3, "p95_ms": pct(v, 95) * 1e3, "runs": len(v)}
 
 
-def protocol(fn, sets=SETS, per_set=RUNS, after=None):
+def protocol(fn, sets=None, per_set=None, after=None):
     """Section 7.3: `sets` sets of per_set + 1 runs, the first of each set
     discarded. Returns the kept run times (s) and after()'s value per kept run."""
+    sets = SETS if sets is None else sets
+    per_set = RUNS if per_set is None else per_set
     times, extra = [], []
     for _ in range(sets):
         for i in range(per_set + 1):
@@ -187,9 +191,10 @@ def protocol(fn, sets=SETS, per_set=RUNS, after=None):
     return times, extra
 
 
-def runs_for(t_one, budget_s, lo=2, hi=RUNS):
-    """Runs per set that fit three sets into budget_s, given one run's time."""
-    return int(max(lo, min(hi, budget_s / max(1e-9, 3.0 * t_one))))
+def runs_for(t_one, budget_s, lo=2, hi=None):
+    """Runs per set that fit the sets into budget_s, given one run's time."""
+    hi = RUNS if hi is None else hi
+    return int(max(min(lo, hi), min(hi, budget_s / max(1e-9, SETS * t_one))))
 
 
 def chrome_trace(trace, stats, path, title):
@@ -528,7 +533,11 @@ def alu_roofline(flops, lane_ops, kern_ms, kernel, counters_name=None):
     if counters_name:
         rec = measured(counters_name)
         r["counters"] = {k: rec[k] for k in ("valu_busy", "valu_utilization", "valu_insts_per_dispatch",
-                                             "command") if k in rec} if rec else None
+                                             "valu_issue_frac_from_counts", "fp32_arith_issue_frac",
+                                             "fp32_tflops_from_counts", "kernel_us_median_trace")
+                         if k in rec} if rec else None
+        if rec:
+            r["counters"]["summary"] = "profiles/" + counters_name.replace(".json", ".md")
     return r
 
 
@@ -609,14 +618,22 @@ def roofline_for(wl, sp, leg, ce, torch, np, stream, hev, K):
         r.update({"iterations": iters, "flops_per_iteration": 8, "lane_efficiency": eff})
         return r
     n = sp.n_items
-    r = alu_roofline(20.0 * n * n * share, 24.0 * n * n * share, kern, "k_persistent<NbodyTile<true>>",
-                     "nbody_65536_valu.json")
-    r.update({"flops_per_interaction": 20, "lane_ops_per_interaction": 24})
+    strict = getattr(sp, "exact", True)
+    # VALU lane-ops per interaction: 3 subs, 3 fmas, the 1/sqrt (strict: Lomont's
+    # estimate and three Newton steps, 12; fast: one v_rsq_f32), 3 muls, 3 fmas
+    lane = 24 if strict else 13
+    r = alu_roofline(20.0 * n * n * share, lane * n * n * share, kern,
+                     "k_persistent<NbodyTile<true>>" if strict else "k_persistent<NbodyTile<false>>",
+                     "nbody_65536_valu.json" if strict else "nbody_65536_fast_valu.json")
+    r.update({"flops_per_interaction": 20, "lane_ops_per_interaction": lane})
     return r
 
 
 def main():
+    global SETS, RUNS, OVERHEAD_RUNS
     args = parse()
+    if args.quick:
+        SETS, RUNS, OVERHEAD_RUNS = 1, 2, 2
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
@@ -672,7 +689,6 @@ def main():
         fl = coexec_leg(ce, fsp, "device", args, stream, hev, torch, np, K=max(3, args.steps // 2))
         out_fast = fl["_out"].cpu().numpy().view(np.float32).reshape(-1, 4)
         fr = roofline_for("nbody", fsp, fl, ce, torch, np, stream, hev, args.steps)
-        fr["kernel"] = "k_persistent<NbodyTile<false>>"
         res["fast_rsqrt"] = dict(public(fl), roofline=fr, note="v_rsq_f32 on the GPU, 1/sqrtf on the host")
         del out_fast
     if args.sched_grid:
