@@ -26,7 +26,8 @@ core beside it), nbody (65,536 bodies, Dynamic 256-body packages, GPU + every
 core; the hardware 1/sqrt beside the strict one), escape-roofline (8192^2,
 max_iter 4096, GPU), runtime, nbody-step, binomial, batch, serve, copy.
 --sched-grid adds the paper's scheduler grid (Static, Static rev, Dynamic 50
-and 150 packages, HGuided) and --sweep the overhead against problem size.
+and 150 packages, HGuided) and --sweep the overhead and the co-execution
+efficiency against problem size.
 """
 from __future__ import annotations
 
@@ -94,7 +95,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-host-resident", action="store_true", help="skip the host-resident leg")
     ap.add_argument("--sched-grid", action="store_true", help="add the scheduler grid of section 7.3")
-    ap.add_argument("--sweep", action="store_true", help="add the overhead against problem size")
+    ap.add_argument("--sweep", action="store_true",
+                    help="add the overhead and the co-execution efficiency against problem size")
     ap.add_argument("--merge", choices=["dma", "gpu"], default="dma",
                     help="how the host's share reaches a device output: the GPU's copy engines (dma) or "
                          "gather workgroups inside its kernel (gpu)")
@@ -694,7 +696,7 @@ def main():
     if args.sched_grid:
         res["sched_grid"] = sched_grid(ce, sp, args, stream, hev, torch, np)
     if args.sweep:
-        res["overhead_sweep"] = overhead_sweep(wl, ce, synth, args, stream, torch, np)
+        res["size_sweep"] = size_sweep(wl, ce, synth, args, stream, torch, np)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_for(wl, sp, np)
     print(json.dumps(res), flush=True)
@@ -720,61 +722,83 @@ def sched_grid(ce, sp, args, stream, hev, torch, np):
     return out
 
 
-def overhead_sweep(wl, ce, synth, args, stream, torch, np):
-    """Engine with the GPU alone against the plain launch, across problem
-    sizes (section 8.2): 3 sets of 100 runs each."""
-    import numpy as _np
+def size_sweep(wl, ce, synth, args, stream, torch, np):
+    """Overhead and co-execution efficiency across problem sizes (sections
+    8.2 and 8.3): at each size the plain launch, the engine with the GPU
+    alone, the host alone and HGuided over the GPU and every core (powers
+    from the standalone times), each timed by the protocol within a few
+    seconds."""
     dev = torch.device("cuda:0")
     rows = []
     if wl == "blur":
         cases = [(s, s) for s in (1024, 2048, 4096, 8192, 16384)]
     elif wl in ("escape", "runtime"):
-        cases = [(s, s) for s in (256, 512, 1024, 2048, 4096)]
+        cases = [(s, s) for s in (256, 512, 1024, 2048, 4096, 8192)]
     else:
         cases = [(n,) for n in (4096, 8192, 16384, 32768, 65536)]
     for c in cases:
+        log(f"size sweep {wl} {c}")
         if wl == "blur":
             w, h = c
-            img = synth.blur_image(w, h, seed=w)
-            ins = [torch.from_numpy(img).to(dev), torch.from_numpy(ce.ce_gauss5_weights(1.0)).to(dev)]
-            out = torch.empty_like(ins[0])
+            ins_h = [synth.blur_image(w, h, seed=w), ce.ce_gauss5_weights(1.0)]
             kid, prm, gws, lws, items = ce.CE_KERNEL_BLUR5, ce.ce_blur5_params(w, h), [w, h], None, w * h
+            out = torch.empty((h, w), dtype=torch.float32, device=dev)
         elif wl in ("escape", "runtime"):
             w, h = c
             p = synth.escape_region(w, h, -2.0, 1.0, -1.5, 1.5, 256)
-            ins, out = [], torch.empty((h, w), dtype=torch.int32, device=dev)
+            ins_h = []
             kid, prm, gws, lws, items = (ce.CE_KERNEL_ESCAPE, ce.ce_escape_params(w, h, *p.as_f32(), 256), [w, h],
                                          None, w * h)
+            out = torch.empty((h, w), dtype=torch.int32, device=dev)
         else:
             n = c[0]
-            ins = [torch.from_numpy(synth.nbody_bodies(n)).to(dev)]
-            out = torch.empty_like(ins[0])
+            ins_h = [synth.nbody_bodies(n)]
             kid, prm, gws, lws, items = ce.CE_KERNEL_NBODY_ACC, ce.ce_nbody_params(n, 1e-6, 1), [n], [256], n
+            out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+        ins = [torch.from_numpy(a).to(dev) for a in ins_h]
         torch.cuda.synchronize()
         bare = lambda: ce.ce_bare_run(kid, prm, ins, out, stream=stream.cuda_stream, sync=True)
         for _ in range(3):
             bare()
         t0 = time.perf_counter()
         bare()
-        per = runs_for(time.perf_counter() - t0, 4.0, lo=5, hi=OVERHEAD_RUNS)
+        per = runs_for(time.perf_counter() - t0, 3.0, lo=5, hi=OVERHEAD_RUNS)
         tb, _ = protocol(bare, per_set=per)
         eng = ce.Engine()
         eng.stream(stream.cuda_stream)
-        eng.use(ce.CE_DEV_GPU, 0, 0)
         eng.work_items(gws, lws)
         eng.program_kernel(kid, prm)
-        for s_, d_ in enumerate(ins):
-            eng.program_in(s_, dev=d_, nbytes=d_.numel() * d_.element_size())
+        for s_, (a_, d_) in enumerate(zip(ins_h, ins)):
+            eng.program_in(s_, host=a_, dev=d_, nbytes=a_.nbytes)
         eng.program_out(0, dev=out, nbytes=out.numel() * out.element_size())
+        eng.use(ce.CE_DEV_GPU, 0, 0)
         eng.scheduler(ce.CE_SCHED_STATIC)
         for _ in range(3):
             eng.run()
         tg, _ = protocol(eng.run, per_set=per)
+        eng.use(ce.CE_DEV_HOST, 0, args.host_threads)
+        t0 = time.perf_counter()
+        eng.run()
+        th, _ = protocol(eng.run, per_set=runs_for(time.perf_counter() - t0, 2.0, lo=2))
+        T_b, T_g, T_h = med(tb), med(tg), med(th)
+        t_min = min(T_g, T_h)
+        eng.use(ce.CE_DEV_GPU | ce.CE_DEV_HOST, 0, args.host_threads)
+        eng.scheduler(kind=ce.CE_SCHED_HGUIDED, k=2,
+                      power=[max(1, int(round(4096 * t_min / T_g))), max(1, int(round(4096 * t_min / T_h)))])
+        for _ in range(3):
+            eng.run()
+        t0 = time.perf_counter()
+        eng.run()
+        tc, stc = protocol(eng.run, per_set=runs_for(time.perf_counter() - t0, 2.0, lo=2), after=eng.stats)
         eng.close()
+        T_c = med(tc)
+        s_max = min(T_b, T_h) * (1.0 / T_b + 1.0 / T_h)
         rows.append({"size": list(c), "items": items, "t_bare": dist_ms(tb), "t_engine_gpu": dist_ms(tg),
-                     "overhead_pct": (med(tg) - med(tb)) / med(tb) * 100.0})
+                     "t_engine_host": dist_ms(th), "t_coexec": dist_ms(tc),
+                     "overhead_pct": (T_g - T_b) / T_b * 100.0, "s_real": T_b / T_c, "s_max": s_max,
+                     "efficiency": (T_b / T_c) / s_max, "balance": med([s_.balance for s_ in stc]),
+                     "gpu_share": med([s_.items[0] for s_ in stc]) / items})
         del ins, out
-    del _np
     return rows
 
 

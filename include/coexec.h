@@ -173,6 +173,11 @@ typedef struct {
   double t_gather;                    /* end of the GPU's last copy of host output into
                                        * the device output (0: no such copies)  */
   uint64_t gathered_bytes;            /* bytes of host output the GPU copied     */
+  /* where the calling thread's time went (seconds from the start of the
+   * run; 0 for phases the run did not have): the GPU kernel launched, the
+   * host device's share finished, the GPU's completion seen, the GPU's
+   * stream synchronised, the host's output copies into HBM drained */
+  double t_launched, t_host_done, t_gpu_seen, t_synced, t_copies_done;
 } ce_run_stats;
 
 /* One package of the last run (section 5 "Introspector"): device, granule

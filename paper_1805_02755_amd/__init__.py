@@ -118,7 +118,9 @@ class ce_run_stats(C.Structure):
                 ("packages", C.c_uint64 * CE_MAX_DEVICES), ("n_devices", C.c_uint32),
                 ("device_kind", C.c_uint32 * CE_MAX_DEVICES), ("balance", C.c_double),
                 ("total_granules", C.c_uint64), ("total_items", C.c_uint64), ("gpu_workgroups", C.c_uint32),
-                ("host_threads", C.c_uint32), ("t_gather", C.c_double), ("gathered_bytes", C.c_uint64)]
+                ("host_threads", C.c_uint32), ("t_gather", C.c_double), ("gathered_bytes", C.c_uint64),
+                ("t_launched", C.c_double), ("t_host_done", C.c_double), ("t_gpu_seen", C.c_double),
+                ("t_synced", C.c_double), ("t_copies_done", C.c_double)]
 
 
 class ce_batch_config(C.Structure):

@@ -282,6 +282,7 @@ struct ce_engine {
   uint64_t* wg_end = nullptr;      // host-coherent, kFastExitMaxWgs entries (fast exit)
   uint64_t* wg_end_dev = nullptr;
   bool fast_exit = false;          // this run's kernel uses the fast exit
+  int64_t ph_launched = 0, ph_host_done = 0, ph_gpu_seen = 0, ph_synced = 0, ph_copies = 0;  // phase ends (ns)
   uint64_t fast_g0 = 0, fast_g1 = 0;  // its one package
   double dispenser_wait_s = (double)kDispenserWaitSeconds;  // bounds on the kernel's waits
   double gather_wait_s = (double)kGatherWaitSeconds;
@@ -1183,6 +1184,8 @@ struct ce_engine {
       if ((he = launch_persistent(kargs, gs, grid, stream)) != hipSuccess) return hip_fail(he, "run: kernel launch");
       if (ev_stop && (he = hipEventRecord(ev_stop, stream)) != hipSuccess) return hip_fail(he, "run: event");
     }
+    ph_launched = use_gpu() ? now_ns() : 0;
+    ph_host_done = ph_gpu_seen = ph_synced = ph_copies = 0;
     gpu_grid_last = grid;
     if (use_host()) {
       ensure_pool();
@@ -1203,9 +1206,11 @@ struct ce_engine {
       }
       const uint32_t want = (uint32_t)pool.size();
       while (pool_done.load(std::memory_order_acquire) < want) cpu_relax();
+      ph_host_done = now_ns();
     }
     if (use_gpu() && fast_exit) {
       if ((he = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(he, "run: kernel");
+      ph_synced = now_ns();
     } else if (use_gpu()) {
       // the last workgroup out writes the done word; poll it, then sync
       const int64_t deadline = now_ns() + kGpuDeadlineNs;
@@ -1225,7 +1230,9 @@ struct ce_engine {
         const uint64_t tl = unwrap_tick40(dw & kTick40, seen);
         re_anchor(tl, seen);
       }
+      ph_gpu_seen = now_ns();
       if ((he = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(he, "run: kernel");
+      ph_synced = now_ns();
       if (!done_is(__atomic_load_n(&l1->gpu_done, __ATOMIC_ACQUIRE), run_id))
         return fail(CE_E_TIMEOUT, "run: GPU did not report completion");
       if (gather) memset(ring_buf.p, 0, ring_count.load() * sizeof(uint64_t));  // ready for the next run
@@ -1236,6 +1243,7 @@ struct ce_engine {
       // the last host packages' copies finish after the host's work
       push_drain(0);
       push_end_ns = now_ns();
+      ph_copies = push_end_ns;
       if (push_error.load()) return fail(CE_E_DEVICE, "run: host output copy to the device failed");
     }
     if (host_error.load()) return fail(CE_E_DEVICE, "run: host package table overflow");
@@ -1332,6 +1340,12 @@ struct ce_engine {
     s.n_devices = n_devices();
     s.total_granules = G;
     s.gpu_workgroups = use_gpu() ? gpu_grid_last : 0;
+    auto ph = [&](int64_t t) { return t ? (double)(t - t0_ns) * 1e-9 : 0.0; };
+    s.t_launched = ph(ph_launched);
+    s.t_host_done = ph(ph_host_done);
+    s.t_gpu_seen = ph(ph_gpu_seen);
+    s.t_synced = ph(ph_synced);
+    s.t_copies_done = ph(ph_copies);
     s.host_threads = use_host() ? (uint32_t)host_threads : 0;
     const int gi = gpu_index(), hi = host_index();
     uint64_t host_items = 0;
