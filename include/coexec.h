@@ -175,8 +175,10 @@ typedef struct {
   uint64_t gathered_bytes;            /* bytes of host output the GPU copied     */
   /* where the calling thread's time went (seconds from the start of the
    * run; 0 for phases the run did not have): the GPU kernel launched, the
-   * host device's share finished, the GPU's completion seen, the GPU's
-   * stream synchronised, the host's output copies into HBM drained */
+   * host device's share finished, the GPU's first workgroup seen starting
+   * (only in runs that re-anchor the GPU clock mapping, one every 5 ms at
+   * most), the GPU's stream synchronised, the host's output copies into
+   * HBM drained */
   double t_launched, t_host_done, t_gpu_seen, t_synced, t_copies_done;
 } ce_run_stats;
 

@@ -44,11 +44,16 @@ inline void cpu_relax() { _mm_pause(); }
 
 constexpr uint32_t kHostNbodyTile = 16;  // bodies per host tile
 constexpr int kMaxSlots = 2;
-// Bounds on the waits inside the GPU kernel, and the host's deadline for a
-// kernel's completion word, which is longer than both.
+// Bounds on the waits inside the GPU kernel: every kernel ends, so the host
+// can wait for it with a plain stream synchronisation.
 constexpr uint64_t kDispenserWaitSeconds = 5;
 constexpr uint64_t kGatherWaitSeconds = 60;
-constexpr int64_t kGpuDeadlineNs = 120'000'000'000LL;
+// Longest time between two re-anchorings of the GPU clock mapping: at the
+// tens of parts per million the two clocks drift apart, a tenth of a
+// microsecond at most.
+constexpr double kReanchorNs = 5e6;
+// How long a re-anchoring run watches for the GPU's first workgroup.
+constexpr int64_t kAnchorWatchNs = 2'000'000;
 
 struct Binding {
   const void* host = nullptr;  // input: read by host workers
@@ -177,8 +182,9 @@ struct ce_engine {
   PkgSlot* trace_pkgs = nullptr;     // package table of the last run
   uint32_t trace_pkgs_cap = 0;
   // GPU tick -> host ns: host_ns = anchor_ns + (tick - anchor_tick) * ns_per_tick.
-  // The anchor is the GPU's latest completion seen as it happened; the rate
-  // is measured between the calibration at creation and that anchor, since
+  // The anchor is the latest GPU start the host saw as it happened (renewed
+  // every few milliseconds); the rate is measured between the calibration
+  // at creation and that anchor, since
   // the two clocks drift apart by a few parts per million (tens of
   // microseconds over a few seconds, as much as a whole blur run).
   uint64_t anchor0_tick = 0, anchor_tick = 0;
@@ -307,19 +313,6 @@ struct ce_engine {
   uint32_t n_devices() const { return (use_gpu() ? 1u : 0u) + (use_host() ? 1u : 0u); }
   int gpu_index() const { return use_gpu() ? 0 : -1; }
   int host_index() const { return use_host() ? (use_gpu() ? 1 : 0) : -1; }
-
-  // The full tick whose low 40 bits are t40, nearest to the host time
-  // host_ns under the current mapping (the mapping is off by far less than
-  // the 2^40-tick wrap).
-  uint64_t unwrap_tick40(uint64_t t40, double host_ns) const {
-    const double est = (double)anchor_tick + (host_ns - anchor_ns) / ns_per_tick;
-    const uint64_t e = est > 0.0 ? (uint64_t)est : 0;
-    const uint64_t half = 1ull << 39;
-    uint64_t t = (e & ~kTick40) | t40;
-    if (t > e + half && t > kTick40) t -= kTick40 + 1;
-    else if (t + half < e) t += kTick40 + 1;
-    return t;
-  }
 
   double tick_to_host_s(uint64_t tick) const {
     return (tick_to_host_ns(tick) - (double)t0_ns) * 1e-9;
@@ -1170,6 +1163,10 @@ struct ce_engine {
 
     t0_ns = now_ns();
     fast_exit = false;
+    // Once the clock mapping's anchor is old, the host watches for the
+    // GPU's first workgroup to stamp its start and re-anchors on it (the
+    // host's own work then starts a few microseconds late).
+    bool anchor_watch = false;
     if (use_gpu()) {
       gpu_preclaim(gs);
       // The GPU's whole share was claimed before the launch and every
@@ -1177,6 +1174,8 @@ struct ce_engine {
       // workgroup needs to count out (the overhead of a single-device run
       // is then that of a plain launch plus the dispenser's first ticket).
       fast_exit = gs.pre_only && gs.stride && !gather && grid <= kFastExitMaxWgs;
+      anchor_watch = clock_ok && gs.pre_nt && (double)t0_ns - anchor_ns > kReanchorNs;
+      if (anchor_watch) __atomic_store_n(&l1->gpu_t_first, 0, __ATOMIC_RELAXED);  // before the doorbell
       gs.wg_end = fast_exit ? wg_end_dev : nullptr;
       fast_g0 = gs.pre_g0;
       fast_g1 = gs.pre_g1;
@@ -1186,6 +1185,18 @@ struct ce_engine {
     }
     ph_launched = use_gpu() ? now_ns() : 0;
     ph_host_done = ph_gpu_seen = ph_synced = ph_copies = 0;
+    if (anchor_watch) {
+      // Only a start seen as it happens (the first read still finds zero)
+      // is an anchor: the host time is then the tick's, give or take the
+      // one-way latency measured at calibration.
+      const int64_t give_up = now_ns() + kAnchorWatchNs;
+      uint64_t tf = __atomic_load_n(&l1->gpu_t_first, __ATOMIC_ACQUIRE);
+      if (tf == 0) {
+        while ((tf = __atomic_load_n(&l1->gpu_t_first, __ATOMIC_ACQUIRE)) == 0 && now_ns() < give_up) cpu_relax();
+        if (tf) re_anchor(tf, (double)now_ns() - clock_latency_ns);
+      }
+      ph_gpu_seen = now_ns();
+    }
     gpu_grid_last = grid;
     if (use_host()) {
       ensure_pool();
@@ -1212,25 +1223,7 @@ struct ce_engine {
       if ((he = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(he, "run: kernel");
       ph_synced = now_ns();
     } else if (use_gpu()) {
-      // the last workgroup out writes the done word; poll it, then sync
-      const int64_t deadline = now_ns() + kGpuDeadlineNs;
-      bool waited = false;
-      uint64_t dw;
-      while (!done_is(dw = __atomic_load_n(&l1->gpu_done, __ATOMIC_ACQUIRE), run_id)) {
-        waited = true;
-        if (now_ns() > deadline) break;
-        cpu_relax();
-      }
-      if (waited && clock_ok && done_is(dw, run_id)) {
-        // The host saw the GPU's last store as it happened (give or take the
-        // one-way latency measured at calibration): re-anchor the tick -> host
-        // mapping here, so the two clocks' drift since creation does not
-        // accumulate into the device times.
-        const double seen = (double)now_ns() - clock_latency_ns;
-        const uint64_t tl = unwrap_tick40(dw & kTick40, seen);
-        re_anchor(tl, seen);
-      }
-      ph_gpu_seen = now_ns();
+      // the last workgroup out writes the done word before the kernel ends
       if ((he = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(he, "run: kernel");
       ph_synced = now_ns();
       if (!done_is(__atomic_load_n(&l1->gpu_done, __ATOMIC_ACQUIRE), run_id))
@@ -1402,7 +1395,13 @@ struct ce_engine {
   size_t build_trace() {
     trace.clear();
     const int gi = gpu_index(), hi = host_index();
-    if (gi >= 0 && gpu_pkgs_last) {
+    if (gi >= 0 && gpu_pkgs_last && fast_exit) {
+      // the one pre-claimed package: its record is the host's own
+      uint64_t tl = 0;
+      for (uint32_t i = 0; i < gpu_grid_last; ++i) tl = std::max(tl, __atomic_load_n(&wg_end[i], __ATOMIC_ACQUIRE));
+      const uint64_t tf = __atomic_load_n(&l1->gpu_t_first, __ATOMIC_ACQUIRE);
+      trace.push_back(ce_package_rec{(uint32_t)gi, 0, fast_g0, fast_g1, tick_to_host_s(tf), tick_to_host_s(tl)});
+    } else if (gi >= 0 && gpu_pkgs_last) {
       std::vector<PkgSlot> v(std::min<uint64_t>(gpu_pkgs_last, trace_pkgs_cap));
       if (hipMemcpy(v.data(), trace_pkgs, v.size() * sizeof(PkgSlot), hipMemcpyDeviceToHost) == hipSuccess) {
         for (auto& p : v)

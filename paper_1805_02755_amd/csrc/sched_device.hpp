@@ -475,6 +475,18 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
   const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) == 0;
   const bool lane0 = threadIdx.x == 0;
   pay.load_constants();
+  if (s.wg_end) {
+    // Fast exit: the GPU's whole share is the package the host claimed
+    // before the launch and workgroup w runs its tickets w, w + n, w + 2n
+    // ...: no claim, no cursor and no barrier of the dispenser's. Each
+    // workgroup leaves the tick at which it ended; the host takes the GPU's
+    // end from them and writes the package's trace record itself.
+    if (blockIdx.x == 0 && lane0) sys_store(&s.l1->gpu_t_first, now_tick());
+    for (uint32_t t = blockIdx.x; t < s.pre_nt; t += gridDim.x) pay.run(s.pre_g0, s.pre_g1, t);
+    __syncthreads();  // every wave's tiles are done
+    if (lane0) sys_store(&s.wg_end[blockIdx.x], now_tick());
+    return;
+  }
   // The scheduler arguments are read from LDS inside the tile loop: kept in
   // scalar registers across the payload they would crowd out its own.
   __shared__ SchedArgs sh_args;
@@ -496,14 +508,6 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
         const uint64_t tp = now_tick();
         dev_store(&s.pkgs[0].t_claim, tp);
         sys_store(&s.l1->gpu_t_first, tp);
-        if (s.wg_end) {
-          // no last workgroup will write the rest of its trace record
-          PkgSlot* ps = &s.pkgs[0];
-          ps->g0 = s.pre_g0;
-          ps->g1 = s.pre_g1;
-          ps->base = 0;
-          ps->ntiles = s.pre_nt;
-        }
       }
     }
   }
@@ -578,11 +582,6 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
   }
   if (wave0) {
     if (lane0) {
-      if (sa.wg_end) {
-        // fast exit: nothing to count or reset, the host reads the ticks
-        sys_store(&sa.wg_end[blockIdx.x], now_tick());
-        return;
-      }
       // the last computing workgroup out marks the end of the GPU's work
       // (gather workgroups may still be copying the host's output)
       if (sa.gather_wgs && dev_add(&sa.l2->exit_compute, 1u) + 1 == gridDim.x - sa.gather_wgs)

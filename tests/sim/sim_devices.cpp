@@ -309,7 +309,10 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, 
         break;
       }
       const uint64_t tc = (uint64_t)(now_ns() / 10);
-      if (!np) t_first = tc;
+      if (!np) {
+        t_first = tc;
+        __atomic_store_n(&s.l1->gpu_t_first, t_first, __ATOMIC_RELEASE);  // the start, as a workgroup stamps it
+      }
       const uint64_t n = items_of(a, g0, g1);
       const int64_t until = now_ns() + (int64_t)(g_gpu_ns_per_item * (double)n);
       mark((uint32_t*)a.out, first_item(a, g0), first_item(a, g0) + n, item_words(a));
