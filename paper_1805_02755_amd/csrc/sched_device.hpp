@@ -165,6 +165,8 @@ struct Cursor {  // zero-initialised at the start of a run
   uint64_t base, g0, g1;
   uint64_t cur_t;  // ticket of the tile being run
   uint32_t p, nt;  // nt == 0: no package yet
+  uint32_t fresh;  // tot_seen is still the launch's own count (first ticket)
+  uint32_t pad;
 };
 
 // After a tile: if it held its package's last ticket, stamp the package end.
@@ -198,8 +200,13 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
   }
   const uint64_t t = c.t_next++;
   if (s.pre_only && t >= s.pre_nt) return false;
+  // The count passed with the launch is current when the workgroups start:
+  // with its first ticket inside the published tiles, only the designated
+  // claimer needs to read the shared count again.
+  const bool known = c.fresh && t < c.tot_seen && t + s.lookahead != c.tot_seen;
+  c.fresh = 0;
   uint64_t spins = 0, t0 = 0;
-  while (!s.pre_only && t + s.lookahead >= c.tot_seen) {
+  while (!s.pre_only && !known && t + s.lookahead >= c.tot_seen) {
     // The published tile count and the "no more packages" flag share one
     // word, so a workgroup never pairs a stale count with a fresh flag (which
     // would make it leave with a ticket that did get published).
@@ -259,6 +266,7 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
     if (waited_out(&t0, s.wait_ticks)) {
       sys_store(&s.l1->gpu_flags, 1);
       __hip_atomic_fetch_or(&q->total, kTotalDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0);  // done before this workgroup counts out and the state is reset
       return false;
     }
     // waiting workgroups poll gently so the claimer's stores are not queued
@@ -327,10 +335,12 @@ __device__ __forceinline__ bool count_out(L2State* q) {
 // and its stores drained once: each round trip here adds to the kernel.
 __device__ void leave(const SchedArgs& s) {
   L2State* q = s.l2;
-  // This workgroup's dispenser atomics are done before it counts itself out
-  // (waiting for them is enough; an agent-scope release would also write back
-  // this XCD's L2, once per workgroup).
-  __builtin_amdgcn_s_waitcnt(0);
+  // Every store of the dispenser's that the last workgroup reads or resets
+  // is waited for where it is made (the claim lock, the timeout flag), so a
+  // workgroup counts out without draining its tile's output stores first.
+  // The last computing workgroup's end tick is read by the last gatherer:
+  // with gatherers, that store is drained here.
+  if (s.gather_wgs) __builtin_amdgcn_s_waitcnt(0);
   if (!count_out(q)) return;
   // without gatherers the last workgroup out is the last computing one
   const uint64_t tl = s.gather_wgs ? dev_load(&q->t_last) : now_tick();
@@ -379,10 +389,10 @@ __device__ void leave(const SchedArgs& s) {
   }
   for (uint32_t x = 0; x < kExitLines; ++x) dev_store(&q->exit_x[x][0], 0u);
   dev_store(&q->exit_count, 0u);
-  // The host polls this word and reads everything else only after the
-  // kernel has ended, so no store above needs to be ordered before it (a
-  // release here would also write back this XCD's L2, which the end of the
-  // kernel does anyway). Its tick lets the host re-anchor the clock mapping.
+  // The host reads this word and everything else only after the kernel has
+  // ended, so no store above needs to be ordered before it (a release here
+  // would also write back this XCD's L2, which the end of the kernel does
+  // anyway).
   sys_store(&s.l1->gpu_done, done_word(s.run_id, now_tick()));
 }
 
@@ -503,6 +513,7 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
       c.t_next = blockIdx.x - s.gather_wgs;  // the first ticket needs no atomic
       c.t_end = c.t_next + 1;
       c.tot_seen = s.pre_nt;
+      c.fresh = 1;
       if (s.pre_nt && c.t_next == 0) {
         // the pre-claimed package starts with the first workgroup
         const uint64_t tp = now_tick();
