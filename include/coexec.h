@@ -330,10 +330,11 @@ ce_status ce_engine_output_merge(ce_engine* e, int mode);
 ce_status ce_engine_wait_bounds(ce_engine* e, double dispenser_s, double gather_s);
 
 /* Number of workgroups of the GPU's persistent kernel for the following
- * runs; 0 (the default) lets the engine choose: the resident workgroups
- * (occupancy x compute units) spread so that the tiles of the whole index
- * space make whole rounds, i.e. ceil(T / ceil(T / R)) for T tiles and R
- * resident workgroups, and never more than T. A caller's value is used as
+ * runs; 0 (the default) lets the engine choose: for T tiles of the whole
+ * index space, R resident workgroups (occupancy x compute units) and C
+ * compute units, the largest g <= min(T, R) that minimises
+ * ceil(T / g) * ceil(g / C), the tiles run by the busiest compute unit
+ * (whole rounds, spread evenly over the CUs). A caller's value is used as
  * given (it may exceed what fits on the GPU at once: the dispenser's
  * waits do not depend on every workgroup being resident), plus the gather
  * workgroups of CE_MERGE_GPU_GATHER. Affects speed only, never results.

@@ -857,6 +857,33 @@ struct ce_engine {
     return st;
   }
 
+  // Persistent grid for T tiles on at most R resident workgroups over C
+  // compute units: with g workgroups the busiest CU runs ceil(T / g) rounds
+  // of ceil(g / C) workgroups, and the grid is the largest g that makes
+  // that product least. 2048 blur tiles on 1280 resident workgroups: 1024
+  // workgroups of two tiles each rather than a second round at 60 %; 8192
+  // tiles: 1024 workgroups of eight (measured 3 % faster than 1171 of seven,
+  // which leaves some CUs five workgroups and others four). The optimum is
+  // a multiple of C or a whole-round split ceil(T / m), so only those are
+  // tried.
+  static uint32_t balanced_grid(uint64_t T, uint64_t R, uint64_t C) {
+    const uint64_t top = std::max<uint64_t>(1, std::min(T, R));
+    uint64_t best = 1, best_cost = ~0ull;
+    auto consider = [&](uint64_t g) {
+      if (g < 1 || g > top) return;
+      const uint64_t cost = ceil_div(T, g) * ceil_div(g, C);
+      if (cost < best_cost || (cost == best_cost && g > best)) {
+        best_cost = cost;
+        best = g;
+      }
+    };
+    consider(top);
+    for (uint64_t k = 1; k * C <= top; ++k) consider(k * C);
+    const uint64_t m0 = ceil_div(T, top);
+    for (uint64_t m = m0; m < m0 + 8; ++m) consider(ceil_div(T, m));
+    return (uint32_t)best;
+  }
+
   // Scratch layout of the allocation-free run: the queue state, then the
   // publication words, then the package table. Packages that fit:
   static uint64_t noalloc_max_pkgs() {
@@ -1033,14 +1060,8 @@ struct ce_engine {
       if (grid_override) {
         grid = grid_override + gather_wgs;
       } else {
-        // Spread the tiles over whole rounds: with R resident workgroups and
-        // T tiles, ceil(T / R) rounds of ceil(T / rounds) workgroups, so no
-        // round runs with part of the GPU idle (2048 blur tiles on 1280
-        // resident workgroups: 1024 workgroups of two tiles each rather than
-        // a second round at 60 %).
         const uint64_t r = std::max<uint64_t>(1, resident - gather_wgs);
-        const uint64_t rounds = std::max<uint64_t>(1, ceil_div(all_tiles, r));
-        grid = (uint32_t)std::min<uint64_t>(r, std::max<uint64_t>(1, ceil_div(all_tiles, rounds))) + gather_wgs;
+        grid = balanced_grid(all_tiles, r, (uint64_t)std::max(1, n_cu)) + gather_wgs;
       }
       if (grid <= gather_wgs) grid = gather_wgs + 1;
     }
@@ -1115,16 +1136,18 @@ struct ce_engine {
       // even when part of the grid becomes resident only as the rest leaves:
       // under the round-robin those late workgroups would still own a full
       // share of tickets and run them on an otherwise idle GPU.
-      // A payload supplied at run time has tiles of unknown cost: dealt
-      // dynamically too.
       const bool long_tiles = kernel_id == CE_KERNEL_BINOMIAL;
       if (long_tiles) gs.chunk = 1;
       // Escape-time tiles of one column block over many rounds differ by
       // orders of magnitude (8192^2: workgroup w would run every 128th row of
       // one 512-pixel column, 64 tiles, the busiest columns all on the same
-      // workgroups): beyond one round they are dealt by atomic tickets.
-      const bool uneven = kernel_id == CE_KERNEL_ESCAPE && gpu_tiles(kargs, 0, G) > (uint64_t)(grid - gather_wgs);
-      gs.stride = (kernel_id == CE_KERNEL_RUNTIME || gather || long_tiles || uneven) ? 0u : 1u;
+      // workgroups), and a payload supplied at run time has tiles of unknown
+      // cost: beyond one round both are dealt by atomic tickets. Within one
+      // round every workgroup runs one tile either way, and the round-robin
+      // needs no atomic.
+      const bool uneven = (kernel_id == CE_KERNEL_ESCAPE || kernel_id == CE_KERNEL_RUNTIME) &&
+                          gpu_tiles(kargs, 0, G) > (uint64_t)(grid - gather_wgs);
+      gs.stride = (gather || long_tiles || uneven) ? 0u : 1u;
       // the gatherers wait for the host's packages, whose length depends on the problem
       gs.gather_wait_ticks = std::max<uint64_t>(1, (uint64_t)((double)wallclock_hz * gather_wait_s));
       if (gather) {

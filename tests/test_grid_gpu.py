@@ -5,6 +5,7 @@ by one workgroup), a few, and more workgroups than the GPU holds at once
 for every scheduler over the GPU alone and the GPU with the host."""
 import numpy as np
 import pytest
+import torch
 
 import paper_1805_02755_amd as ce
 from paper_1805_02755_amd import synth
@@ -76,18 +77,29 @@ def test_nbody_any_grid(eng, grid):
             check_trace(tr, (n + 255) // 256, st.n_devices)
 
 
-def test_default_grid_whole_rounds(eng):
-    """Without an override the grid spreads the tiles of the whole space
-    over whole rounds: ceil(T / ceil(T / R)) workgroups for T tiles, so
-    every workgroup gets the same number of tiles, give or take one."""
+def _busiest_cu_tiles(tiles, g, cus):
+    return -(-tiles // g) * -(-g // cus)
+
+
+@pytest.mark.parametrize("w,h", [(1024, 1024), (4096, 1024), (2048, 3000), (1000, 77)])
+def test_default_grid_balances_the_cus(eng, w, h):
+    """Without an override the grid spreads the tiles of the whole space so
+    that the busiest compute unit runs no more tiles than it must: with g
+    workgroups it runs ceil(T / g) rounds of ceil(g / C) workgroups, and the
+    least possible is ceil(T / C) (g = C achieves it); every workgroup gets
+    the same number of tiles, give or take one. Checked on escape-time grids
+    of 2048, 8192, 12,000 and 154 one-row tiles; the output stays exact."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
     eng.gpu_workgroups(0)
-    p = synth.escape_small()
-    run_payload(eng, ce.CE_KERNEL_ESCAPE, escape_params(p), [p.w, p.h], None, [], (p.h, p.w), np.uint32,
-                ce.CE_DEV_GPU, "static")
-    g = eng.stats().gpu_workgroups
-    tiles = 1024 * 2  # 1024 rows x two 512-pixel column blocks
+    p = synth.escape_region(w, h, -2.0, 1.0, -1.5, 1.5, 64)
+    out, st, tr = run_payload(eng, ce.CE_KERNEL_ESCAPE, escape_params(p), [w, h], None, [], (h, w), np.uint32,
+                              ce.CE_DEV_GPU, "static")
+    ref = O.escape(w, h, *[float(v) for v in p.as_f32()], p.max_iter)
+    assert np.array_equal(out, ref), diff_report(out, ref, tr)
+    g = st.gpu_workgroups
+    tiles = h * -(-w // 512)  # one-row tiles of 512 columns
     assert 0 < g <= tiles
-    assert -(-tiles // -(-tiles // g)) == g
+    assert _busiest_cu_tiles(tiles, g, cus) == -(-tiles // cus), (g, tiles, cus)
 
 
 def test_refuses_huge_grid(eng):
