@@ -73,8 +73,10 @@ struct ce_batch {
         return fail(CE_E_DEVICE, "stream: %s", hipGetErrorString(he));
       own_stream = true;
     }
+    // cleared before anything runs on the (non-blocking) stream, which does
+    // not wait for the null stream's memset
     if ((he = hipMalloc((void**)&counter, 2 * sizeof(uint64_t))) != hipSuccess ||
-        (he = hipMemset(counter, 0, 2 * sizeof(uint64_t))) != hipSuccess)
+        (he = hipMemset(counter, 0, 2 * sizeof(uint64_t))) != hipSuccess || (he = hipDeviceSynchronize()) != hipSuccess)
       return fail(CE_E_DEVICE, "counter: %s", hipGetErrorString(he));
     if ((he = hipEventCreate(&ev0)) != hipSuccess || (he = hipEventCreate(&ev1)) != hipSuccess)
       return fail(CE_E_DEVICE, "events: %s", hipGetErrorString(he));

@@ -280,6 +280,18 @@ struct ce_engine {
   // ---- results
   ce_run_stats stats{};
   bool stats_valid = false;
+  // The statistics of a run are worked out when first asked for, not inside
+  // the run: a run on the GPU alone would otherwise read every workgroup's
+  // end tick back from host memory the GPU just wrote (2048 cache lines'
+  // worth of misses for a 2048-workgroup grid) before returning.
+  bool stats_pending = false;
+  uint64_t pending_G = 0;
+  int64_t pending_t_end = 0;
+  void ensure_stats() {
+    if (!stats_pending) return;
+    stats_pending = false;
+    fill_stats(pending_G, pending_t_end);
+  }
   std::vector<ce_package_rec> trace;
   uint64_t gpu_pkgs_last = 0;
   uint32_t gpu_grid_last = 0;
@@ -937,6 +949,7 @@ struct ce_engine {
     const uint64_t G = granules();
     ++run_id;
     stats_valid = false;
+    stats_pending = false;
     trace.clear();
     hipError_t he;
 
@@ -1091,8 +1104,13 @@ struct ce_engine {
       } else if (gmax > pkgs_dev_cap) {
         if (!pkgs_dev.ensure(gmax * sizeof(PkgSlot)) || !pub_dev.ensure(gmax * sizeof(uint64_t)))
           return fail(CE_E_NOMEM, "run: package table");
-        if ((he = hipMemset(pub_dev.p, 0, gmax * sizeof(uint64_t))) != hipSuccess ||
-            (he = hipMemset(pkgs_dev.p, 0, gmax * sizeof(PkgSlot))) != hipSuccess)
+        // Cleared on the run's own stream, ahead of the kernel: a plain
+        // hipMemset goes to the null stream, which a non-blocking stream does
+        // not wait for, and could still be clearing the table while the
+        // kernel writes its first records.
+        static_assert(sizeof(PkgSlot) % sizeof(uint64_t) == 0, "package records are whole words");
+        if ((he = launch_zero_words(pub_dev.p, gmax, stream)) != hipSuccess ||
+            (he = launch_zero_words(pkgs_dev.p, gmax * (sizeof(PkgSlot) / sizeof(uint64_t)), stream)) != hipSuccess)
           return hip_fail(he, "run: package table");
         pkgs_dev_cap = (uint32_t)gmax;
       }
@@ -1270,8 +1288,9 @@ struct ce_engine {
     // merge outputs so each bound pointer holds the whole result
     st = merge_outputs(gpu_out);
     if (st != CE_OK) return st;
-    const int64_t t_end = now_ns();
-    fill_stats(G, t_end);
+    pending_t_end = now_ns();
+    pending_G = G;
+    stats_pending = true;
     return CE_OK;
   }
 
@@ -1475,7 +1494,10 @@ struct ce_engine {
     if ((he = hipHostGetDevicePointer((void**)&wg_end_dev, wg_end, 0)) != hipSuccess)
       return hip_fail(he, "create: device view of host memory");
     if ((he = hipMalloc((void**)&l2, sizeof(L2State))) != hipSuccess) return hip_fail(he, "create: queue state");
-    if ((he = hipMemset(l2, 0, sizeof(L2State))) != hipSuccess) return hip_fail(he, "create: queue state");
+    // the null stream's clear must be done before any run's kernel, which
+    // goes to a stream that does not wait for the null stream
+    if ((he = hipMemset(l2, 0, sizeof(L2State))) != hipSuccess || (he = hipDeviceSynchronize()) != hipSuccess)
+      return hip_fail(he, "create: queue state");
     // the allocation-free run's scratch on this GPU (a failure only disables that run)
     noalloc_err = noalloc_scratch_address(gpu, &noalloc_base);
     hp = host_payloads();
@@ -1564,6 +1586,7 @@ void ce_engine_destroy(ce_engine* e) { delete e; }
 
 ce_status ce_engine_use(ce_engine* e, uint32_t dev_mask, int gpu_ordinal, int host_threads) {
   if (!e) return CE_E_INVALID;
+  e->ensure_stats();  // the last run's statistics, before its settings change
   if (dev_mask == 0 || (dev_mask & ~(CE_DEV_GPU | CE_DEV_HOST)))
     return e->fail(CE_E_INVALID, "use: device mask 0x%x", dev_mask);
   if ((dev_mask & CE_DEV_GPU) && gpu_ordinal != e->gpu)
@@ -1577,6 +1600,7 @@ ce_status ce_engine_use(ce_engine* e, uint32_t dev_mask, int gpu_ordinal, int ho
 
 ce_status ce_engine_work_items(ce_engine* e, uint32_t ndim, const uint64_t* gws, const uint32_t* lws) {
   if (!e) return CE_E_INVALID;
+  e->ensure_stats();  // the last run's statistics, before its settings change
   if (ndim < 1 || ndim > 2 || !gws) return e->fail(CE_E_INVALID, "work_items: ndim must be 1 or 2");
   for (uint32_t d = 0; d < ndim; ++d)
     if (gws[d] == 0 || gws[d] > 0xFFFFFFFFull) return e->fail(CE_E_INVALID, "work_items: gws[%u] out of range", d);
@@ -1589,6 +1613,7 @@ ce_status ce_engine_work_items(ce_engine* e, uint32_t ndim, const uint64_t* gws,
 
 ce_status ce_engine_scheduler(ce_engine* e, const ce_sched_desc* s) {
   if (!e) return CE_E_INVALID;
+  e->ensure_stats();  // the last run's statistics, before its settings change
   if (!s) return e->fail(CE_E_INVALID, "scheduler: NULL descriptor");
   if (s->kind < CE_SCHED_STATIC || s->kind > CE_SCHED_HGUIDED)
     return e->fail(CE_E_INVALID, "scheduler: unknown kind %d", s->kind);
@@ -1602,12 +1627,14 @@ ce_status ce_engine_scheduler(ce_engine* e, const ce_sched_desc* s) {
 
 ce_status ce_engine_stream(ce_engine* e, void* hip_stream) {
   if (!e) return CE_E_INVALID;
+  e->ensure_stats();  // the last run's statistics, before its settings change
   e->stream = hip_stream ? (hipStream_t)hip_stream : e->own_stream;
   return CE_OK;
 }
 
 ce_status ce_engine_output_merge(ce_engine* e, int mode) {
   if (!e) return CE_E_INVALID;
+  e->ensure_stats();  // the last run's statistics, before its settings change
   if (mode != CE_MERGE_DMA && mode != CE_MERGE_GPU_GATHER) return e->fail(CE_E_INVALID, "output_merge: mode %d", mode);
   if (mode == CE_MERGE_DMA && !e->sdma.ready())
     return e->fail(CE_E_UNSUPPORTED, "output_merge: no DMA engine (%s)", e->sdma_why);
@@ -1617,6 +1644,7 @@ ce_status ce_engine_output_merge(ce_engine* e, int mode) {
 
 ce_status ce_engine_wait_bounds(ce_engine* e, double dispenser_s, double gather_s) {
   if (!e) return CE_E_INVALID;
+  e->ensure_stats();  // the last run's statistics, before its settings change
   if (!(dispenser_s >= 0.0 && dispenser_s <= 3600.0) || !(gather_s >= 0.0 && gather_s <= 3600.0))
     return e->fail(CE_E_INVALID, "wait_bounds: each bound must lie in [0, 3600] s");
   e->dispenser_wait_s = dispenser_s > 0.0 ? dispenser_s : (double)kDispenserWaitSeconds;
@@ -1626,6 +1654,7 @@ ce_status ce_engine_wait_bounds(ce_engine* e, double dispenser_s, double gather_
 
 ce_status ce_engine_gpu_workgroups(ce_engine* e, uint32_t workgroups) {
   if (!e) return CE_E_INVALID;
+  e->ensure_stats();  // the last run's statistics, before its settings change
   if (workgroups > (1u << 20)) return e->fail(CE_E_INVALID, "gpu_workgroups: %u is above 2^20", workgroups);
   e->grid_override = workgroups;
   return CE_OK;
@@ -1633,6 +1662,7 @@ ce_status ce_engine_gpu_workgroups(ce_engine* e, uint32_t workgroups) {
 
 ce_status ce_engine_kernel_events(ce_engine* e, void* start_event, void* stop_event) {
   if (!e) return CE_E_INVALID;
+  e->ensure_stats();  // the last run's statistics, before its settings change
   if ((start_event == nullptr) != (stop_event == nullptr))
     return e->fail(CE_E_INVALID, "kernel_events: give both events or neither");
   e->ev_start = (hipEvent_t)start_event;
@@ -1642,6 +1672,7 @@ ce_status ce_engine_kernel_events(ce_engine* e, void* start_event, void* stop_ev
 
 ce_status ce_program_kernel(ce_engine* e, int kernel_id, const void* params, size_t params_size) {
   if (!e) return CE_E_INVALID;
+  e->ensure_stats();  // the last run's statistics, before its settings change
   if (!params) return e->fail(CE_E_INVALID, "kernel: NULL params");
   switch (kernel_id) {
     case CE_KERNEL_ESCAPE: {
@@ -1703,6 +1734,7 @@ ce_status ce_program_kernel(ce_engine* e, int kernel_id, const void* params, siz
 
 ce_status ce_program_in(ce_engine* e, uint32_t slot, const void* host_ptr, const void* dev_ptr, size_t bytes) {
   if (!e) return CE_E_INVALID;
+  e->ensure_stats();  // the last run's statistics, before its settings change
   if (e->kernel_id == 0) return e->fail(CE_E_STATE, "in: bind a kernel first");
   if ((int)slot >= e->n_in_slots()) return e->fail(CE_E_INVALID, "in: kernel has no input slot %u", slot);
   if (!host_ptr && !dev_ptr) return e->fail(CE_E_INVALID, "in: slot %u needs a host or device pointer", slot);
@@ -1714,6 +1746,7 @@ ce_status ce_program_in(ce_engine* e, uint32_t slot, const void* host_ptr, const
 
 ce_status ce_program_out(ce_engine* e, uint32_t slot, void* host_ptr, void* dev_ptr, size_t bytes) {
   if (!e) return CE_E_INVALID;
+  e->ensure_stats();  // the last run's statistics, before its settings change
   if (e->kernel_id == 0) return e->fail(CE_E_STATE, "out: bind a kernel first");
   if ((int)slot >= e->n_out_slots()) return e->fail(CE_E_INVALID, "out: kernel has no output slot %u", slot);
   if (!host_ptr && !dev_ptr) return e->fail(CE_E_INVALID, "out: needs a host or device pointer");
@@ -1724,6 +1757,7 @@ ce_status ce_program_out(ce_engine* e, uint32_t slot, void* host_ptr, void* dev_
 
 ce_status ce_program_out_pattern(ce_engine* e, uint32_t outs, uint32_t items) {
   if (!e) return CE_E_INVALID;
+  e->ensure_stats();  // the last run's statistics, before its settings change
   if (outs == 0 || items == 0) return e->fail(CE_E_INVALID, "out_pattern: zero term");
   // the pattern is fixed by the payload: 1:(steps+1) for binomial, 1:1 otherwise
   const uint32_t want = e->kernel_id == CE_KERNEL_BINOMIAL ? e->bin.steps + 1 : 1;
@@ -1765,6 +1799,7 @@ ce_status ce_rt_code_object(const char* source, const char* entry, void* buf, si
 
 ce_status ce_program_source(ce_engine* e, const ce_rt_desc* d, char* log, size_t log_len) {
   if (!e) return CE_E_INVALID;
+  e->ensure_stats();  // the last run's statistics, before its settings change
   copy_log("", log, log_len);
   if (!d || !d->source || !d->entry) return e->fail(CE_E_INVALID, "source: NULL descriptor, source or entry");
   if (d->n_in > 2 || d->n_out < 1 || d->n_out > 2)
@@ -1806,6 +1841,7 @@ ce_status ce_program_source(ce_engine* e, const ce_rt_desc* d, char* log, size_t
 ce_status ce_engine_bare_run_source(ce_engine* e, uint64_t gws, uint32_t lws, const void* const* ins,
                                     void* const* outs, void* hip_stream, int sync) {
   if (!e) return CE_E_INVALID;
+  e->ensure_stats();  // the last run's statistics, before its settings change
   if (e->kernel_id != CE_KERNEL_RUNTIME || !e->rt_fn_bare) return e->fail(CE_E_STATE, "bare: no runtime payload bound");
   if (gws == 0 || lws == 0 || !outs) return e->fail(CE_E_INVALID, "bare: empty space or no outputs");
   KernelArgs a{};
@@ -1856,8 +1892,10 @@ ce_status ce_engine_run(ce_engine* e) {
   }
 }
 
-ce_status ce_engine_stats(const ce_engine* e, ce_run_stats* out) {
-  if (!e || !out) return CE_E_INVALID;
+ce_status ce_engine_stats(const ce_engine* ce, ce_run_stats* out) {
+  if (!ce || !out) return CE_E_INVALID;
+  ce_engine* e = const_cast<ce_engine*>(ce);
+  e->ensure_stats();
   if (!e->stats_valid) return CE_E_STATE;
   *out = e->stats;
   return CE_OK;
@@ -1866,6 +1904,7 @@ ce_status ce_engine_stats(const ce_engine* e, ce_run_stats* out) {
 size_t ce_engine_trace(const ce_engine* ce, ce_package_rec* buf, size_t cap) {
   if (!ce) return 0;
   ce_engine* e = const_cast<ce_engine*>(ce);
+  e->ensure_stats();
   if (!e->stats_valid) return 0;
   size_t n = 0;
   try {

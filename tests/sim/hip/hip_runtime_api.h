@@ -23,6 +23,7 @@ hipError_t hipDeviceGetAttribute(int*, hipDeviceAttribute_t, int);
 hipError_t hipStreamCreateWithFlags(hipStream_t*, unsigned);
 hipError_t hipStreamDestroy(hipStream_t);
 hipError_t hipStreamSynchronize(hipStream_t);
+hipError_t hipDeviceSynchronize();
 hipError_t hipMalloc(void**, size_t);
 hipError_t hipFree(void*);
 hipError_t hipHostMalloc(void**, size_t, unsigned);

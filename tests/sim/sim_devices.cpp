@@ -99,6 +99,10 @@ hipError_t hipHostMalloc(void** p, size_t n, unsigned) { *p = calloc(1, n ? n : 
 hipError_t hipHostFree(void* p) { free(p); return hipSuccess; }
 hipError_t hipHostGetDevicePointer(void** d, void* h, unsigned) { *d = h; return hipSuccess; }
 hipError_t hipMemset(void* p, int v, size_t n) { memset(p, v, n); return hipSuccess; }
+hipError_t hipDeviceSynchronize() {
+  join_gpu();
+  return hipSuccess;
+}
 hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) { join_gpu(); memcpy(d, s, n); return hipSuccess; }
 hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t st) {
   if (on_gpu_stream(st)) join_gpu();  // stream order: after the kernel
