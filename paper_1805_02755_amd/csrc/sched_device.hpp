@@ -165,8 +165,6 @@ struct Cursor {  // zero-initialised at the start of a run
   uint64_t base, g0, g1;
   uint64_t cur_t;  // ticket of the tile being run
   uint32_t p, nt;  // nt == 0: no package yet
-  uint32_t fresh;  // tot_seen is still the launch's own count (first ticket)
-  uint32_t pad;
 };
 
 // After a tile: if it held its package's last ticket, stamp the package end.
@@ -200,13 +198,8 @@ __device__ bool next_tile(const T& pay, const SchedArgs& s, Cursor& c, uint32_t*
   }
   const uint64_t t = c.t_next++;
   if (s.pre_only && t >= s.pre_nt) return false;
-  // The count passed with the launch is current when the workgroups start:
-  // with its first ticket inside the published tiles, only the designated
-  // claimer needs to read the shared count again.
-  const bool known = c.fresh && t < c.tot_seen && t + s.lookahead != c.tot_seen;
-  c.fresh = 0;
   uint64_t spins = 0, t0 = 0;
-  while (!s.pre_only && !known && t + s.lookahead >= c.tot_seen) {
+  while (!s.pre_only && t + s.lookahead >= c.tot_seen) {
     // The published tile count and the "no more packages" flag share one
     // word, so a workgroup never pairs a stale count with a fresh flag (which
     // would make it leave with a ticket that did get published).
@@ -485,20 +478,46 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
   const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) == 0;
   const bool lane0 = threadIdx.x == 0;
   pay.load_constants();
+  // Direct phase. The tickets of the package the host claimed before the
+  // launch need nothing from the dispenser: workgroup w runs them straight
+  // from the arguments (w, w + n, w + 2n ... with round-robin tickets; only
+  // its first one with atomic tickets), with no cursor and no barrier of the
+  // dispenser's. Only the designated claimer's ticket (lookahead before the
+  // package's end, when more packages may follow) goes through the cursor,
+  // so that the claim still overlaps the other workgroups' tiles.
+  const bool computing = blockIdx.x >= s.gather_wgs;
+  const uint32_t n_comp = gridDim.x - s.gather_wgs;
+  const uint64_t t_first = computing ? blockIdx.x - s.gather_wgs : 0;
+  uint64_t t_dir = t_first;  // first ticket the direct phase did not run
+  if (computing && s.pre_nt) {
+    if (t_first == 0 && lane0) {
+      // the pre-claimed package starts with the first workgroup
+      const uint64_t tp = now_tick();
+      dev_store(&s.pkgs[0].t_claim, tp);
+      sys_store(&s.l1->gpu_t_first, tp);
+    }
+    while (t_dir < s.pre_nt && (s.pre_only || t_dir + s.lookahead != s.pre_nt)) {
+      pay.run(s.pre_g0, s.pre_g1, (uint32_t)t_dir);
+      if (t_dir + 1 == s.pre_nt && lane0) dev_store(&s.pkgs[0].t_end, now_tick());  // its last ticket
+      if (!s.stride) {
+        t_dir = ~0ull;  // later tickets come from the counter
+        break;
+      }
+      t_dir += n_comp;
+    }
+  }
   if (s.wg_end) {
-    // Fast exit: the GPU's whole share is the package the host claimed
-    // before the launch and workgroup w runs its tickets w, w + n, w + 2n
-    // ...: no claim, no cursor and no barrier of the dispenser's. Each
-    // workgroup leaves the tick at which it ended; the host takes the GPU's
-    // end from them and writes the package's trace record itself.
-    if (blockIdx.x == 0 && lane0) sys_store(&s.l1->gpu_t_first, now_tick());
-    for (uint32_t t = blockIdx.x; t < s.pre_nt; t += gridDim.x) pay.run(s.pre_g0, s.pre_g1, t);
+    // Fast exit: the direct phase ran the GPU's whole share. Each workgroup
+    // leaves the tick at which it ended; nothing is counted or reset, and the
+    // host takes the GPU's end from these ticks and writes the package's
+    // trace record itself.
     __syncthreads();  // every wave's tiles are done
     if (lane0) sys_store(&s.wg_end[blockIdx.x], now_tick());
     return;
   }
   // The scheduler arguments are read from LDS inside the tile loop: kept in
-  // scalar registers across the payload they would crowd out its own.
+  // scalar registers across the payload they would crowd out its own. The
+  // barrier also ends the direct tiles' use of the payload's own LDS.
   __shared__ SchedArgs sh_args;
   if (threadIdx.x == 0) sh_args = s;
   __syncthreads();
@@ -510,16 +529,13 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
   if (wave0) {
     if (lane0) {
       c = Cursor{};
-      c.t_next = blockIdx.x - s.gather_wgs;  // the first ticket needs no atomic
-      c.t_end = c.t_next + 1;
-      c.tot_seen = s.pre_nt;
-      c.fresh = 1;
-      if (s.pre_nt && c.t_next == 0) {
-        // the pre-claimed package starts with the first workgroup
-        const uint64_t tp = now_tick();
-        dev_store(&s.pkgs[0].t_claim, tp);
-        sys_store(&s.l1->gpu_t_first, tp);
+      if (t_dir == ~0ull) {
+        c.t_next = c.t_end = 1;  // the next ticket comes from the counter
+      } else {
+        c.t_next = t_dir;  // the first ticket needs no atomic
+        c.t_end = t_dir + 1;
       }
+      c.tot_seen = s.pre_nt;
     }
   }
   uint32_t prev_p = 0xFFFFFFFFu;
