@@ -484,10 +484,14 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
   // its first one with atomic tickets), with no cursor and no barrier of the
   // dispenser's. Only the designated claimer's ticket (lookahead before the
   // package's end, when more packages may follow) goes through the cursor,
-  // so that the claim still overlaps the other workgroups' tiles.
+  // so that the claim still overlaps the other workgroups' tiles; when the
+  // package does not fill the grid, a workgroup left without a ticket claims
+  // at once anyway, and that ticket runs directly too (a claim before it
+  // would delay a tile that may be among the longest).
   const bool computing = blockIdx.x >= s.gather_wgs;
   const uint32_t n_comp = gridDim.x - s.gather_wgs;
   const uint64_t t_first = computing ? blockIdx.x - s.gather_wgs : 0;
+  const bool claim_free = s.pre_only || s.pre_nt < n_comp;
   uint64_t t_dir = t_first;  // first ticket the direct phase did not run
   if (computing && s.pre_nt) {
     if (t_first == 0 && lane0) {
@@ -496,7 +500,7 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
       dev_store(&s.pkgs[0].t_claim, tp);
       sys_store(&s.l1->gpu_t_first, tp);
     }
-    while (t_dir < s.pre_nt && (s.pre_only || t_dir + s.lookahead != s.pre_nt)) {
+    while (t_dir < s.pre_nt && (claim_free || t_dir + s.lookahead != s.pre_nt)) {
       pay.run(s.pre_g0, s.pre_g1, (uint32_t)t_dir);
       if (t_dir + 1 == s.pre_nt && lane0) dev_store(&s.pkgs[0].t_end, now_tick());  // its last ticket
       if (!s.stride) {
