@@ -169,14 +169,36 @@ struct SchedArgs {
   uint32_t gather_wgs;  // workgroups 0 .. gather_wgs-1 only gather
   uint32_t ring_cap;    // entries in the ring
   uint64_t gather_wait_ticks;  // longest wait for the host's next finished tile
-  // Fast exit (pre_only with one ticket sequence per workgroup and no
-  // gatherers): no workgroup counts itself out; each stores the tick at
-  // which it left into wg_end[blockIdx.x] (host-coherent) and the host takes
-  // the GPU's end from them after the kernel. Null: the regular exit.
+  // Light exit (no gather workgroups): no workgroup counts itself out or
+  // resets anything; each stores the tick at which it left into
+  // wg_end[blockIdx.x] (host-coherent) and the host takes the GPU's end from
+  // them after the kernel. This run's queue state is left as it is: the next
+  // run uses the other buffer. Null: the regular exit (count out; the last
+  // workgroup publishes the summary and resets the state).
   uint64_t* wg_end;
+  // The other of the two queue-state buffers and its publication words, the
+  // next run's: cleared by this run's workgroups as they start, while
+  // nothing uses them (null: single-buffered, as in the allocation-free run,
+  // which clears its state before each run).
+  L2State* l2_next;
+  uint64_t* pub_next;
+  uint32_t pub_next_words;
+  uint32_t pad_next;
 };
 
 constexpr uint32_t kFastExitMaxWgs = 16384;  // entries of the host's wg_end array
+
+// Arguments of the direct kernel, for a run whose whole GPU share is the
+// package the host claimed before the launch, dealt round-robin: no
+// dispenser at all, so nothing of it is passed.
+struct DirectArgs {
+  uint64_t g0, g1;      // the package
+  uint32_t ntiles;      // its tiles
+  uint32_t pad;
+  L1State* l1;          // device address of the dispenser: the first workgroup stamps the GPU's start
+  PkgSlot* pkgs;        // ... and the package's claim time into its trace record
+  uint64_t* wg_end;     // each workgroup's end tick (host-coherent)
+};
 
 // HGuided package size (section 5.3 equation), integer only. Callers keep
 // G_r < 2^40 and P <= 2^20 so the products fit in 64 bits.

@@ -268,6 +268,7 @@ struct ce_engine {
   void* rt_module = nullptr;
   void* rt_fn_persistent = nullptr;
   void* rt_fn_bare = nullptr;
+  void* rt_fn_direct = nullptr;
   ce_rt_host_fn rt_host = nullptr;
   uint32_t rt_n_in = 0, rt_n_out = 0, rt_item_bytes = 0;
   uint64_t rt_in_bytes[2] = {0, 0};
@@ -300,6 +301,12 @@ struct ce_engine {
   uint64_t* wg_end = nullptr;      // host-coherent, kFastExitMaxWgs entries (fast exit)
   uint64_t* wg_end_dev = nullptr;
   bool fast_exit = false;          // this run's kernel uses the fast exit
+  bool light_exit = false;         // its workgroups leave without counting out
+  // Two queue-state buffers (and two halves of the publication words) taken
+  // in turn by successive GPU runs: a run's kernel clears the other one for
+  // the next run, so no workgroup resets anything as it leaves.
+  uint64_t gpu_seq = 0;            // GPU runs launched from the double buffers
+  L2State* l2_last = nullptr;      // the queue state of the last run
   int64_t ph_launched = 0, ph_host_done = 0, ph_gpu_seen = 0, ph_synced = 0, ph_copies = 0;  // phase ends (ns)
   uint64_t fast_g0 = 0, fast_g1 = 0;  // its one package
   double dispenser_wait_s = (double)kDispenserWaitSeconds;  // bounds on the kernel's waits
@@ -1005,6 +1012,7 @@ struct ce_engine {
       kargs.rt_item_bytes = rt_item_bytes;
       kargs.rt_fn_persistent = rt_fn_persistent;
       kargs.rt_fn_bare = rt_fn_bare;
+      kargs.rt_fn_direct = rt_fn_direct;
     }
 
     // host-side pointers
@@ -1102,23 +1110,29 @@ struct ce_engine {
         if ((he = launch_zero_words(base, sizeof(L2State) / sizeof(uint64_t) + gmax, stream)) != hipSuccess)
           return hip_fail(he, "run_noalloc: clearing the scratch");
       } else if (gmax > pkgs_dev_cap) {
-        if (!pkgs_dev.ensure(gmax * sizeof(PkgSlot)) || !pub_dev.ensure(gmax * sizeof(uint64_t)))
+        if (!pkgs_dev.ensure(gmax * sizeof(PkgSlot)) || !pub_dev.ensure(2 * gmax * sizeof(uint64_t)))
           return fail(CE_E_NOMEM, "run: package table");
         // Cleared on the run's own stream, ahead of the kernel: a plain
         // hipMemset goes to the null stream, which a non-blocking stream does
         // not wait for, and could still be clearing the table while the
         // kernel writes its first records.
         static_assert(sizeof(PkgSlot) % sizeof(uint64_t) == 0, "package records are whole words");
-        if ((he = launch_zero_words(pub_dev.p, gmax, stream)) != hipSuccess ||
+        if ((he = launch_zero_words(pub_dev.p, 2 * gmax, stream)) != hipSuccess ||
             (he = launch_zero_words(pkgs_dev.p, gmax * (sizeof(PkgSlot) / sizeof(uint64_t)), stream)) != hipSuccess)
           return hip_fail(he, "run: package table");
         pkgs_dev_cap = (uint32_t)gmax;
       }
       if (!noalloc) {
+        const uint32_t b = (uint32_t)(gpu_seq & 1);
         gs.pkgs = (PkgSlot*)pkgs_dev.p;
-        gs.pub = (uint64_t*)pub_dev.p;
         gs.max_pkgs = pkgs_dev_cap;
+        gs.l2 = l2 + b;
+        gs.pub = (uint64_t*)pub_dev.p + (size_t)b * pkgs_dev_cap;
+        gs.l2_next = l2 + (b ^ 1u);
+        gs.pub_next = (uint64_t*)pub_dev.p + (size_t)(b ^ 1u) * pkgs_dev_cap;
+        gs.pub_next_words = pkgs_dev_cap;
       }
+      l2_last = gs.l2;
       trace_pkgs = gs.pkgs;
       trace_pkgs_cap = gs.max_pkgs;
       // Claim the next package while half a round of tiles is still to be
@@ -1204,6 +1218,7 @@ struct ce_engine {
 
     t0_ns = now_ns();
     fast_exit = false;
+    light_exit = false;
     // Once the clock mapping's anchor is old, the host watches for the
     // GPU's first workgroup to stamp its start and re-anchors on it (the
     // host's own work then starts a few microseconds late).
@@ -1214,14 +1229,40 @@ struct ce_engine {
       // workgroup walks its own tickets: no claim, no shared counter, so no
       // workgroup needs to count out (the overhead of a single-device run
       // is then that of a plain launch plus the dispenser's first ticket).
-      fast_exit = gs.pre_only && gs.stride && !gather && grid <= kFastExitMaxWgs;
+      // Without gather workgroups every workgroup leaves on its own (the
+      // next run's state is cleared as the kernel starts), and with the
+      // whole share claimed before the launch the kernel needs no dispenser.
+      light_exit = !gather && grid <= kFastExitMaxWgs;
+      fast_exit = light_exit && gs.pre_only && gs.stride;
+      // The fast path never touches its queue state, which therefore stays
+      // clear for the next run: the buffers keep their roles, and nothing is
+      // cleared either.
+      if (fast_exit) {
+        gs.l2_next = nullptr;
+        gs.pub_next = nullptr;
+        gs.pub_next_words = 0;
+      }
       anchor_watch = clock_ok && gs.pre_nt && (double)t0_ns - anchor_ns > kReanchorNs;
       if (anchor_watch) __atomic_store_n(&l1->gpu_t_first, 0, __ATOMIC_RELAXED);  // before the doorbell
-      gs.wg_end = fast_exit ? wg_end_dev : nullptr;
+      gs.wg_end = light_exit ? wg_end_dev : nullptr;
       fast_g0 = gs.pre_g0;
       fast_g1 = gs.pre_g1;
       if (ev_start && (he = hipEventRecord(ev_start, stream)) != hipSuccess) return hip_fail(he, "run: event");
-      if ((he = launch_persistent(kargs, gs, grid, stream)) != hipSuccess) return hip_fail(he, "run: kernel launch");
+      if (fast_exit) {
+        // the direct kernel: no dispenser, nothing of the queue state touched
+        DirectArgs da{};
+        da.g0 = gs.pre_g0;
+        da.g1 = gs.pre_g1;
+        da.ntiles = gs.pre_nt;
+        da.l1 = gs.l1;
+        da.pkgs = gs.pkgs;
+        da.wg_end = wg_end_dev;
+        he = launch_direct(kargs, da, grid, stream);
+      } else {
+        he = launch_persistent(kargs, gs, grid, stream);
+      }
+      if (he != hipSuccess) return hip_fail(he, "run: kernel launch");
+      if (!noalloc && !fast_exit) ++gpu_seq;  // the buffers' roles swap for the next run
       if (ev_stop && (he = hipEventRecord(ev_stop, stream)) != hipSuccess) return hip_fail(he, "run: event");
     }
     ph_launched = use_gpu() ? now_ns() : 0;
@@ -1264,10 +1305,11 @@ struct ce_engine {
       if ((he = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(he, "run: kernel");
       ph_synced = now_ns();
     } else if (use_gpu()) {
-      // the last workgroup out writes the done word before the kernel ends
       if ((he = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(he, "run: kernel");
       ph_synced = now_ns();
-      if (!done_is(__atomic_load_n(&l1->gpu_done, __ATOMIC_ACQUIRE), run_id))
+      // with the regular exit the last workgroup out writes the done word
+      // before the kernel ends
+      if (!light_exit && !done_is(__atomic_load_n(&l1->gpu_done, __ATOMIC_ACQUIRE), run_id))
         return fail(CE_E_TIMEOUT, "run: GPU did not report completion");
       if (gather) memset(ring_buf.p, 0, ring_count.load() * sizeof(uint64_t));  // ready for the next run
       if (__atomic_load_n(&l1->gpu_flags, __ATOMIC_ACQUIRE))
@@ -1390,17 +1432,29 @@ struct ce_engine {
       uint64_t gr = __atomic_load_n(&l1->gpu_granules, __ATOMIC_ACQUIRE);
       const uint64_t tf = __atomic_load_n(&l1->gpu_t_first, __ATOMIC_ACQUIRE);
       uint64_t tl = __atomic_load_n(&l1->gpu_t_last, __ATOMIC_ACQUIRE);
-      if (fast_exit) {
-        // the one pre-claimed package; the GPU ended when its last workgroup left
-        np = 1;
-        gr = fast_g1 - fast_g0;
+      uint64_t tf_l = tf;
+      if (light_exit) {
+        // no last workgroup summarised the run: the GPU ended when its last
+        // workgroup left, and the packages the kernel claimed are counted in
+        // its queue state (read back only here, when statistics are asked for)
+        const bool pre = fast_g1 > fast_g0;
         tl = 0;
         for (uint32_t i = 0; i < gpu_grid_last; ++i) tl = std::max(tl, __atomic_load_n(&wg_end[i], __ATOMIC_ACQUIRE));
+        np = pre ? 1 : 0;
+        gr = fast_g1 - fast_g0;
+        if (!fast_exit) {
+          L2State q;
+          if (hipMemcpy(&q, l2_last, sizeof q, hipMemcpyDeviceToHost) == hipSuccess) {
+            np += q.n_pkgs;
+            gr += q.granules;
+            if (!pre) tf_l = q.t_first;
+          }
+        }
       }
       s.packages[gi] = np;
       s.granules[gi] = gr;
       s.t_device[gi] = np ? std::max(0.0, tick_to_host_s(tl)) : 0.0;
-      s.t_gpu_kernel = np ? (double)(tl - tf) / (double)wallclock_hz : 0.0;
+      s.t_gpu_kernel = np ? (double)(tl - tf_l) / (double)wallclock_hz : 0.0;
       const uint64_t tg = __atomic_load_n(&l1->gpu_t_gather, __ATOMIC_ACQUIRE);
       s.t_gather = (gather && tg) ? std::max(0.0, tick_to_host_s(tg)) : 0.0;
       s.gathered_bytes = gather ? __atomic_load_n(&l1->gathered, __ATOMIC_ACQUIRE) : 0;
@@ -1446,6 +1500,12 @@ struct ce_engine {
     } else if (gi >= 0 && gpu_pkgs_last) {
       std::vector<PkgSlot> v(std::min<uint64_t>(gpu_pkgs_last, trace_pkgs_cap));
       if (hipMemcpy(v.data(), trace_pkgs, v.size() * sizeof(PkgSlot), hipMemcpyDeviceToHost) == hipSuccess) {
+        // with the light exit no last workgroup filled in the range of the
+        // package claimed before the launch: the host knows it
+        if (light_exit && fast_g1 > fast_g0 && !v.empty()) {
+          v[0].g0 = fast_g0;
+          v[0].g1 = fast_g1;
+        }
         for (auto& p : v)
           trace.push_back(ce_package_rec{(uint32_t)gi, 0, p.g0, p.g1, tick_to_host_s(p.t_claim), tick_to_host_s(p.t_end)});
       }
@@ -1493,10 +1553,10 @@ struct ce_engine {
     memset(wg_end, 0, kFastExitMaxWgs * sizeof(uint64_t));
     if ((he = hipHostGetDevicePointer((void**)&wg_end_dev, wg_end, 0)) != hipSuccess)
       return hip_fail(he, "create: device view of host memory");
-    if ((he = hipMalloc((void**)&l2, sizeof(L2State))) != hipSuccess) return hip_fail(he, "create: queue state");
+    if ((he = hipMalloc((void**)&l2, 2 * sizeof(L2State))) != hipSuccess) return hip_fail(he, "create: queue state");
     // the null stream's clear must be done before any run's kernel, which
     // goes to a stream that does not wait for the null stream
-    if ((he = hipMemset(l2, 0, sizeof(L2State))) != hipSuccess || (he = hipDeviceSynchronize()) != hipSuccess)
+    if ((he = hipMemset(l2, 0, 2 * sizeof(L2State))) != hipSuccess || (he = hipDeviceSynchronize()) != hipSuccess)
       return hip_fail(he, "create: queue state");
     // the allocation-free run's scratch on this GPU (a failure only disables that run)
     noalloc_err = noalloc_scratch_address(gpu, &noalloc_base);
@@ -1778,8 +1838,8 @@ void copy_log(const std::string& text, char* log, size_t log_len) {
 }  // namespace
 
 ce_status ce_rt_compile_check(const char* source, const char* entry, char* log, size_t log_len) {
-  std::string code, lp, lb, text;
-  const int rc = rt_compile(source, entry, &code, &lp, &lb, &text);
+  std::string code, lp, lb, ld, text;
+  const int rc = rt_compile(source, entry, &code, &lp, &lb, &ld, &text);
   copy_log(text, log, log_len);
   return rc == 0 ? CE_OK : (rc == -1 ? CE_E_INVALID : CE_E_DEVICE);
 }
@@ -1788,8 +1848,8 @@ ce_status ce_rt_code_object(const char* source, const char* entry, void* buf, si
                             size_t log_len) {
   if (!size) return CE_E_INVALID;
   *size = 0;
-  std::string code, lp, lb, text;
-  const int rc = rt_compile(source, entry, &code, &lp, &lb, &text);
+  std::string code, lp, lb, ld, text;
+  const int rc = rt_compile(source, entry, &code, &lp, &lb, &ld, &text);
   copy_log(text, log, log_len);
   if (rc != 0) return rc == -1 ? CE_E_INVALID : CE_E_DEVICE;
   *size = code.size();
@@ -1815,9 +1875,10 @@ ce_status ce_program_source(ce_engine* e, const ce_rt_desc* d, char* log, size_t
   for (auto& b : e->in) b = Binding{};
   for (auto& b : e->out) b = Binding{};
   rt_release(e->rt_module);
-  e->rt_module = e->rt_fn_persistent = e->rt_fn_bare = nullptr;
+  e->rt_module = e->rt_fn_persistent = e->rt_fn_bare = e->rt_fn_direct = nullptr;
   std::string text;
-  const int rc = rt_build(d->source, d->entry, &e->rt_module, &e->rt_fn_persistent, &e->rt_fn_bare, &text);
+  const int rc =
+      rt_build(d->source, d->entry, &e->rt_module, &e->rt_fn_persistent, &e->rt_fn_bare, &e->rt_fn_direct, &text);
   copy_log(text, log, log_len);
   if (rc != 0) {
     if (rc == -1) return e->fail(CE_E_INVALID, "source: the payload did not compile (see the log)");
@@ -1860,6 +1921,7 @@ ce_status ce_engine_bare_run_source(ce_engine* e, uint64_t gws, uint32_t lws, co
   a.rt_item_bytes = e->rt_item_bytes;
   a.rt_fn_persistent = e->rt_fn_persistent;
   a.rt_fn_bare = e->rt_fn_bare;
+  a.rt_fn_direct = e->rt_fn_direct;
   hipStream_t st = (hipStream_t)hip_stream;
   hipError_t he;
   if ((he = launch_bare(a, st)) != hipSuccess) return e->hip_fail(he, "bare: launch");

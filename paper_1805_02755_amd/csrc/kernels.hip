@@ -140,6 +140,37 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t g
   return hipGetLastError();
 }
 
+hipError_t launch_direct(const KernelArgs& a, const DirectArgs& d, uint32_t grid, hipStream_t st) {
+  const dim3 g(grid), b(kBlockThreads);
+  switch (a.kernel_id) {
+    case CE_KERNEL_ESCAPE: hipLaunchKernelGGL(k_direct<EscapeTile>, g, b, 0, st, make_escape(a), d); break;
+    case CE_KERNEL_BLUR5: hipLaunchKernelGGL(k_direct<Blur5Tile>, g, b, 0, st, make_blur(a), d); break;
+    case CE_KERNEL_NBODY_ACC:
+      if (a.strict)
+        hipLaunchKernelGGL(k_direct<NbodyTile<true>>, g, b, 0, st, make_nbody<true>(a), d);
+      else
+        hipLaunchKernelGGL(k_direct<NbodyTile<false>>, g, b, 0, st, make_nbody<false>(a), d);
+      break;
+    case CE_KERNEL_NBODY_STEP:
+      if (a.strict)
+        hipLaunchKernelGGL(k_direct<NbodyStepTile<true>>, g, b, 0, st, make_nbody_step<true>(a), d);
+      else
+        hipLaunchKernelGGL(k_direct<NbodyStepTile<false>>, g, b, 0, st, make_nbody_step<false>(a), d);
+      break;
+    case CE_KERNEL_BINOMIAL: hipLaunchKernelGGL(k_direct<BinomialTile>, g, b, 0, st, make_binomial(a), d); break;
+    case CE_KERNEL_RUNTIME: {
+      if (!a.rt_fn_direct) return hipErrorInvalidValue;
+      RtTile pay = make_rt(a);
+      DirectArgs da = d;
+      void* params[] = {&pay, &da};
+      return hipModuleLaunchKernel((hipFunction_t)a.rt_fn_direct, grid, 1, 1, kBlockThreads, 1, 1, 0, st, params,
+                                   nullptr);
+    }
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_bare(const KernelArgs& a, hipStream_t st) {
   const uint64_t G = gpu_granules(a);
   const uint32_t tiles = gpu_tiles(a, 0, G);

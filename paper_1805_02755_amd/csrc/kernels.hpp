@@ -32,6 +32,7 @@ struct KernelArgs {
   uint32_t rt_item_bytes;
   void* rt_fn_persistent;
   void* rt_fn_bare;
+  void* rt_fn_direct;
 };
 
 // Granules of the index space and tiles of a package, as the GPU cuts them.
@@ -41,14 +42,15 @@ uint32_t gpu_tiles(const KernelArgs& a, uint64_t g0, uint64_t g1);
 // Resident workgroups per CU of the persistent kernel for this payload.
 hipError_t persistent_blocks_per_cu(const KernelArgs& a, int* blocks);
 hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t grid, hipStream_t st);
+hipError_t launch_direct(const KernelArgs& a, const DirectArgs& d, uint32_t grid, hipStream_t st);
 hipError_t launch_bare(const KernelArgs& a, hipStream_t st);
 // Runtime payloads (rt_module.cpp): compile the caller's work-item source
 // for gfx950 (no GPU needed), and compile and load it on the current device.
 // 0 on success; otherwise negative with the compiler's log.
 int rt_compile(const char* source, const char* entry, std::string* code, std::string* lowered_persistent,
-               std::string* lowered_bare, std::string* log);
+               std::string* lowered_bare, std::string* lowered_direct, std::string* log);
 int rt_build(const char* source, const char* entry, void** module, void** fn_persistent, void** fn_bare,
-             std::string* log);
+             void** fn_direct, std::string* log);
 void rt_release(void* module);
 // Allocation-free runs (noalloc.hip): the address of this device's static
 // scratch array (kNoallocScratchBytes), looked up once per device; and a

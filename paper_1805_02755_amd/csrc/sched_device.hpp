@@ -510,14 +510,17 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
       t_dir += n_comp;
     }
   }
-  if (s.wg_end) {
-    // Fast exit: the direct phase ran the GPU's whole share. Each workgroup
-    // leaves the tick at which it ended; nothing is counted or reset, and the
-    // host takes the GPU's end from these ticks and writes the package's
-    // trace record itself.
-    __syncthreads();  // every wave's tiles are done
-    if (lane0) sys_store(&s.wg_end[blockIdx.x], now_tick());
-    return;
+  // The next run's queue state (the other buffer) is cleared now, while
+  // nothing uses it, so that no workgroup has to reset anything as it
+  // leaves. Agent-scope stores: they reach memory, where the next run's
+  // atomics read them, whichever XCD runs them. (After the direct tiles, so
+  // that reading these arguments does not hold up the kernel's start.)
+  if (s.l2_next) {
+    constexpr uint32_t kStateWords = sizeof(L2State) / sizeof(uint64_t);
+    uint64_t* const st = reinterpret_cast<uint64_t*>(s.l2_next);
+    const uint32_t words = kStateWords + s.pub_next_words;
+    for (uint32_t i = blockIdx.x * kBlockThreads + threadIdx.x; i < words; i += gridDim.x * kBlockThreads)
+      dev_store(i < kStateWords ? &st[i] : &s.pub_next[i - kStateWords], (uint64_t)0);
   }
   // The scheduler arguments are read from LDS inside the tile loop: kept in
   // scalar registers across the payload they would crowd out its own. The
@@ -613,13 +616,40 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
   }
   if (wave0) {
     if (lane0) {
-      // the last computing workgroup out marks the end of the GPU's work
-      // (gather workgroups may still be copying the host's output)
-      if (sa.gather_wgs && dev_add(&sa.l2->exit_compute, 1u) + 1 == gridDim.x - sa.gather_wgs)
-        dev_store(&sa.l2->t_last, now_tick());
-      leave(sa);
+      if (sa.wg_end) {
+        // light exit: the loop's last barrier has seen every wave's tiles
+        // done; the next run's state is already clear
+        sys_store(&sa.wg_end[blockIdx.x], now_tick());
+      } else {
+        // the last computing workgroup out marks the end of the GPU's work
+        // (gather workgroups may still be copying the host's output)
+        if (sa.gather_wgs && dev_add(&sa.l2->exit_compute, 1u) + 1 == gridDim.x - sa.gather_wgs)
+          dev_store(&sa.l2->t_last, now_tick());
+        leave(sa);
+      }
     }
   }
+}
+
+// Direct kernel: the GPU's whole share is the package the host claimed
+// before the launch (a run on the GPU alone, or a Static plan that gives it
+// one package) and its tiles cost alike, so workgroup w runs tickets w,
+// w + n, w + 2n ... straight from the arguments. Each workgroup leaves the
+// tick at which it ended; the host takes the GPU's end from these ticks and
+// writes the package's trace record itself. Kept apart from the persistent
+// kernel so that it carries none of the dispenser's code or registers.
+template <class T>
+__global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_direct(T pay, DirectArgs d) {
+  const bool lane0 = threadIdx.x == 0;
+  pay.load_constants();
+  if (blockIdx.x == 0 && lane0) {
+    const uint64_t tp = now_tick();
+    dev_store(&d.pkgs[0].t_claim, tp);
+    sys_store(&d.l1->gpu_t_first, tp);
+  }
+  for (uint32_t t = blockIdx.x; t < d.ntiles; t += gridDim.x) pay.run(d.g0, d.g1, t);
+  __syncthreads();  // every wave's tiles are done
+  if (lane0) sys_store(&d.wg_end[blockIdx.x], now_tick());
 }
 
 template <class T>

@@ -261,6 +261,11 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, 
   join_gpu();
   g_gpu_stream.store((uintptr_t)st);
   g_gpu = std::thread([a, s] {
+    // the next run's queue state, cleared as the real kernel clears it
+    if (s.l2_next) {
+      memset(s.l2_next, 0, sizeof(L2State));
+      memset(s.pub_next, 0, (size_t)s.pub_next_words * sizeof(uint64_t));
+    }
     uint64_t np = 0, gr = 0, stn = s.st_first, t_first = 0, t_last = 0;
     bool pre = s.pre_nt != 0;  // the package the host claimed for the GPU before the launch
     for (;;) {
@@ -360,7 +365,13 @@ hipError_t launch_persistent(const KernelArgs& a, const SchedArgs& s, uint32_t, 
     __atomic_store_n(&s.l1->gpu_granules, gr, __ATOMIC_RELEASE);
     __atomic_store_n(&s.l1->gpu_packages, np, __ATOMIC_RELEASE);
     if (s.wg_end) {
-      __atomic_store_n(&s.wg_end[0], t_last, __ATOMIC_RELEASE);  // fast exit: one workgroup's end
+      // light exit: one workgroup's end; the packages the kernel claimed
+      // (beyond the one claimed before the launch) in its queue state
+      __atomic_store_n(&s.wg_end[0], t_last, __ATOMIC_RELEASE);
+      const uint64_t pre = s.pre_nt ? 1 : 0;
+      s.l2->n_pkgs = (uint32_t)(np - std::min(np, pre));
+      s.l2->granules = gr - (np && pre ? s.pre_g1 - s.pre_g0 : 0);
+      s.l2->t_first = t_first;
     }
     __atomic_store_n(&s.l1->gpu_done, done_word(s.run_id, (uint64_t)(now_ns() / 10)), __ATOMIC_RELEASE);
   });
@@ -384,6 +395,26 @@ hipError_t launch_stream_copy(void* dst, const void* src, uint64_t n16, hipStrea
   return hipSuccess;
 }
 
+// The direct kernel: the one package claimed before the launch, then each
+// workgroup's end tick (one workgroup here).
+hipError_t launch_direct(const KernelArgs& a, const DirectArgs& d, uint32_t, hipStream_t st) {
+  join_gpu();
+  g_gpu_stream.store((uintptr_t)st);
+  g_gpu = std::thread([a, d] {
+    spin_until(now_ns() + (int64_t)g_gpu_claim_ns);
+    const uint64_t tc = (uint64_t)(now_ns() / 10);
+    __atomic_store_n(&d.l1->gpu_t_first, tc, __ATOMIC_RELEASE);
+    const uint64_t n = items_of(a, d.g0, d.g1);
+    const int64_t until = now_ns() + (int64_t)(g_gpu_ns_per_item * (double)n);
+    mark((uint32_t*)a.out, first_item(a, d.g0), first_item(a, d.g0) + n, item_words(a));
+    mark_second((uint32_t*)a.out1, first_item(a, d.g0), first_item(a, d.g0) + n);
+    spin_until(until);
+    d.pkgs[0].t_claim = tc;
+    __atomic_store_n(&d.wg_end[0], (uint64_t)(now_ns() / 10), __ATOMIC_RELEASE);
+  });
+  return hipSuccess;
+}
+
 hipError_t launch_bare(const KernelArgs& a, hipStream_t) {
   const uint64_t G = gpu_granules(a);
   mark((uint32_t*)a.out, 0, items_of(a, 0, G), item_words(a));
@@ -394,21 +425,21 @@ hipError_t launch_bare(const KernelArgs& a, hipStream_t) {
 // Runtime payloads: the stand-in "compiler" accepts a source that names its
 // entry; the simulated GPU marks coverage like the fixed payloads.
 int rt_compile(const char* source, const char* entry, std::string* code, std::string* lp, std::string* lb,
-               std::string* log) {
+               std::string* ld, std::string* log) {
   if (!source || !entry || !*entry || !strstr(source, entry)) {
     *log = "payload.hip: error: entry not found (simulated compiler)";
     return -1;
   }
   *code = "sim";
-  *lp = *lb = entry;
+  *lp = *lb = *ld = entry;
   return 0;
 }
 int rt_build(const char* source, const char* entry, void** module, void** fn_persistent, void** fn_bare,
-             std::string* log) {
-  std::string c, a, b;
-  const int rc = rt_compile(source, entry, &c, &a, &b, log);
+             void** fn_direct, std::string* log) {
+  std::string c, a, b, d;
+  const int rc = rt_compile(source, entry, &c, &a, &b, &d, log);
   if (rc != 0) return rc;
-  *module = *fn_persistent = *fn_bare = (void*)1;
+  *module = *fn_persistent = *fn_bare = *fn_direct = (void*)1;
   return 0;
 }
 void rt_release(void*) {}

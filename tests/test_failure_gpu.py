@@ -104,7 +104,12 @@ def test_failing_host_version(eng, failing_host, devs):
             eng.program_out(0, dev=out_d, nbytes=n * 4)
         else:
             eng.program_out(0, host=out_h)
-        eng.scheduler(kind=ce.CE_SCHED_DYNAMIC, package_granules=256)
+        # a fixed share for the host, so its version surely runs (with Dynamic
+        # packages the GPU's batched claims may leave it none)
+        if devs == "both":
+            eng.scheduler(kind=ce.CE_SCHED_STATIC, props=[0.75], order=ce.CE_ORDER_GPU_FIRST)
+        else:
+            eng.scheduler(kind=ce.CE_SCHED_DYNAMIC, package_granules=256)
         st = eng.run_status()
         msgs = eng.errors()
         eng.clear_errors()
