@@ -17,9 +17,11 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1805_02755_amd", "csrc")
 HIPCC = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
-# source file -> (persistent kernel name fragment, number of instantiations)
-SOURCES = {"kernels.hip": ("k_persistent", 7), "batch_kernels.hip": ("k_batch_escape", 5),
-           "serve_kernels.hip": ("k_serve", 1)}
+# source file -> (kernel name fragment, number of instantiations) for each
+# kernel with a tile loop: the persistent kernels and the direct kernels of
+# the co-execution, the batched and the serving forms
+SOURCES = {"kernels.hip": (("k_persistent", 7), ("k_direct", 7)), "batch_kernels.hip": (("k_batch_escape", 5),),
+           "serve_kernels.hip": (("k_serve", 1),)}
 
 
 @pytest.fixture(scope="module")
@@ -68,9 +70,11 @@ def _blocks(body):
 
 @pytest.mark.parametrize("src", sorted(SOURCES))
 def test_persistent_loops_have_uniform_exits_around_barriers(asm, src):
-    frag, count = SOURCES[src]
-    funcs = {k: v for k, v in _functions(asm[src]).items() if frag in k}
-    assert len(funcs) == count, sorted(funcs)
+    funcs = {}
+    for frag, count in SOURCES[src]:
+        these = {k: v for k, v in _functions(asm[src]).items() if frag in k}
+        assert len(these) == count, (frag, sorted(these))
+        funcs.update(these)
     for name, body in funcs.items():
         blocks = _blocks(body)
         barrier_loops = {hdr for _, hdr, lines in blocks if hdr and any(l.startswith("s_barrier") for l in lines)}
