@@ -443,9 +443,13 @@ struct ce_engine {
   }
   void pool_loop(int tid, uint64_t seen) {
     for (;;) {
-      // spin briefly for low wake-up latency, then sleep
+      // Spin briefly for low wake-up latency, then sleep. While spinning,
+      // give the core up now and then: with a worker on every core, a thread
+      // of the HIP runtime (or the caller's) that needs one would otherwise
+      // preempt a worker for a whole time slice, possibly one holding a tile.
       const int64_t spin_until = now_ns() + 20'000'000;
       uint64_t e;
+      uint32_t spins = 0;
       while ((e = epoch.load(std::memory_order_acquire)) == seen && !quit.load(std::memory_order_relaxed)) {
         if (now_ns() > spin_until) {
           std::unique_lock<std::mutex> lk(mu);
@@ -453,6 +457,7 @@ struct ce_engine {
           cv.wait(lk, [&] { return epoch.load() != seen || quit.load(); });
           sleeping.fetch_sub(1);
         }
+        if ((++spins & 255u) == 0) std::this_thread::yield();
         cpu_relax();
       }
       if (quit.load()) return;
