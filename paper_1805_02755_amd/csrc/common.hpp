@@ -28,9 +28,10 @@ constexpr uint32_t kBlockThreads = 256;
 struct alignas(64) L1State {
   uint64_t next;        // next granule not yet handed to any device
   uint64_t pad0[7];
-  // written by the last GPU workgroup of a run (system-scope stores); the
-  // host reads them once the kernel has ended, except the done word, which
-  // it polls
+  // written with system-scope stores and read by the host once the kernel
+  // has ended: the start tick by the first workgroup (the host also watches
+  // it as it changes, to re-anchor its clock mapping), the flags by any
+  // workgroup, the rest by the last workgroup of a run with the counted exit
   uint64_t gpu_done;    // done_word(run id, tick at which the last workgroup left)
   uint64_t gpu_t_first; // s_memrealtime of the first package claim
   uint64_t gpu_t_last;  // s_memrealtime of the last package end
@@ -77,8 +78,9 @@ constexpr uint32_t kExitLines = 8;
 // 14,000 packages).
 constexpr uint64_t kNoallocScratchBytes = 1ull << 20;
 
-// Per-run GPU queue state in HBM (device-scope atomics only). The last
-// workgroup to leave a run resets it to zero for the next run. Contended
+// Per-run GPU queue state in HBM (device-scope atomics only), two of them
+// taken in turn: each run's kernel clears the other one for the next run
+// (with the counted exit the last workgroup also resets its own). Contended
 // atomics on one cache line serialise at the memory side, so the ticket
 // counter, the read-mostly publication state, the claim lock and the
 // bookkeeping each get a line of their own.

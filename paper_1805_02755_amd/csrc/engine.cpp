@@ -298,9 +298,9 @@ struct ce_engine {
   uint32_t gpu_grid_last = 0;
   uint32_t grid_override = 0;  // persistent workgroups chosen by the caller (0: the engine chooses)
   bool pcie_stream = false;    // this run's kernel reads or writes pinned host memory directly
-  uint64_t* wg_end = nullptr;      // host-coherent, kFastExitMaxWgs entries (fast exit)
+  uint64_t* wg_end = nullptr;      // host-coherent, kFastExitMaxWgs entries (light exit)
   uint64_t* wg_end_dev = nullptr;
-  bool fast_exit = false;          // this run's kernel uses the fast exit
+  bool fast_exit = false;          // this run's kernel is the direct one
   bool light_exit = false;         // its workgroups leave without counting out
   // Two queue-state buffers (and two halves of the publication words) taken
   // in turn by successive GPU runs: a run's kernel clears the other one for
@@ -1230,13 +1230,12 @@ struct ce_engine {
     bool anchor_watch = false;
     if (use_gpu()) {
       gpu_preclaim(gs);
-      // The GPU's whole share was claimed before the launch and every
-      // workgroup walks its own tickets: no claim, no shared counter, so no
-      // workgroup needs to count out (the overhead of a single-device run
-      // is then that of a plain launch plus the dispenser's first ticket).
       // Without gather workgroups every workgroup leaves on its own (the
-      // next run's state is cleared as the kernel starts), and with the
-      // whole share claimed before the launch the kernel needs no dispenser.
+      // next run's state is cleared by this run's kernel). When the GPU's
+      // whole share was claimed before the launch and every workgroup walks
+      // its own tickets, no dispenser is needed at all: the direct kernel
+      // runs (the overhead of a single-device run is then that of a plain
+      // launch).
       light_exit = !gather && grid <= kFastExitMaxWgs;
       fast_exit = light_exit && gs.pre_only && gs.stride;
       // The fast path never touches its queue state, which therefore stays
