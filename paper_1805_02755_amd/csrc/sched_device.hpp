@@ -492,6 +492,33 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
   const uint32_t n_comp = gridDim.x - s.gather_wgs;
   const uint64_t t_first = computing ? blockIdx.x - s.gather_wgs : 0;
   const bool claim_free = s.pre_only || s.pre_nt < n_comp;
+  // After the direct phase the scheduler arguments are read from LDS only.
+  // Kept in scalar registers across the payload they would crowd out its
+  // own; and every argument the kernel names directly is loaded as it
+  // starts (the compiler places those loads at the entry), where beyond the
+  // few fields of the direct phase they would spill and hold up every
+  // workgroup's first tile. So the lanes copy the argument block word by
+  // word from the kernel-argument segment, through an address the compiler
+  // cannot see through, so that it neither moves the copy to the entry nor
+  // splits it into pieces staged in scratch (taking the address of the
+  // argument itself would make a private copy of it). The block lies at its
+  // ABI offset: the arguments are laid out in order, each at its own
+  // alignment. Each lane's word is loaded here (a relaxed atomic load, which
+  // the compiler keeps where it is written) and stored after the direct
+  // tiles, so that its latency hides behind them instead of lengthening the
+  // workgroup's end.
+  static_assert(sizeof(SchedArgs) % 4 == 0 && sizeof(SchedArgs) / 4 <= kBlockThreads, "one word per lane");
+  constexpr uint32_t kArgWords = sizeof(SchedArgs) / 4;
+  uint32_t arg_word = 0;
+  {
+    constexpr size_t kOffset = (sizeof(T) + alignof(SchedArgs) - 1) / alignof(SchedArgs) * alignof(SchedArgs);
+    uint64_t seg = reinterpret_cast<uint64_t>(__builtin_amdgcn_kernarg_segment_ptr());
+    asm volatile("" : "+s"(seg));
+    uint32_t __attribute__((address_space(1)))* src =
+        reinterpret_cast<uint32_t __attribute__((address_space(1)))*>(seg + kOffset);
+    if (threadIdx.x < kArgWords)
+      arg_word = __hip_atomic_load(src + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
   uint64_t t_dir = t_first;  // first ticket the direct phase did not run
   if (computing && s.pre_nt) {
     if (t_first == 0 && lane0) {
@@ -510,25 +537,23 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
       t_dir += n_comp;
     }
   }
+  // The argument block into LDS (the barrier also ends the direct tiles' use
+  // of the payload's own LDS).
+  __shared__ SchedArgs sh_args;
+  if (threadIdx.x < kArgWords) reinterpret_cast<uint32_t*>(&sh_args)[threadIdx.x] = arg_word;
+  __syncthreads();
+  const SchedArgs& sa = sh_args;
   // The next run's queue state (the other buffer) is cleared now, while
   // nothing uses it, so that no workgroup has to reset anything as it
   // leaves. Agent-scope stores: they reach memory, where the next run's
-  // atomics read them, whichever XCD runs them. (After the direct tiles, so
-  // that reading these arguments does not hold up the kernel's start.)
-  if (s.l2_next) {
+  // atomics read them, whichever XCD runs them.
+  if (sa.l2_next) {
     constexpr uint32_t kStateWords = sizeof(L2State) / sizeof(uint64_t);
-    uint64_t* const st = reinterpret_cast<uint64_t*>(s.l2_next);
-    const uint32_t words = kStateWords + s.pub_next_words;
+    uint64_t* const st = reinterpret_cast<uint64_t*>(sa.l2_next);
+    const uint32_t words = kStateWords + sa.pub_next_words;
     for (uint32_t i = blockIdx.x * kBlockThreads + threadIdx.x; i < words; i += gridDim.x * kBlockThreads)
-      dev_store(i < kStateWords ? &st[i] : &s.pub_next[i - kStateWords], (uint64_t)0);
+      dev_store(i < kStateWords ? &st[i] : &sa.pub_next[i - kStateWords], (uint64_t)0);
   }
-  // The scheduler arguments are read from LDS inside the tile loop: kept in
-  // scalar registers across the payload they would crowd out its own. The
-  // barrier also ends the direct tiles' use of the payload's own LDS.
-  __shared__ SchedArgs sh_args;
-  if (threadIdx.x == 0) sh_args = s;
-  __syncthreads();
-  const SchedArgs& sa = sh_args;
   // The cursor lives in LDS too: only lane 0 of wave 0 uses it, and keeping
   // it in registers across the tile loop would cost the payload occupancy.
   __shared__ Cursor sh_cursor;
@@ -542,11 +567,11 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
         c.t_next = t_dir;  // the first ticket needs no atomic
         c.t_end = t_dir + 1;
       }
-      c.tot_seen = s.pre_nt;
+      c.tot_seen = sa.pre_nt;
     }
   }
   uint32_t prev_p = 0xFFFFFFFFu;
-  if (blockIdx.x < s.gather_wgs) {
+  if (!computing) {
     __shared__ uint64_t sh_off;
     __shared__ uint32_t sh_len;
     for (;;) {
@@ -554,7 +579,7 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
         if (lane0) {
           uint64_t off = 0;
           uint32_t len = 0;
-          sh_go = gather_entry(s, &off, &len) ? 1u : 0u;
+          sh_go = gather_entry(sa, &off, &len) ? 1u : 0u;
           sh_off = off;
           sh_len = len;
         }
@@ -564,17 +589,17 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_persisten
       const uint64_t off = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sh_off >> 32)) << 32) |
                            __builtin_amdgcn_readfirstlane((uint32_t)sh_off);
       const uint32_t len = __builtin_amdgcn_readfirstlane(sh_len);
-      gather_copy(s, off, len);
+      gather_copy(sa, off, len);
       if (wave0) {
         if (lane0) {
-          sys_fetch_add(&s.l1->gathered, (uint64_t)len);  // progress for the host's throttle
-          __hip_atomic_fetch_max(&s.l2->t_gather, now_tick(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          sys_fetch_add(&sa.l1->gathered, (uint64_t)len);  // progress for the host's throttle
+          __hip_atomic_fetch_max(&sa.l2->t_gather, now_tick(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
       __syncthreads();
     }
     if (wave0) {
-      if (lane0) leave(s);
+      if (lane0) leave(sa);
     }
     return;
   }

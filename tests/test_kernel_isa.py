@@ -99,3 +99,49 @@ def test_serving_kernel_drops_stale_lines_at_job_switch(asm):
     invalidate (the job-switch acquire)."""
     body = next(v for k, v in _functions(asm["serve_kernels.hip"]).items() if "k_serve" in k)
     assert "buffer_inv sc0 sc1" in body
+
+
+def _kernel_meta(text):
+    """name -> (argument (offset, size) list, private segment bytes) from the
+    code object's kernel metadata."""
+    meta = {}
+    for m in re.finditer(r"\.args:\s*\n(.*?)\n    \.group_segment_fixed_size.*?\.name:\s+(\S+)\n(.*?)(?=\n  - \.|\n\.end_amdgpu_metadata)",
+                         text, flags=re.S):
+        args = [(int(o), int(s)) for o, s in re.findall(r"\.offset:\s+(\d+)\s*\n\s*\.size:\s+(\d+)", m.group(1))]
+        priv = re.search(r"\.private_segment_fixed_size:\s+(\d+)", m.group(3))
+        meta[m.group(2)] = (args, int(priv.group(1)) if priv else None)
+    return meta
+
+
+def test_persistent_kernel_reads_its_arguments_where_the_abi_puts_them(asm):
+    """The persistent kernel copies its scheduler arguments into LDS from the
+    kernel-argument segment at the offset the payload's size and the block's
+    alignment give; the metadata must place the block there, for every
+    payload. No tile kernel uses scratch memory."""
+    meta = _kernel_meta(asm["kernels.hip"])
+    seen = 0
+    for name, (args, priv) in meta.items():
+        if "k_persistent" not in name and "k_direct" not in name:
+            continue
+        assert priv == 0, (name, priv)
+        if "k_persistent" in name:
+            (o0, s0), (o1, s1) = args[0], args[1]
+            assert o0 == 0 and o1 == (s0 + 7) // 8 * 8, (name, args[:2])
+            seen += 1
+    assert seen == 7
+
+
+def test_persistent_kernel_starts_without_waiting_on_its_arguments(asm):
+    """Only the few arguments of the direct phase are loaded before the first
+    branch: at most two waits on scalar loads, where loading the whole block
+    at the entry took four and spilled registers."""
+    for name, body in _functions(asm["kernels.hip"]).items():
+        if "k_persistent" not in name:
+            continue
+        lines = [l.strip() for l in body.splitlines()]
+        entry = []
+        for l in lines:
+            if l.startswith("s_cbranch"):
+                break
+            entry.append(l)
+        assert sum(l.startswith("s_waitcnt lgkmcnt(0)") for l in entry) <= 2, name
