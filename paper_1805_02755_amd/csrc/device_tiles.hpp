@@ -257,9 +257,7 @@ __device__ __forceinline__ void nbody_accumulate(const float4* pos, uint32_t n, 
     __syncthreads();
     if (j0 + kNbodyGranule + threadIdx.x < n) stage = pos[j0 + kNbodyGranule + threadIdx.x];
     const uint32_t m = (n - j0 < kNbodyGranule) ? n - j0 : kNbodyGranule;
-#pragma unroll 8
-    for (uint32_t jj = 0; jj < m; ++jj) {
-      const float4 pj = sh[jj];
+    const auto body = [&](const float4 pj) {
       const float dx = pj.x - pi.x;
       const float dy = pj.y - pi.y;
       const float dz = pj.z - pi.z;
@@ -270,7 +268,41 @@ __device__ __forceinline__ void nbody_accumulate(const float4* pos, uint32_t n, 
       ax = __builtin_fmaf(f, dx, ax);
       ay = __builtin_fmaf(f, dy, ay);
       az = __builtin_fmaf(f, dz, az);
+    };
+    // Two batches of eight bodies in registers: the next batch is read from
+    // LDS while the current one is computed, so the reads' latency never
+    // waits on the arithmetic (with one wave per SIMD nothing else would
+    // hide it, and how much of it a plain unrolled loop hides depends on the
+    // compiler's schedule). Scheduling fences keep each batch's reads a
+    // phase ahead of its arithmetic; the bodies of a batch still interleave.
+    // The bodies are taken in index order.
+    uint32_t jj = 0;
+    if (m >= 8) {
+      float4 a[8], b[8];
+#pragma unroll
+      for (uint32_t k = 0; k < 8; ++k) a[k] = sh[k];
+      for (; jj + 16 <= m; jj += 16) {
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) b[k] = sh[jj + 8 + k];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) body(a[k]);
+        __builtin_amdgcn_sched_barrier(0);
+        // the batch after (read within the stage; unused past its end)
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) a[k] = sh[(jj + 16 + k) & (kNbodyGranule - 1)];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) body(b[k]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (jj + 8 <= m) {
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) body(a[k]);
+        jj += 8;
+      }
     }
+    for (; jj < m; ++jj) body(sh[jj]);
   }
 }
 

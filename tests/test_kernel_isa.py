@@ -145,3 +145,30 @@ def test_persistent_kernel_starts_without_waiting_on_its_arguments(asm):
                 break
             entry.append(l)
         assert sum(l.startswith("s_waitcnt lgkmcnt(0)") for l in entry) <= 2, name
+
+
+def test_nbody_loop_reads_each_batch_a_phase_ahead(asm):
+    """The n-body inner loop keeps two batches of eight bodies: after issuing
+    a batch's eight LDS reads, it computes the batch read before, so until
+    the next reads no wait may reach into the batch just issued (lgkmcnt
+    stays at 8 or more). Otherwise the reads' latency would wait on the
+    arithmetic, with one wave per SIMD to hide it."""
+    seen = 0
+    for src in ("kernels.hip",):
+        for name, body in _functions(asm[src]).items():
+            if "Nbody" not in name:
+                continue
+            for block in re.split(r"\n(?=\.LBB\d+_\d+:)", body):
+                lines = [l.strip() for l in block.splitlines()]
+                if sum(l.startswith("ds_read_b128") for l in lines) != 16:
+                    continue
+                after_batch = False
+                for l in lines:
+                    if l.startswith("ds_read_b128"):
+                        after_batch = True
+                        continue
+                    m = re.match(r"s_waitcnt lgkmcnt\((\d+)\)", l)
+                    if m and after_batch:
+                        assert int(m.group(1)) >= 8, (name, l)
+                seen += 1
+    assert seen >= 16
