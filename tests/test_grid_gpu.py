@@ -107,3 +107,21 @@ def test_refuses_huge_grid(eng):
         eng.gpu_workgroups((1 << 20) + 1)
     eng.clear_errors()
     eng.gpu_workgroups(0)
+
+
+def test_direct_kernel_one_workgroup_per_tile_over_many_rounds(eng):
+    """Equal-cost tiles spanning four or more rounds of resident workgroups,
+    the GPU's whole share claimed before the launch: the direct kernel runs
+    one workgroup per tile (5120 blur tiles of 32 x 1024 pixels against
+    5 x 256 resident workgroups), dealt by the hardware; twice in a row, and
+    the whole output bit-exact against the oracle."""
+    w, h = 4096, 40960
+    img = synth.blur_image(w, h)
+    wt = ce.ce_gauss5_weights(1.0)
+    ref = O.blur5(img, O.gauss5_weights(1.0))
+    for _ in range(2):
+        out, st, tr = run_payload(eng, ce.CE_KERNEL_BLUR5, ce.ce_blur5_params(w, h), [w, h], None, [img, wt], (h, w),
+                                  np.float32, ce.CE_DEV_GPU, "static")
+        assert st.gpu_workgroups == (h // 32) * (w // 1024)
+        assert np.array_equal(out.view(np.uint32), ref.view(np.uint32)), diff_report(out, ref, tr)
+        check_trace(tr, h, 1)
