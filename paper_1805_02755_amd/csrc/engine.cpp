@@ -1159,9 +1159,16 @@ struct ce_engine {
         gs.dyn_tiles = std::max<uint32_t>(1, gpu_tiles(kargs, 0, std::min(gs.pkg, G)));
         gs.batch = std::max<uint32_t>(1, gs.lookahead / gs.dyn_tiles);
       }
-      // several tickets per atomic once there are many tiles per workgroup
+      // Several tickets per atomic once there are several tiles per
+      // workgroup: every ticket atomic goes to one counter, which serialises
+      // them (escape-time 3072^2, nine tiles per workgroup, one ticket each:
+      // twice the plain launch's time), while a large grab leaves the
+      // workgroups uneven at the end. With k tiles per workgroup, taking
+      // about sqrt(k) per atomic balances the two: sqrt(k) atomics per
+      // workgroup and a last grab of sqrt(k) tiles (measured 2048^2 to
+      // 8192^2: best at 2, 2-3, 4 and 8 for k = 4, 9, 16 and 64).
       const uint64_t per_wg = gpu_tiles(kargs, 0, G) / std::max<uint32_t>(1, grid - gather_wgs);
-      gs.chunk = (uint32_t)std::min<uint64_t>(8, std::max<uint64_t>(1, per_wg / 8));
+      gs.chunk = (uint32_t)std::min<uint64_t>(8, std::max<uint64_t>(1, (uint64_t)std::lround(std::sqrt((double)per_wg))));
       // Blur and n-body tiles all cost the same: a fixed round-robin needs no
       // atomics. Escape-time tiles vary, but a tile is one row segment and a
       // workgroup's rows lie far apart, which evens out its share; measured
