@@ -471,7 +471,7 @@ struct ce_engine {
   // Claims the GPU's first package on the host just before the launch, with
   // the same arithmetic the kernel's claimer uses, so that the workgroups find
   // work published when they start instead of racing for the claim lock.
-  void gpu_preclaim(SchedArgs& gs) {
+  void gpu_preclaim(SchedArgs& gs, uint64_t round_wgs) {
     gs.pre_nt = 0;
     gs.st_first = 0;
     gs.pre_only = 0;
@@ -494,17 +494,38 @@ struct ce_engine {
       g0 = a;
       g1 = std::min(a + gs.pkg, gs.G);
     } else {
+      // One HGuided package; and a second, consecutive one when the first
+      // holds less than two rounds of tiles and two rounds' worth would
+      // still remain after it. The kernel's first claim then falls due a round later:
+      // a claim made as the first round ends queues behind every
+      // workgroup's ticket atomic (when the first tiles are cheap they all
+      // come at once), and the GPU would wait for it with nothing published.
+      // No other device claims before the launch, so the two ranges are
+      // contiguous: the GPU claims twice in a row, as one range.
+      const uint64_t round = std::max<uint64_t>(1, round_wgs);
       uint64_t cur = __atomic_load_n(&l1->next, __ATOMIC_ACQUIRE);
-      for (;;) {
-        if (cur >= gs.G) return;
-        uint64_t sz = hguided_size(gs.G - cur, gs.P_self, gs.sumP, gs.n_dev, gs.k, gs.min_self);
-        if (sz > kPubMaxSize) sz = kPubMaxSize;
-        if (__atomic_compare_exchange_n(&l1->next, &cur, cur + sz, false, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE)) {
-          g0 = cur;
-          g1 = cur + sz;
-          break;
+      for (int n = 0; n < 2; ++n) {
+        bool got = false;
+        for (;;) {
+          if (cur >= gs.G) break;
+          uint64_t sz = hguided_size(gs.G - cur, gs.P_self, gs.sumP, gs.n_dev, gs.k, gs.min_self);
+          if (g1 > g0 && sz > kPubMaxSize - (g1 - g0)) sz = kPubMaxSize - (g1 - g0);
+          if (sz > kPubMaxSize) sz = kPubMaxSize;
+          if (sz == 0) break;
+          if (n == 1 && (cur != g1 || gpu_tiles(kargs, g0, g1) >= 2 * round ||
+                         gpu_tiles(kargs, cur + sz, gs.G) < 2 * round))
+            break;
+          if (__atomic_compare_exchange_n(&l1->next, &cur, cur + sz, false, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE)) {
+            if (n == 0) g0 = cur;
+            g1 = cur + sz;
+            cur += sz;
+            got = true;
+            break;
+          }
         }
+        if (!got) break;
       }
+      if (g1 == g0) return;
     }
     gs.pre_g0 = g0;
     gs.pre_g1 = g1;
@@ -1238,7 +1259,7 @@ struct ce_engine {
     // host's own work then starts a few microseconds late).
     bool anchor_watch = false;
     if (use_gpu()) {
-      gpu_preclaim(gs);
+      gpu_preclaim(gs, grid - gather_wgs);
       // Without gather workgroups every workgroup leaves on its own (the
       // next run's state is cleared by this run's kernel). When the GPU's
       // whole share was claimed before the launch and every workgroup walks
