@@ -156,6 +156,29 @@ def test_hguided_packages_follow_the_equation(simlib):
             assert e - b == want, (d, b, e, want)
 
 
+def test_hguided_preclaim_takes_two_packages_for_a_short_first_round(simlib):
+    """When the GPU's first HGuided package holds less than two rounds of
+    tiles and two rounds would remain after a second one, the host claims
+    both for the GPU before the launch, as one record: its size is the sum of
+    two consecutive HGuided packages from granule 0. Every later package
+    still follows the equation. (Simulated GPU: 8 CUs x 2 workgroups, a round
+    of 16 blur tiles of 32 rows.)"""
+    s = SCHEDS["hguided"]
+    P, k, mins = s["power"], s["k"], s["min_granules"]
+    cnt, st, tr, G = _run(simlib, "blur", (1024, 4096), BOTH, s, rates=(0.2, 4.0, 100.0))
+    assert np.all(cnt == 1)
+    s1 = O.hguided_size(G, P, k, 0, mins[0])
+    s2 = O.hguided_size(G - s1, P, k, 0, mins[0])
+    tiles = lambda rows: -(-rows // 32)
+    assert tiles(s1) < 2 * 16 and tiles(G - s1 - s2) >= 2 * 16  # the rule applies here
+    first = [(b, e) for d, b, e, tc, te in tr if d == 0 and b == 0]
+    assert first == [(0, s1 + s2)], (first, s1, s2)
+    for d, b, e, tc, te in tr:
+        if d == 0 and b == 0:
+            continue
+        assert e - b == O.hguided_size(G - b, P, k, d, mins[d]), (d, b, e)
+
+
 def test_dynamic_packages_are_equal_and_aligned(simlib):
     cnt, st, tr, G = _run(simlib, "escape", (64, 301), BOTH, SCHEDS["dynamic"], rates=(1.0, 3.0, 100.0))
     for d, b, e, tc, te in tr:
