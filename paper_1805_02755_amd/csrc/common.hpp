@@ -188,7 +188,7 @@ struct SchedArgs {
   uint32_t pad_next;
 };
 
-constexpr uint32_t kFastExitMaxWgs = 16384;  // entries of the host's wg_end array
+constexpr uint32_t kFastExitMaxWgs = 65536;  // entries of the host's wg_end array
 
 // Arguments of the direct kernel, for a run whose whole GPU share is the
 // package the host claimed before the launch, dealt round-robin: no
@@ -196,7 +196,7 @@ constexpr uint32_t kFastExitMaxWgs = 16384;  // entries of the host's wg_end arr
 struct DirectArgs {
   uint64_t g0, g1;      // the package
   uint32_t ntiles;      // its tiles
-  uint32_t pad;
+  uint32_t swizzle;     // 1: one workgroup per tile, dealt over the XCDs in turn (see k_direct)
   L1State* l1;          // device address of the dispenser: the first workgroup stamps the GPU's start
   PkgSlot* pkgs;        // ... and the package's claim time into its trace record
   uint64_t* wg_end;     // each workgroup's end tick (host-coherent)

@@ -672,7 +672,19 @@ __global__ __launch_bounds__(kBlockThreads, T::kMinBlocksPerCu) void k_direct(T 
     dev_store(&d.pkgs[0].t_claim, tp);
     sys_store(&d.l1->gpu_t_first, tp);
   }
-  for (uint32_t t = blockIdx.x; t < d.ntiles; t += gridDim.x) pay.run(d.g0, d.g1, t);
+  for (uint32_t i = blockIdx.x; i < d.ntiles; i += gridDim.x) {
+    // Swizzled: the hardware deals workgroup i to XCD i mod 8, so without it
+    // the tiles at one position of every group of eight (escape-time: one
+    // column block of every row, when a row holds eight) would all land on
+    // one XCD. Within each whole group of eight the tiles are rotated by the
+    // group's index instead, so every XCD meets every position in turn.
+    uint32_t t = i;
+    if (d.swizzle) {
+      const uint32_t j = i / 8;
+      if (8 * j + 8 <= d.ntiles) t = 8 * j + (i + j) % 8;
+    }
+    pay.run(d.g0, d.g1, t);
+  }
   __syncthreads();  // every wave's tiles are done
   if (lane0) sys_store(&d.wg_end[blockIdx.x], now_tick());
 }

@@ -125,3 +125,20 @@ def test_direct_kernel_one_workgroup_per_tile_over_many_rounds(eng):
         assert st.gpu_workgroups == (h // 32) * (w // 1024)
         assert np.array_equal(out.view(np.uint32), ref.view(np.uint32)), diff_report(out, ref, tr)
         check_trace(tr, h, 1)
+
+
+def test_uneven_tiles_one_workgroup_each_over_many_rounds(eng):
+    """Escape-time tiles (uneven cost) over more than four rounds of resident
+    workgroups, the GPU alone: the direct kernel runs one workgroup per tile,
+    the tiles swizzled over the XCDs (10,005 tiles: the last group of eight
+    is partial and keeps its order); twice, the whole image bit-exact."""
+    w, h = 2560, 2001
+    eng.gpu_workgroups(0)
+    p = synth.escape_region(w, h, -2.0, 1.0, -1.5, 1.5, 64)
+    ref = O.escape(w, h, *[float(v) for v in p.as_f32()], p.max_iter)
+    for _ in range(2):
+        out, st, tr = run_payload(eng, ce.CE_KERNEL_ESCAPE, escape_params(p), [w, h], None, [], (h, w), np.uint32,
+                                  ce.CE_DEV_GPU, "static")
+        assert st.gpu_workgroups == h * -(-w // 512)
+        assert np.array_equal(out, ref), diff_report(out, ref, tr)
+        check_trace(tr, h, 1)
