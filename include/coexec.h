@@ -335,9 +335,11 @@ ce_status ce_engine_wait_bounds(ce_engine* e, double dispenser_s, double gather_
  * compute units, the largest g <= min(T, R) that minimises
  * ceil(T / g) * ceil(g / C), the tiles run by the busiest compute unit
  * (whole rounds, spread evenly over the CUs); except that a run whose GPU
- * share is one package of equal-cost tiles (the direct kernel) with at
- * least 4 R tiles, and at most 16384, gets one workgroup per tile, dealt
- * by the hardware as a plain launch is. A caller's value is used as
+ * share is one package (the direct kernel) of equal-cost tiles with at
+ * least 4 R tiles, or of escape-time or runtime-payload tiles with more
+ * than 4 R, and at most 65536 tiles, gets one workgroup per tile, dealt by
+ * the hardware as a plain launch is (uneven tiles swizzled over the XCDs).
+ * A caller's value is used as
  * given (it may exceed what fits on the GPU at once: the dispenser's
  * waits do not depend on every workgroup being resident), plus the gather
  * workgroups of CE_MERGE_GPU_GATHER. Affects speed only, never results.
